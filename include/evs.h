@@ -1,0 +1,229 @@
+/*
+ * evs.h -- C ABI of the MI355X EvSNet library (libevs.so).
+ *
+ * EvSNet (arXiv 2508.18071, Sec. 3.3) turns noisy rendered video into
+ * bipolar event streams: every frame passes through 3x3 convolution layers,
+ * and every layer feeds bipolar leaky integrate-and-fire (BiLIF) units whose
+ * membrane potential is carried through time at every pixel.  This library
+ * computes, on one AMD Instinct MI355X (gfx950):
+ *
+ *   evs_forward         the network over a clip (or a batch of clips)
+ *   evs_backward        the surrogate-gradient BPTT backward (Eq. 4)
+ *   evs_emd_loss        the bidirectional polarity-split EMD loss (Eq. 7-11)
+ *   evs_compact_events  dense spike frames -> (t, x, y, c, polarity) events
+ *
+ * Network definition, per frame t and layer l = 1..L (s_0[t] = x[t]):
+ *   u_l[t] = conv3x3(s_{l-1}[t], W_l)       zero "same" padding, stride 1,
+ *                                           cross-correlation, no bias
+ *   h_l[t] = leak * v_l[t-1] + u_l[t]       charge (Eq. 2, leak = 1 - 1/tau)
+ *   s_l[t] = +1 if h >= theta, -1 if h <= -theta, else 0     (Eq. 3)
+ *   v_l[t] = h_l[t] - theta * s_l[t]        reset
+ * with v_l[-1] = 0 unless an initial state is supplied.
+ *
+ * Conventions shared by every entry point
+ *   - Every tensor argument is a DEVICE pointer owned by the caller, dense,
+ *     row-major in the index order written next to it; the library never
+ *     keeps a pointer after the call returns (its kernels read and write it
+ *     asynchronously on `stream`).  Host-memory arguments are marked "host".
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     only enqueue work: no host synchronisation and no device allocation
+ *     happen inside evs_forward, evs_backward, evs_emd_loss or
+ *     evs_compact_events, so they may be captured in a hipGraph.  Scratch
+ *     memory comes from the caller's workspace `ws` of `ws_bytes` bytes
+ *     (size from evs_workspace_bytes; alignment 256 bytes).
+ *   - Every call returns an evs_status.  Argument errors are detected on the
+ *     host before anything is enqueued; the message is then available from
+ *     evs_last_error() on the calling thread.  EVS_EHIP reports a failed HIP
+ *     launch.  Outputs are overwritten, never accumulated.
+ */
+#ifndef EVS_H
+#define EVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EVS_OK = 0,
+  EVS_EINVAL = 1,        /* bad argument (null pointer, size, range) */
+  EVS_EUNSUPPORTED = 2,  /* valid but not implemented (e.g. channel count) */
+  EVS_EWORKSPACE = 3,    /* workspace missing or too small */
+  EVS_EHIP = 4,          /* HIP runtime error */
+  EVS_EOVERFLOW = 5      /* an index or size does not fit its field */
+} evs_status;
+
+typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
+
+/* Network description (host struct, read during the call only).
+ *   n_layers   L in 1..3
+ *   ch[0]      input channels Cin in 1..4 (3 for RGB)
+ *   ch[1..L-1] hidden widths, each in 1..32 (all hidden layers equal);
+ *              widths are padded internally to 16 or 32 with zero weights
+ *   ch[L]      output channels in 1..2.  With two outputs, channel 0 is the
+ *              ON stream and channel 1 the OFF stream; each is a BiLIF unit
+ *              that may itself fire with either sign.
+ *   theta      firing threshold V_th > 0 (Eq. 2-3)
+ *   leak       beta = 1 - 1/tau in [0, 1]
+ *   surr_alpha slope of the sigmoid surrogate sigma(z) = 1/(1+exp(-alpha z))
+ *              used by evs_backward and by relaxed forwards (Eq. 4)
+ *   precision  EVS_FP32: convolutions in FP32 (MFMA f32);
+ *              EVS_BF16: x and W rounded to bfloat16 (round-to-nearest-even)
+ *              and multiplied on BF16 MFMA with FP32 accumulation.
+ *              Membrane state, threshold compare and reset are FP32 in both.
+ *   relaxed    0: hard spikes (Eq. 3).  1: smooth spikes
+ *              sigma(h-theta) - sigma(-h-theta) in the output and the reset,
+ *              whose exact derivative is the surrogate (FP32 only; used to
+ *              check gradients against finite differences).
+ *   detach_reset  evs_backward only: 1 stops the gradient through the
+ *              reset term theta * s.                                        */
+typedef struct evs_net {
+  int32_t n_layers;
+  int32_t ch[4];
+  float theta;
+  float leak;
+  float surr_alpha;
+  int32_t precision;
+  int32_t relaxed;
+  int32_t detach_reset;
+} evs_net;
+
+/* One clip, or a batch of N clips of equal shape (host struct).
+ *   x        [N][T][Cin][H][W] float32, the noisy linear RGB frames
+ *   s_out    [N][T][Cout][H][W] spikes: int8 in {-1,0,1} (s_fp32 = 0) or
+ *            float32 (s_fp32 = 1; required for relaxed nets); may be NULL
+ *   v_state  NULL, or [N][sum_l C_l][H][W] float32 membrane potentials of
+ *            all layers (layer-major): read as the initial state and
+ *            overwritten with the state after frame T-1.  Splitting a clip
+ *            at any frame and carrying v_state gives bit-identical spikes.
+ *   h_trace  NULL, or [N][T][sum_l C_l][H][W] float32: the charged
+ *            potential h of every layer at every frame (debug/training).   */
+typedef struct evs_clip {
+  int32_t N, T, H, W;
+  const float* x;
+  void* s_out;
+  int32_t s_fp32;
+  float* v_state;
+  float* h_trace;
+} evs_clip;
+
+/* Event record produced by evs_compact_events, packed in a uint64:
+ *   bits  0..31  t (frame index; physical time t / F_evt, F_evt = 1000)
+ *   bits 32..43  x       bits 44..55  y
+ *   bits 56..62  channel bit 63 polarity (1 = negative spike)            */
+#define EVS_EVENT_T(e)   ((uint32_t)((e) & 0xffffffffu))
+#define EVS_EVENT_X(e)   ((uint32_t)(((e) >> 32) & 0xfffu))
+#define EVS_EVENT_Y(e)   ((uint32_t)(((e) >> 44) & 0xfffu))
+#define EVS_EVENT_C(e)   ((uint32_t)(((e) >> 56) & 0x7fu))
+#define EVS_EVENT_NEG(e) ((uint32_t)((e) >> 63))
+
+/* Operation selector for evs_workspace_bytes. */
+typedef enum {
+  EVS_OP_FORWARD = 0,
+  EVS_OP_BACKWARD = 1,
+  EVS_OP_EMD = 2,
+  EVS_OP_COMPACT = 3
+} evs_op;
+
+/* Workspace bytes needed by `op` for these arguments (0 = none needed).
+ * For EVS_OP_EMD / EVS_OP_COMPACT only clip[0].N/T/H/W and net->ch[L] are
+ * read.  Returns (size_t)-1 on invalid arguments.                        */
+size_t evs_workspace_bytes(const evs_net* net, const evs_clip* clips, int32_t n_clips,
+                           int32_t ckpt_every, int32_t op);
+
+/* Size in bytes of the packed weight buffer for `net`.                   */
+size_t evs_packed_weights_bytes(const evs_net* net);
+
+/* Pack the per-layer weights into one device buffer read by the kernels.
+ *   w       host array of L device pointers; w[l] is float32
+ *           [C_{l+1}][C_l][3][3] (torch Conv2d layout)
+ *   packed  device buffer of evs_packed_weights_bytes(net) bytes        */
+int evs_pack_weights(const evs_net* net, const float* const* w, void* packed, void* stream);
+
+/* Forward pass (Sec. 3.3, Eq. 2-3 with 3x3 convolution layers).
+ *   clips, n_clips  host array of clip descriptors.  n_clips = 1 runs the
+ *           single-clip kernel over N x tiles.  n_clips > 1 (at most 64)
+ *           runs the persistent batched kernel: (clip, tile) work items in
+ *           longest-first order are taken from a device counter in `ws`.
+ *   ckpt    NULL, or (n_clips = 1 only) [N][ceil(T/ckpt_every)][sum C][H][W]
+ *           float32: the membrane of every layer before frames 0, k, 2k, ...
+ *           (k = ckpt_every), as needed by evs_backward.
+ *   tile    tiles are chosen by the autotuner cache (evs_autotune) or a
+ *           built-in default; results do not depend on the tile choice.  */
+int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, int32_t n_clips,
+                float* ckpt, int32_t ckpt_every, void* ws, size_t ws_bytes, void* stream);
+
+/* Surrogate-gradient BPTT backward through the whole clip (Eq. 4).
+ * The surrogate is psi(h) = sigma'(h - theta) + sigma'(-h - theta), the
+ * derivative of sigma(h - theta) - sigma(-h - theta); one BiLIF step's
+ * adjoint with g_v = dL/dv[t] arriving from frame t+1 is
+ *     g_h = (G - theta g_v) psi(h) + g_v   (G * psi(h) + g_v if detached)
+ *     dL/dv[t-1] = leak * g_h,   dL/du[t] = g_h.
+ *   clip    the same x as the forward; clip->v_state is not read (the
+ *           initial state is ckpt segment 0); s_out/h_trace are ignored.
+ *   ckpt    the checkpoints written by evs_forward with the same ckpt_every
+ *   grad_s  [N][T][Cout][H][W] float32 dLoss/ds_L
+ *   grad_w  host array of L device pointers, float32 [C_l][C_{l-1}][3][3],
+ *           overwritten with dLoss/dW_l (summed over the batch)
+ *   grad_x  NULL or [N][T][Cin][H][W] float32 dLoss/dx
+ *   grad_v  NULL or [N][sum C][H][W] float32 dLoss/d(initial membrane)
+ * Segments are recomputed from their checkpoints in reverse order; the
+ * weight gradient is reduced deterministically (no float atomics).      */
+int evs_backward(const evs_net* net, const void* packed, const evs_clip* clip,
+                 const float* ckpt, int32_t ckpt_every, const float* grad_s,
+                 float* const* grad_w, float* grad_x, float* grad_v,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Bidirectional polarity-split EMD loss plus spike-count term (Eq. 7-11).
+ *   s       [N][T][C][H][W] float32 spikes, C = 2 (channel 0 = ON stream,
+ *           channel 1 = OFF stream, each scored with its signed values) or
+ *           C = 1 (bipolar; split into S*[S>0] and -S*[S<0] as in Eq. 9)
+ *   e       [N][T][2][H][W] int8 target counts (>= 0): [..][0] ON, [..][1] OFF
+ *   loss    device float32 scalar: sum over clips, channels and pixels of
+ *           (1/2T) sum_i (|D_i| + |R_i|), D = prefix and R = suffix sums of
+ *           S - E over time, plus lambda_count * sum over pixels of
+ *           | sum_t |S| - sum_t E |.
+ *   grad_s  NULL or [N][T][C][H][W] float32 dloss/ds (subgradient 0 at 0)
+ * The reduction order is fixed, so results are bitwise reproducible.    */
+int evs_emd_loss(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t C,
+                 int32_t H, int32_t W, float lambda_count, float* loss, float* grad_s,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Dense spikes -> event list in (t, c, y, x) order (Sec. 3.1 event tuples).
+ *   s         [T][C][H][W] int8 spikes
+ *   events    device uint64 array of `capacity` records (format above)
+ *   count     device int64: the number of events in s.  If it exceeds
+ *             capacity, only the first `capacity` events are written.
+ * Requires W, H <= 4096, C <= 128, T < 2^32.                            */
+int evs_compact_events(const int8_t* s, int32_t T, int32_t C, int32_t H, int32_t W,
+                       uint64_t* events, int64_t capacity, int64_t* count,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Time the compiled tile shapes for this network and frame size on
+ * `stream` (allocates its own scratch; not capture-safe) and remember the
+ * fastest for later evs_forward calls with this (net, H, W).  If the
+ * environment variable EVS_AUTOTUNE_CACHE names a file, the cache is
+ * loaded from and saved to it.  `chosen` (host, may be NULL) receives the
+ * chosen tile id.                                                        */
+int evs_autotune(const evs_net* net, int32_t H, int32_t W, int32_t T, int32_t* chosen, void* stream);
+
+/* Number of compiled tile variants for `net`, and a description of one
+ * (host string, valid until the library is unloaded).                    */
+int32_t evs_tile_count(const evs_net* net);
+const char* evs_tile_name(const evs_net* net, int32_t tile_id);
+
+/* Force a tile variant for later calls with `net` (-1 = automatic).      */
+int evs_set_tile(const evs_net* net, int32_t tile_id);
+
+/* Static strings. */
+const char* evs_status_str(int status);
+const char* evs_last_error(void);
+const char* evs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVS_H */

@@ -96,6 +96,25 @@ def surrogate(h: np.ndarray, theta: float, alpha: float) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# BF16 operand quantisation (the precision form rounds x and W, not spikes)
+# ----------------------------------------------------------------------------
+
+def bf16_round(a) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (ties to even), as float64.
+
+    bfloat16 keeps the upper 16 bits of an IEEE float32; rounding adds half a
+    unit of the dropped 16 bits plus the kept lowest bit (ties to even).
+    """
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    special = (u & 0x7F800000) == 0x7F800000
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000)
+    quiet = np.where((u & 0xFFFF) != 0, np.uint64(0x400000), np.uint64(0))
+    r = np.where(special, (u & np.uint64(0xFFFF0000)) | quiet, r)
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# ----------------------------------------------------------------------------
 # forward
 # ----------------------------------------------------------------------------
 

@@ -1,0 +1,246 @@
+"""Torch-facing binding of libevs (argument marshalling only).
+
+Torch supplies device memory and the current stream; every step of the
+computation runs in the library's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+from ._lib import EvsClip, EvsNet, check, lib
+
+
+@dataclass
+class Net:
+    """EvSNet description: conv3x3 -> BiLIF layers with the given widths."""
+    channels: tuple
+    theta: float = 0.5
+    leak: float = 0.9
+    surr_alpha: float = 4.0
+    precision: str = "fp32"        # "fp32" | "bf16"
+    relaxed: bool = False
+    detach_reset: bool = False
+
+    def c(self) -> EvsNet:
+        n = EvsNet()
+        L = len(self.channels) - 1
+        n.n_layers = L
+        for i in range(4):
+            n.ch[i] = self.channels[i] if i <= L else 0
+        n.theta = self.theta
+        n.leak = self.leak
+        n.surr_alpha = self.surr_alpha
+        n.precision = _lib.EVS_BF16 if self.precision == "bf16" else _lib.EVS_FP32
+        n.relaxed = int(self.relaxed)
+        n.detach_reset = int(self.detach_reset)
+        return n
+
+    @property
+    def n_layers(self) -> int:
+        return len(self.channels) - 1
+
+    @property
+    def sum_c(self) -> int:
+        return sum(self.channels[1:])
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _clip(x, s_out=None, s_fp32=False, v_state=None, h_trace=None):
+    N, T, _, H, W = x.shape
+    c = EvsClip()
+    c.N, c.T, c.H, c.W = N, T, H, W
+    c.x = x.data_ptr()
+    c.s_out = s_out.data_ptr() if s_out is not None else None
+    c.s_fp32 = int(s_fp32)
+    c.v_state = v_state.data_ptr() if v_state is not None else None
+    c.h_trace = h_trace.data_ptr() if h_trace is not None else None
+    return c
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None:
+            if not t.is_cuda:
+                raise ValueError("tensors must live on the GPU")
+            if not t.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+
+
+def pack_weights(net: Net, weights, stream=None) -> torch.Tensor:
+    L = lib()
+    cn = net.c()
+    ws = [w.contiguous() for w in weights]
+    _check_dev(*ws)
+    for w, ci, co in zip(ws, net.channels[:-1], net.channels[1:]):
+        if w.dtype != torch.float32 or tuple(w.shape) != (co, ci, 3, 3):
+            raise ValueError(f"weight must be float32 [{co},{ci},3,3], got {w.dtype} {tuple(w.shape)}")
+    nb = L.evs_packed_weights_bytes(ctypes.byref(cn))
+    if nb == ctypes.c_size_t(-1).value:
+        check(L.evs_pack_weights(ctypes.byref(cn), None, None, None), "pack_weights")
+    packed = torch.empty(nb, dtype=torch.uint8, device=ws[0].device)
+    arr = (ctypes.c_void_p * len(ws))(*[w.data_ptr() for w in ws])
+    check(L.evs_pack_weights(ctypes.byref(cn), arr, packed.data_ptr(), _stream(stream)), "pack_weights")
+    packed._evs_keep = ws       # keep the sources alive until the copy ran
+    return packed
+
+
+def workspace(net: Net, clips, op=_lib.EVS_OP_FORWARD, ckpt_every=0, device=None):
+    L = lib()
+    cn = net.c()
+    arr = (EvsClip * len(clips))(*clips)
+    nb = L.evs_workspace_bytes(ctypes.byref(cn), arr, len(clips), ckpt_every, op)
+    if nb == ctypes.c_size_t(-1).value:
+        raise _lib.EvsError(_lib.EVS_EINVAL, "workspace_bytes")
+    if nb == 0:
+        return None, 0
+    return torch.empty(nb, dtype=torch.uint8, device=device), nb
+
+
+def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = False,
+            v_state: torch.Tensor | None = None, trace: bool = False, ckpt_every: int = 0,
+            out: torch.Tensor | None = None, stream=None):
+    """Run the network over x [N,T,Cin,H,W] (float32, on the GPU).
+
+    Returns a dict: "s" [N,T,Cout,H,W] (int8 or float32), "h" (the charged
+    potentials of all layers [N,T,sumC,H,W], if trace), "ckpt" (if
+    ckpt_every > 0).  v_state [N,sumC,H,W] is read and overwritten in place.
+    """
+    if x.dim() == 4:
+        x = x.unsqueeze(0)
+    _check_dev(x, v_state, packed)
+    if x.dtype != torch.float32:
+        raise ValueError("x must be float32")
+    N, T, C, H, W = x.shape
+    if C != net.channels[0]:
+        raise ValueError("x channels do not match the network")
+    dev = x.device
+    cout = net.channels[-1]
+    if out is None:
+        out = torch.empty(N, T, cout, H, W, dtype=torch.float32 if s_fp32 else torch.int8, device=dev)
+    h = torch.empty(N, T, net.sum_c, H, W, dtype=torch.float32, device=dev) if trace else None
+    ck = None
+    if ckpt_every > 0:
+        nseg = (T + ckpt_every - 1) // ckpt_every
+        ck = torch.empty(N, nseg, net.sum_c, H, W, dtype=torch.float32, device=dev)
+    c = _clip(x, out, s_fp32, v_state, h)
+    ws, nb = workspace(net, [c], device=dev)
+    cn = net.c()
+    check(lib().evs_forward(ctypes.byref(cn), packed.data_ptr(), ctypes.byref(c), 1,
+                            ck.data_ptr() if ck is not None else None, ckpt_every,
+                            ws.data_ptr() if ws is not None else None, nb, _stream(stream)), "forward")
+    return {"s": out, "h": h, "ckpt": ck, "_ws": ws}
+
+
+def forward_batched(net: Net, packed: torch.Tensor, xs, outs, v_states=None, stream=None, ws=None):
+    """One persistent launch over several clips xs[i] [N_i,T_i,Cin,H_i,W_i]."""
+    clips = []
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        v = v_states[i] if v_states is not None else None
+        _check_dev(x, o, v)
+        clips.append(_clip(x, o, o.dtype == torch.float32, v, None))
+    cn = net.c()
+    arr = (EvsClip * len(clips))(*clips)
+    nb = lib().evs_workspace_bytes(ctypes.byref(cn), arr, len(clips), 0, _lib.EVS_OP_FORWARD)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=xs[0].device)
+    check(lib().evs_forward(ctypes.byref(cn), packed.data_ptr(), arr, len(clips), None, 0,
+                            ws.data_ptr(), nb, _stream(stream)), "forward_batched")
+    return ws
+
+
+def tile_count(net: Net) -> int:
+    cn = net.c()
+    return lib().evs_tile_count(ctypes.byref(cn))
+
+
+def tile_name(net: Net, tile: int) -> str:
+    cn = net.c()
+    r = lib().evs_tile_name(ctypes.byref(cn), tile)
+    return r.decode() if r else ""
+
+
+def set_tile(net: Net, tile: int):
+    cn = net.c()
+    check(lib().evs_set_tile(ctypes.byref(cn), tile), "set_tile")
+
+
+def autotune(net: Net, H: int, W: int, T: int = 8, stream=None) -> int:
+    cn = net.c()
+    chosen = ctypes.c_int32(-1)
+    check(lib().evs_autotune(ctypes.byref(cn), H, W, T, ctypes.byref(chosen), _stream(stream)), "autotune")
+    return chosen.value
+
+
+def emd_loss(s: torch.Tensor, e: torch.Tensor, lambda_count: float = 0.0, grad: bool = True, stream=None):
+    """Bidirectional polarity-split EMD (+ count term); returns (loss, grad_s)."""
+    if s.dim() == 4:
+        s, e = s.unsqueeze(0), e.unsqueeze(0)
+    _check_dev(s, e)
+    N, T, C, H, W = s.shape
+    loss = torch.empty(1, dtype=torch.float32, device=s.device)
+    g = torch.empty_like(s) if grad else None
+    c = EvsClip()
+    c.N, c.T, c.H, c.W = N, T, H, W
+    net = Net((3, C)).c()
+    nb = lib().evs_workspace_bytes(ctypes.byref(net), ctypes.byref(c), 1, 0, _lib.EVS_OP_EMD)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=s.device)
+    check(lib().evs_emd_loss(s.data_ptr(), e.data_ptr(), N, T, C, H, W, lambda_count, loss.data_ptr(),
+                             g.data_ptr() if g is not None else None, ws.data_ptr(), nb, _stream(stream)),
+          "emd_loss")
+    return loss, g
+
+
+def compact_events(s: torch.Tensor, capacity: int | None = None, stream=None):
+    """Dense int8 spikes [T,C,H,W] -> (events uint64 as int64 tensor, count)."""
+    _check_dev(s)
+    T, C, H, W = s.shape
+    if capacity is None:
+        capacity = int(s.numel())
+    ev = torch.empty(max(capacity, 1), dtype=torch.int64, device=s.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=s.device)
+    c = EvsClip()
+    c.N, c.T, c.H, c.W = 1, T, H, W
+    net = Net((3, C)).c()
+    nb = lib().evs_workspace_bytes(ctypes.byref(net), ctypes.byref(c), 1, 0, _lib.EVS_OP_COMPACT)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=s.device)
+    check(lib().evs_compact_events(s.data_ptr(), T, C, H, W, ev.data_ptr(), capacity, cnt.data_ptr(),
+                                   ws.data_ptr(), nb, _stream(stream)), "compact_events")
+    return ev, cnt
+
+
+def backward(net: Net, packed, x, ckpt, ckpt_every, grad_s, want_dx=False, want_dv=False, stream=None):
+    """BPTT backward; returns (list of dW, dx or None, dv or None)."""
+    if x.dim() == 4:
+        x = x.unsqueeze(0)
+    N, T, C, H, W = x.shape
+    dev = x.device
+    gws = [torch.empty(co, ci, 3, 3, dtype=torch.float32, device=dev)
+           for ci, co in zip(net.channels[:-1], net.channels[1:])]
+    dx = torch.empty_like(x) if want_dx else None
+    dv = torch.empty(N, net.sum_c, H, W, dtype=torch.float32, device=dev) if want_dv else None
+    c = _clip(x)
+    cn = net.c()
+    nb = lib().evs_workspace_bytes(ctypes.byref(cn), ctypes.byref(c), 1, ckpt_every, _lib.EVS_OP_BACKWARD)
+    if nb == ctypes.c_size_t(-1).value:
+        raise _lib.EvsError(_lib.EVS_EINVAL, "workspace_bytes(backward)")
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    arr = (ctypes.c_void_p * len(gws))(*[g.data_ptr() for g in gws])
+    check(lib().evs_backward(ctypes.byref(cn), packed.data_ptr(), ctypes.byref(c), ckpt.data_ptr(), ckpt_every,
+                             grad_s.data_ptr(), arr, dx.data_ptr() if dx is not None else None,
+                             dv.data_ptr() if dv is not None else None, ws.data_ptr(), nb, _stream(stream)),
+          "backward")
+    return gws, dx, dv

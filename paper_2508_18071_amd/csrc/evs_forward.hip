@@ -1,0 +1,855 @@
+// EvSNet forward on gfx950: conv3x3 layers feeding BiLIF units, fused over
+// all layers and all frames of a clip (arXiv 2508.18071, Sec. 3.3, Eq. 2-3).
+//
+// Dataflow (one workgroup = one spatial tile of TH x TW output pixels):
+//   * The tile is processed on a canvas of (TH+2L) x (TW+2L) pixels.  Layer
+//     l is evaluated on the canvas shrunk by l pixels on each side, so the
+//     halo rings needed by the next layer are recomputed redundantly inside
+//     the workgroup (no inter-workgroup exchange per frame).  Each
+//     workgroup keeps the membrane state of its canvas neurons in registers
+//     for all T frames; halo neurons replicate bit-for-bit the neurons of
+//     the neighbouring tile because every pixel is computed by the same
+//     instruction sequence.
+//   * Per frame, the x tile (+halo) is staged in LDS (register prefetch of
+//     frame t+1 overlaps frame t), hidden layers run as transposed GEMMs
+//     D[cout][pixel] = W[cout][K] * S[K][pixel] on MFMA (f32 16x16x4 or
+//     bf16 16x16x32 with f32 accumulation), with K = (tap, cin) and the
+//     spike operand gathered from LDS; the accumulator fragment IS the
+//     membrane state (C input = leak * v), so BiLIF runs in place.  The
+//     spikes of a hidden layer go back to LDS (f32 or bf16, exact) for the
+//     next layer.  The output layer (1-2 channels) runs on the VALU with
+//     its weights broadcast from LDS.
+//   * Only the HBM traffic of the algorithm remains: x in (12 B/px/frame)
+//     and the output spikes (int8).
+#include "evs_internal.hpp"
+
+namespace evs {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+constexpr int align16(int b) { return (b + 15) & ~15; }
+
+template <int NL_, int CIN_, int CH_, bool BF16_, int TH_, int TW_, int NW_>
+struct Cfg {
+  static constexpr int NL = NL_, CIN = CIN_, CH = CH_, TH = TH_, TW = TW_, NW = NW_;
+  static constexpr bool BF16 = BF16_;
+  static constexpr int CO = 2;                       // output channels (max)
+  static constexpr int NH = NL - 1;                  // hidden layers
+  static constexpr int CHT = TH + 2 * NL, CWT = TW + 2 * NL;
+  static constexpr int NPIX = CHT * CWT;
+  static constexpr int PADF = 32;                    // zeroed front pad (pixels)
+  static constexpr int NPIXL = PADF + NPIX + 48;     // canvas + pads
+  static constexpr int NT = 64 * NW;
+  static constexpr int MB = CH / 16;                 // 16-row output blocks
+  static constexpr int npb(int l) { return cdiv((CHT - 2 * l) * CWT, 16); }
+  static constexpr int NPB1 = NH >= 1 ? npb(1) : 1;
+  static constexpr int NPB2 = NH >= 2 ? npb(2) : 1;
+  static constexpr int NB1 = cdiv(NPB1, NW);
+  static constexpr int NB2 = cdiv(NPB2, NW);
+  static constexpr int NOUT = cdiv(TH * TW, NT);
+  static constexpr int XN = CIN * NPIX;
+  static constexpr int XPF = cdiv(XN, NT);
+  static constexpr int K1 = 9 * CIN;
+  static constexpr int KS1 = BF16 ? cdiv(K1, 32) : cdiv(K1, 4);
+  static constexpr int KS2 = BF16 ? (CH == 32 ? 9 : 5) : 9 * CH / 4;
+  static constexpr int XELEM = BF16 ? 2 : 4;
+  static constexpr int XS_BYTES = align16(CIN * NPIXL * XELEM);
+  static constexpr int SP_BYTES = NH >= 1 ? align16(NPIXL * CH * XELEM) : 0;
+  static constexpr int WL_FLOATS = 9 * (NH >= 1 ? CH : CIN) * CO;
+  static constexpr int LDS_BYTES = XS_BYTES + SP_BYTES + WL_FLOATS * 4;
+  static_assert(LDS_BYTES <= 160 * 1024, "tile does not fit in LDS");
+  static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
+  static_assert(NB1 <= 32 && NB2 <= 32 && NOUT <= 32 && (BF16 ? 8 * KS1 : KS1) <= 32, "mask words overflow");
+  static constexpr int toff(int tau) { return (tau / 3 - 1) * CWT + (tau % 3 - 1); }
+};
+
+__device__ inline f4 mfma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma_bf16(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                 __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+__device__ inline float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// BiLIF fire + reset (Eq. 2-3): returns the spike, updates v in place (v
+// holds the charged potential h on entry).
+__device__ inline float bilif(float& v, float theta, float alpha, bool relaxed) {
+  const float h = v;
+  float s;
+  if (relaxed) {
+    s = sigm(alpha * (h - theta)) - sigm(alpha * (-h - theta));
+  } else {
+    s = h >= theta ? 1.0f : (h <= -theta ? -1.0f : 0.0f);
+  }
+  v = fmaf(-theta, s, h);
+  return s;
+}
+
+__device__ inline unsigned pack_bf16x2(float lo, float hi) {
+  // spikes are exactly representable: take the upper halves of the floats
+  return (__builtin_bit_cast(unsigned, lo) >> 16) | (__builtin_bit_cast(unsigned, hi) & 0xffff0000u);
+}
+
+// ------------------------------------------------------------------ weights
+// Weight fragments of the MFMA layers, loaded once per workgroup.
+template <class C>
+struct Frags {
+  // layer 1 (hidden, input x): A[cout][K], K = tap * CIN + c
+  float a1f[C::MB][C::BF16 ? 1 : C::KS1];
+  u4 a1b[C::MB][C::BF16 ? C::KS1 : 1];
+  // layer 2 (hidden->hidden): A[cout][K], K = tap * CH + ci
+  float a2f[C::NH >= 2 && !C::BF16 ? C::MB : 1][C::NH >= 2 && !C::BF16 ? C::KS2 : 1];
+  u4 a2b[C::NH >= 2 && C::BF16 ? C::MB : 1][C::NH >= 2 && C::BF16 ? C::KS2 : 1];
+};
+
+__device__ inline float wget(const FwdNetArgs& na, int layer, int co, int ci, int tap, bool bf) {
+  // layer 0-based; real channel bounds checked by the caller
+  const int cin = na.ch[layer];
+  float w = na.w[na.wofs[layer] + (co * cin + ci) * 9 + tap];
+  return bf ? round_bf16(w) : w;
+}
+
+template <class C>
+__device__ void load_frags(const FwdNetArgs& na, Frags<C>& F, int lane) {
+  const int i = lane & 15, g = lane >> 4;
+  if constexpr (C::NH >= 1) {
+    const int c1 = na.ch[1];
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m) {
+      const int co = 16 * m + i;
+      if constexpr (!C::BF16) {
+#pragma unroll
+        for (int q = 0; q < C::KS1; ++q) {
+          const int K = 4 * q + g;
+          float w = 0.f;
+          if (K < C::K1 && co < c1) w = wget(na, 0, co, K % C::CIN, K / C::CIN, false);
+          F.a1f[m][q] = w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < C::KS1; ++q) {
+          unsigned wd[4];
+#pragma unroll
+          for (int e2 = 0; e2 < 4; ++e2) {
+            float ww[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int K = 32 * q + 8 * g + 2 * e2 + h;
+              ww[h] = (K < C::K1 && co < c1) ? wget(na, 0, co, K % C::CIN, K / C::CIN, true) : 0.f;
+            }
+            wd[e2] = pack_bf16x2(ww[0], ww[1]);
+          }
+          F.a1b[m][q] = u4{wd[0], wd[1], wd[2], wd[3]};
+        }
+      }
+    }
+  }
+  if constexpr (C::NH >= 2) {
+    const int c1 = na.ch[1], c2 = na.ch[2];
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m) {
+      const int co = 16 * m + i;
+      if constexpr (!C::BF16) {
+#pragma unroll
+        for (int tau = 0; tau < 9; ++tau) {
+#pragma unroll
+          for (int q = 0; q < C::CH / 4; ++q) {
+            const int ci = 4 * g + (q & 3) + 16 * (q >> 2);
+            F.a2f[m][tau * (C::CH / 4) + q] =
+                (co < c2 && ci < c1) ? wget(na, 1, co, ci, tau, false) : 0.f;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < C::KS2; ++q) {
+          int tau, cib;
+          if constexpr (C::CH == 32) { tau = q; cib = 8 * g; }
+          else { tau = 2 * q + (g >> 1); cib = 8 * (g & 1); }
+          unsigned wd[4];
+#pragma unroll
+          for (int e2 = 0; e2 < 4; ++e2) {
+            float ww[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int ci = cib + 2 * e2 + h;
+              ww[h] = (tau < 9 && co < c2 && ci < c1) ? wget(na, 1, co, ci, tau, true) : 0.f;
+            }
+            wd[e2] = pack_bf16x2(ww[0], ww[1]);
+          }
+          F.a2b[m][q] = u4{wd[0], wd[1], wd[2], wd[3]};
+        }
+      }
+    }
+  }
+}
+
+// Output-layer weights into LDS as wl[tap][ci][co] (co padded to 2).
+template <class C>
+__device__ void load_out_weights(const FwdNetArgs& na, float* wl) {
+  const int L = na.n_layers - 1;
+  const int cin = na.ch[L], cout = na.ch[L + 1];
+  constexpr int CI = C::NH >= 1 ? C::CH : C::CIN;
+  for (int e = threadIdx.x; e < C::WL_FLOATS; e += C::NT) {
+    const int co = e % 2, ci = (e / 2) % CI, tap = e / (2 * CI);
+    float w = 0.f;
+    if (co < cout && ci < cin) w = wget(na, L, co, ci, tap, C::BF16);
+    wl[e] = w;
+  }
+}
+
+// ------------------------------------------------------------------ tile
+struct Tile {
+  int n, ty0, tx0;
+};
+
+template <class C>
+struct Lds {
+  float* xsf;            // [CIN][NPIXL] f32      (BF16: unused)
+  uint16_t* xsb;         // [CIN][NPIXL] bf16     (FP32: unused)
+  float* spf;            // [NPIXL][CH] f32
+  uint16_t* spb;         // [NPIXL][CH] bf16
+  float* wl;             // output-layer weights
+};
+
+// Process one tile over frames [0, T) of one clip.
+template <class C>
+__device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl,
+                         const Frags<C>& F, const Lds<C>& S) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int j = lane & 15, g = lane >> 4;
+  const int H = ca.H, W = ca.W, T = ca.T;
+  const size_t HW = (size_t)H * W;
+  const int sumc = na.sum_c;
+  const float theta = na.theta, leak = na.leak, alpha = na.alpha;
+  const bool relaxed = na.relaxed != 0;
+  const int c1 = na.ch[1], c2 = na.ch[2];
+  const int cout = na.ch[na.n_layers];
+  const int choff2 = c1, choffo = (C::NH == 0) ? 0 : (C::NH == 1 ? c1 : c1 + c2);
+  const int gy0 = tl.ty0 - C::NL, gx0 = tl.tx0 - C::NL;   // image coords of canvas (0,0)
+
+  // ---- per-lane geometry: validity masks of hidden blocks
+  unsigned vm1 = 0, vm2 = 0;
+  if constexpr (C::NH >= 1) {
+#pragma unroll
+    for (int i = 0; i < C::NB1; ++i) {
+      const int b = wave + C::NW * i;
+      const int pr = C::CWT * 1 + 16 * b + j;
+      const int row = pr / C::CWT, col = pr % C::CWT;
+      const int gy = gy0 + row, gx = gx0 + col;
+      const bool ok = b < C::NPB1 && row < C::CHT - 1 && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      vm1 |= (ok ? 1u : 0u) << i;
+    }
+  }
+  if constexpr (C::NH >= 2) {
+#pragma unroll
+    for (int i = 0; i < C::NB2; ++i) {
+      const int b = wave + C::NW * i;
+      const int pr = C::CWT * 2 + 16 * b + j;
+      const int row = pr / C::CWT, col = pr % C::CWT;
+      const int gy = gy0 + row, gx = gx0 + col;
+      const bool ok = b < C::NPB2 && row < C::CHT - 2 && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      vm2 |= (ok ? 1u : 0u) << i;
+    }
+  }
+  // output pixels of this lane
+  int op[C::NOUT];
+  unsigned ovm = 0;
+#pragma unroll
+  for (int k = 0; k < C::NOUT; ++k) {
+    const int q = tid + C::NT * k;
+    const int ty = q / C::TW, tx = q % C::TW;
+    const bool inq = q < C::TH * C::TW;
+    op[k] = inq ? (C::NL + ty) * C::CWT + (C::NL + tx) : C::NL * C::CWT + C::NL;
+    const int gy = tl.ty0 + ty, gx = tl.tx0 + tx;
+    ovm |= ((inq && gy < H && gx < W) ? 1u : 0u) << k;
+  }
+
+  // ---- layer-1 B-operand gather offsets (relative to the block pixel)
+  int xo1[C::BF16 ? 8 * C::KS1 : C::KS1];
+  unsigned xk1 = 0;   // bit set: gather slot holds a real (tap, channel)
+  if constexpr (!C::BF16) {
+#pragma unroll
+    for (int q = 0; q < C::KS1; ++q) {
+      const int K = 4 * q + g;
+      const int tap = K / C::CIN, c = K % C::CIN;
+      xo1[q] = K < C::K1 ? c * C::NPIXL + (tap / 3 - 1) * C::CWT + (tap % 3 - 1) : 0;
+      xk1 |= (K < C::K1 ? 1u : 0u) << q;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < C::KS1; ++q)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int K = 32 * q + 8 * g + e;
+        const int tap = K / C::CIN, c = K % C::CIN;
+        xo1[8 * q + e] = K < C::K1 ? c * C::NPIXL + (tap / 3 - 1) * C::CWT + (tap % 3 - 1) : 0;
+        xk1 |= (K < C::K1 ? 1u : 0u) << (8 * q + e);
+      }
+  }
+  // BF16 CH=16 hidden->hidden: tap per (k-step, lane group)
+  int so2[C::NH >= 2 && C::BF16 && C::CH == 16 ? C::KS2 : 1];
+  if constexpr (C::NH >= 2 && C::BF16 && C::CH == 16) {
+#pragma unroll
+    for (int q = 0; q < C::KS2; ++q) {
+      int tau = 2 * q + (g >> 1);
+      if (tau > 8) tau = 8;              // zero weights in that slot
+      so2[q] = ((tau / 3 - 1) * C::CWT + (tau % 3 - 1)) * C::CH + 8 * (g & 1);
+    }
+  }
+
+  // ---- state registers
+  f4 st1[C::NB1][C::MB];
+  f4 st2[C::NB2][C::MB];
+  float so[C::NOUT][2];
+  const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * sumc * HW : nullptr;
+  if constexpr (C::NH >= 1) {
+#pragma unroll
+    for (int i = 0; i < C::NB1; ++i)
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m) {
+        f4 v = {0.f, 0.f, 0.f, 0.f};
+        if (vin && ((vm1 >> i) & 1u)) {
+          const int pr = C::CWT + 16 * (wave + C::NW * i) + j;
+          const size_t pix = (size_t)(gy0 + pr / C::CWT) * W + (gx0 + pr % C::CWT);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int co = 16 * m + 4 * g + r;
+            if (co < c1) v[r] = vin[(size_t)co * HW + pix];
+          }
+        }
+        st1[i][m] = v;
+      }
+  }
+  if constexpr (C::NH >= 2) {
+#pragma unroll
+    for (int i = 0; i < C::NB2; ++i)
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m) {
+        f4 v = {0.f, 0.f, 0.f, 0.f};
+        if (vin && ((vm2 >> i) & 1u)) {
+          const int pr = 2 * C::CWT + 16 * (wave + C::NW * i) + j;
+          const size_t pix = (size_t)(gy0 + pr / C::CWT) * W + (gx0 + pr % C::CWT);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int co = 16 * m + 4 * g + r;
+            if (co < c2) v[r] = vin[(size_t)(choff2 + co) * HW + pix];
+          }
+        }
+        st2[i][m] = v;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < C::NOUT; ++k) {
+    so[k][0] = so[k][1] = 0.f;
+    if (vin && ((ovm >> k) & 1u)) {
+      const int q = tid + C::NT * k;
+      const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
+#pragma unroll
+      for (int co = 0; co < 2; ++co)
+        if (co < cout) so[k][co] = vin[(size_t)(choffo + co) * HW + pix];
+    }
+  }
+
+  // ---- x staging
+  const float* xclip = ca.x + (size_t)tl.n * T * C::CIN * HW;
+  float xpf[C::XPF];
+  auto load_x = [&](int t) {
+    const float* xf = xclip + (size_t)t * C::CIN * HW;
+#pragma unroll
+    for (int k = 0; k < C::XPF; ++k) {
+      const int e = tid + C::NT * k;
+      const int c = e / C::NPIX, rem = e % C::NPIX;
+      const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;
+      float v = 0.f;
+      if (e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = xf[(size_t)c * HW + (size_t)gy * W + gx];
+      xpf[k] = v;
+    }
+  };
+  auto store_x = [&]() {
+#pragma unroll
+    for (int k = 0; k < C::XPF; ++k) {
+      const int e = tid + C::NT * k;
+      if (e < C::XN) {
+        const int c = e / C::NPIX, rem = e % C::NPIX;
+        if constexpr (C::BF16) S.xsb[c * C::NPIXL + C::PADF + rem] = f32_to_bf16_rne(xpf[k]);
+        else S.xsf[c * C::NPIXL + C::PADF + rem] = xpf[k];
+      }
+    }
+  };
+
+  const int nseg = ca.ckpt_every > 0 ? cdiv(T, ca.ckpt_every) : 0;
+  // writes the current state (before frame t) of interior pixels to dst
+  // ([sumC][H][W] for this clip)
+  auto write_state = [&](float* dst) {
+    if constexpr (C::NH >= 1) {
+#pragma unroll
+      for (int i = 0; i < C::NB1; ++i) {
+        const int pr = C::CWT + 16 * (wave + C::NW * i) + j;
+        const int row = pr / C::CWT, col = pr % C::CWT;
+        if (((vm1 >> i) & 1u) && row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
+          const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
+#pragma unroll
+          for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int co = 16 * m + 4 * g + r;
+              if (co < c1) dst[(size_t)co * HW + pix] = st1[i][m][r];
+            }
+        }
+      }
+    }
+    if constexpr (C::NH >= 2) {
+#pragma unroll
+      for (int i = 0; i < C::NB2; ++i) {
+        const int pr = 2 * C::CWT + 16 * (wave + C::NW * i) + j;
+        const int row = pr / C::CWT, col = pr % C::CWT;
+        if (((vm2 >> i) & 1u) && row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
+          const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
+#pragma unroll
+          for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int co = 16 * m + 4 * g + r;
+              if (co < c2) dst[(size_t)(choff2 + co) * HW + pix] = st2[i][m][r];
+            }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < C::NOUT; ++k) {
+      if ((ovm >> k) & 1u) {
+        const int q = tid + C::NT * k;
+        const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
+#pragma unroll
+        for (int co = 0; co < 2; ++co)
+          if (co < cout) dst[(size_t)(choffo + co) * HW + pix] = so[k][co];
+      }
+    }
+  };
+
+  // hidden-layer BiLIF epilogue on st (holding h): spikes -> LDS, trace
+  auto hidden_epilogue = [&](f4 (&st)[C::MB], int layer /*1 or 2*/, int b, bool valid, int cl, int choff,
+                             float* trace_t) {
+    const int pr = layer * C::CWT + 16 * b + j;
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m) {
+      f4 s;
+      if (trace_t && valid) {
+        const int row = pr / C::CWT, col = pr % C::CWT;
+        if (row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
+          const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int co = 16 * m + 4 * g + r;
+            if (co < cl) trace_t[(size_t)(choff + co) * HW + pix] = st[m][r];
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = st[m][r];
+        s[r] = bilif(v, theta, alpha, relaxed);
+        st[m][r] = v;
+      }
+      if (!valid) s = f4{0.f, 0.f, 0.f, 0.f};
+      const int p = C::PADF + pr;
+      if constexpr (C::BF16) {
+        uint2 w2 = {pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
+        *reinterpret_cast<uint2*>(S.spb + (size_t)p * C::CH + 16 * m + 4 * g) = w2;
+      } else {
+        *reinterpret_cast<f4*>(S.spf + (size_t)p * C::CH + 16 * m + 4 * g) = s;
+      }
+    }
+  };
+
+  // ---- prologue: frame 0 into LDS, frame 1 into registers
+  load_x(0);
+  store_x();
+  if (T > 1) load_x(1);
+  __syncthreads();
+
+  for (int t = 0; t < T; ++t) {
+    if (ca.ckpt && (t % ca.ckpt_every) == 0)
+      write_state(ca.ckpt + ((size_t)tl.n * nseg + t / ca.ckpt_every) * sumc * HW);
+    float* trace_t = ca.h_trace ? ca.h_trace + ((size_t)tl.n * T + t) * sumc * HW : nullptr;
+
+    if constexpr (C::NH >= 1) {
+      // ================= layer 1: x -> hidden (MFMA)
+#pragma unroll
+      for (int i = 0; i < C::NB1; ++i)
+#pragma unroll
+        for (int m = 0; m < C::MB; ++m) st1[i][m] *= leak;
+#pragma unroll
+      for (int q = 0; q < C::KS1; ++q) {
+#pragma unroll
+        for (int i = 0; i < C::NB1; ++i) {
+          const int b = wave + C::NW * i;
+          if (b < C::NPB1) {
+            const int p = C::PADF + C::CWT + 16 * b + j;
+            if constexpr (!C::BF16) {
+              const int o = xo1[q];
+              const float xv = S.xsf[p + o];
+              const float bv = ((xk1 >> q) & 1u) ? xv : 0.f;
+#pragma unroll
+              for (int m = 0; m < C::MB; ++m) st1[i][m] = mfma_f32(F.a1f[m][q], bv, st1[i][m]);
+            } else {
+              unsigned wd[4];
+#pragma unroll
+              for (int e2 = 0; e2 < 4; ++e2) {
+                const int o0 = xo1[8 * q + 2 * e2], o1 = xo1[8 * q + 2 * e2 + 1];
+                const unsigned r0 = S.xsb[p + o0], r1 = S.xsb[p + o1];
+                const unsigned lo = ((xk1 >> (8 * q + 2 * e2)) & 1u) ? r0 : 0u;
+                const unsigned hi = ((xk1 >> (8 * q + 2 * e2 + 1)) & 1u) ? r1 : 0u;
+                wd[e2] = lo | (hi << 16);
+              }
+              const u4 bv = {wd[0], wd[1], wd[2], wd[3]};
+#pragma unroll
+              for (int m = 0; m < C::MB; ++m) st1[i][m] = mfma_bf16(F.a1b[m][q], bv, st1[i][m]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < C::NB1; ++i) {
+        const int b = wave + C::NW * i;
+        if (b < C::NPB1) hidden_epilogue(st1[i], 1, b, (vm1 >> i) & 1u, c1, 0, trace_t);
+      }
+      __syncthreads();                                   // B1: s1 visible, xs free
+      if (t + 1 < T) store_x();
+      if (t + 2 < T) load_x(t + 2);
+    }
+
+    if constexpr (C::NH >= 2) {
+      // ================= layer 2: hidden -> hidden (MFMA)
+#pragma unroll
+      for (int i = 0; i < C::NB2; ++i)
+#pragma unroll
+        for (int m = 0; m < C::MB; ++m) st2[i][m] *= leak;
+      if constexpr (!C::BF16) {
+#pragma unroll
+        for (int tau = 0; tau < 9; ++tau) {
+#pragma unroll
+          for (int i = 0; i < C::NB2; ++i) {
+            const int b = wave + C::NW * i;
+            if (b < C::NPB2) {
+              const int p = C::PADF + 2 * C::CWT + 16 * b + j + C::toff(tau);
+#pragma unroll
+              for (int hh = 0; hh < C::CH / 16; ++hh) {
+                const f4 bv = *reinterpret_cast<const f4*>(S.spf + (size_t)p * C::CH + 16 * hh + 4 * g);
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+                  for (int m = 0; m < C::MB; ++m)
+                    st2[i][m] = mfma_f32(F.a2f[m][tau * (C::CH / 4) + 4 * hh + q4], bv[q4], st2[i][m]);
+              }
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < C::KS2; ++q) {
+#pragma unroll
+          for (int i = 0; i < C::NB2; ++i) {
+            const int b = wave + C::NW * i;
+            if (b < C::NPB2) {
+              const int p = C::PADF + 2 * C::CWT + 16 * b + j;
+              int o;
+              if constexpr (C::CH == 32) o = C::toff(q) * C::CH + 8 * g;
+              else o = so2[q];
+              const u4 bv = *reinterpret_cast<const u4*>(S.spb + (size_t)p * C::CH + o);
+#pragma unroll
+              for (int m = 0; m < C::MB; ++m) st2[i][m] = mfma_bf16(F.a2b[m][q], bv, st2[i][m]);
+            }
+          }
+        }
+      }
+      __syncthreads();                                   // B2: all reads of s1 done
+#pragma unroll
+      for (int i = 0; i < C::NB2; ++i) {
+        const int b = wave + C::NW * i;
+        if (b < C::NPB2) hidden_epilogue(st2[i], 2, b, (vm2 >> i) & 1u, c2, choff2, trace_t);
+      }
+      __syncthreads();                                   // B3: s2 visible
+    }
+
+    // ================= output layer (VALU)
+    {
+      float u[C::NOUT][2];
+#pragma unroll
+      for (int k = 0; k < C::NOUT; ++k) { u[k][0] = leak * so[k][0]; u[k][1] = leak * so[k][1]; }
+#pragma unroll
+      for (int tau = 0; tau < 9; ++tau) {
+        const int to = C::toff(tau);
+        if constexpr (C::NH == 0) {
+#pragma unroll
+          for (int c = 0; c < C::CIN; ++c) {
+            const float w0 = S.wl[(tau * C::CIN + c) * 2], w1 = S.wl[(tau * C::CIN + c) * 2 + 1];
+#pragma unroll
+            for (int k = 0; k < C::NOUT; ++k) {
+              const float xv = S.xsf[c * C::NPIXL + C::PADF + op[k] + to];
+              u[k][0] = fmaf(w0, xv, u[k][0]);
+              u[k][1] = fmaf(w1, xv, u[k][1]);
+            }
+          }
+        } else if constexpr (!C::BF16) {
+#pragma unroll
+          for (int c4 = 0; c4 < C::CH / 4; ++c4) {
+            const f4 wa = *reinterpret_cast<const f4*>(S.wl + (tau * C::CH + 4 * c4) * 2);
+            const f4 wb = *reinterpret_cast<const f4*>(S.wl + (tau * C::CH + 4 * c4) * 2 + 4);
+#pragma unroll
+            for (int k = 0; k < C::NOUT; ++k) {
+              const f4 sv = *reinterpret_cast<const f4*>(S.spf + (size_t)(C::PADF + op[k] + to) * C::CH + 4 * c4);
+              u[k][0] = fmaf(wa[0], sv[0], u[k][0]); u[k][1] = fmaf(wa[1], sv[0], u[k][1]);
+              u[k][0] = fmaf(wa[2], sv[1], u[k][0]); u[k][1] = fmaf(wa[3], sv[1], u[k][1]);
+              u[k][0] = fmaf(wb[0], sv[2], u[k][0]); u[k][1] = fmaf(wb[1], sv[2], u[k][1]);
+              u[k][0] = fmaf(wb[2], sv[3], u[k][0]); u[k][1] = fmaf(wb[3], sv[3], u[k][1]);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int c8 = 0; c8 < C::CH / 8; ++c8) {
+            f4 wv[4];
+#pragma unroll
+            for (int z = 0; z < 4; ++z) wv[z] = *reinterpret_cast<const f4*>(S.wl + (tau * C::CH + 8 * c8) * 2 + 4 * z);
+#pragma unroll
+            for (int k = 0; k < C::NOUT; ++k) {
+              const u4 raw = *reinterpret_cast<const u4*>(S.spb + (size_t)(C::PADF + op[k] + to) * C::CH + 8 * c8);
+#pragma unroll
+              for (int z = 0; z < 4; ++z) {
+                const float s0 = __builtin_bit_cast(float, raw[z] << 16);
+                const float s1 = __builtin_bit_cast(float, raw[z] & 0xffff0000u);
+                u[k][0] = fmaf(wv[z][0], s0, u[k][0]); u[k][1] = fmaf(wv[z][1], s0, u[k][1]);
+                u[k][0] = fmaf(wv[z][2], s1, u[k][0]); u[k][1] = fmaf(wv[z][3], s1, u[k][1]);
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < C::NOUT; ++k) {
+        const bool ok = (ovm >> k) & 1u;
+        const int q = tid + C::NT * k;
+        const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
+#pragma unroll
+        for (int co = 0; co < 2; ++co) {
+          if (ok && co < cout && trace_t) trace_t[(size_t)(choffo + co) * HW + pix] = u[k][co];
+          float v = u[k][co];
+          const float s = bilif(v, theta, alpha, relaxed);
+          so[k][co] = v;
+          if (ok && co < cout && ca.s_out) {
+            const size_t o = (((size_t)tl.n * T + t) * cout + co) * HW + pix;
+            if (ca.s_fp32) reinterpret_cast<float*>(ca.s_out)[o] = s;
+            else reinterpret_cast<int8_t*>(ca.s_out)[o] = (int8_t)s;
+          }
+        }
+      }
+    }
+    if constexpr (C::NH == 0) {
+      __syncthreads();
+      if (t + 1 < T) store_x();
+      if (t + 2 < T) load_x(t + 2);
+    }
+    __syncthreads();                                     // B4: spikes / xs consumed
+  }
+  if (ca.v_out) write_state(ca.v_out + (size_t)tl.n * sumc * HW);
+}
+
+template <class C>
+__device__ void init_lds(const FwdNetArgs& na, Lds<C>& S, char* lds) {
+  S.xsf = reinterpret_cast<float*>(lds);
+  S.xsb = reinterpret_cast<uint16_t*>(lds);
+  S.spf = reinterpret_cast<float*>(lds + C::XS_BYTES);
+  S.spb = reinterpret_cast<uint16_t*>(lds + C::XS_BYTES);
+  S.wl = reinterpret_cast<float*>(lds + C::XS_BYTES + C::SP_BYTES);
+  // zero canvas and pads once: pads are read only by junk (masked) pixels
+  unsigned* z = reinterpret_cast<unsigned*>(lds);
+  for (int e = threadIdx.x; e < (C::XS_BYTES + C::SP_BYTES) / 4; e += C::NT) z[e] = 0u;
+  load_out_weights<C>(na, S.wl);
+}
+
+// XCD-aware tile order: the hardware deals workgroups round-robin over the
+// 8 XCDs; give each XCD a contiguous run of tiles so that the halos that
+// neighbouring tiles share are fetched into the same L2.
+__device__ inline int xcd_remap(int b, int n) {
+  const int x = b & 7, k = b >> 3;
+  const int q = n >> 3, r = n & 7;
+  const int start = x * q + (x < r ? x : r);
+  return start + k;
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void fwd_kernel(FwdNetArgs na, FwdClipArgs ca) {
+  __shared__ __attribute__((aligned(16))) char lds[C::LDS_BYTES];
+  Lds<C> S;
+  init_lds<C>(na, S, lds);
+  Frags<C> F;
+  load_frags<C>(na, F, threadIdx.x & 63);
+  __syncthreads();
+  const int ntiles = ca.tiles_x * ca.tiles_y;
+  const int tile = xcd_remap(blockIdx.x, ntiles);
+  Tile tl;
+  tl.n = blockIdx.y;
+  tl.ty0 = (tile / ca.tiles_x) * C::TH;
+  tl.tx0 = (tile % ca.tiles_x) * C::TW;
+  run_tile<C>(na, ca, tl, F, S);
+}
+
+// Persistent batched kernel: workgroups pop (clip, tile) items from a device
+// counter; items are ordered clip by clip, clips longest-first.
+template <class C>
+__global__ __launch_bounds__(C::NT) void fwd_batched_kernel(FwdNetArgs na, BatchTable bt, int32_t* counter) {
+  __shared__ __attribute__((aligned(16))) char lds[C::LDS_BYTES];
+  __shared__ int item_sh;
+  Lds<C> S;
+  init_lds<C>(na, S, lds);
+  Frags<C> F;
+  load_frags<C>(na, F, threadIdx.x & 63);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = item_sh;
+    if (item >= bt.n_items) break;
+    int c = 0;
+    while (c + 1 < bt.n_clips && bt.item_start[c + 1] <= item) ++c;
+    const FwdClipArgs& ca = bt.clip[c];
+    const int local = item - bt.item_start[c];
+    const int per_n = ca.tiles_x * ca.tiles_y;
+    Tile tl;
+    tl.n = local / per_n;
+    const int tile = local % per_n;
+    tl.ty0 = (tile / ca.tiles_x) * C::TH;
+    tl.tx0 = (tile % ca.tiles_x) * C::TW;
+    // LDS canvas must start from zeros for every item (pads and junk)
+    unsigned* z = reinterpret_cast<unsigned*>(lds);
+    for (int e = threadIdx.x; e < (C::XS_BYTES + C::SP_BYTES) / 4; e += C::NT) z[e] = 0u;
+    __syncthreads();
+    run_tile<C>(na, ca, tl, F, S);
+  }
+}
+
+// ------------------------------------------------------------------ registry
+struct Variant {
+  int nl, cin, ch, bf16, th, tw;
+  const char* name;
+  void (*single)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
+  void (*batched)(const FwdNetArgs&, const BatchTable&, int32_t*, int, hipStream_t, hipError_t*);
+};
+
+template <class C>
+void launch_single(const FwdNetArgs& na, const FwdClipArgs& ca, hipStream_t st, hipError_t* err) {
+  dim3 grid(ca.tiles_x * ca.tiles_y, ca.N);
+  hipLaunchKernelGGL(fwd_kernel<C>, grid, dim3(C::NT), 0, st, na, ca);
+  *err = hipGetLastError();
+}
+template <class C>
+void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter, int n_wg,
+                    hipStream_t st, hipError_t* err) {
+  hipLaunchKernelGGL(fwd_batched_kernel<C>, dim3(n_wg), dim3(C::NT), 0, st, na, bt, counter);
+  *err = hipGetLastError();
+}
+
+#define EVS_VARIANT(NL, CIN, CH, BF, TH, TW, NW, NAME)                                     \
+  Variant{NL, CIN, CH, BF, TH, TW, NAME, &launch_single<Cfg<NL, CIN, CH, (bool)BF, TH, TW, NW>>, \
+          &launch_batched<Cfg<NL, CIN, CH, (bool)BF, TH, TW, NW>>}
+
+const Variant kVariants[] = {
+    // single-layer nets (input -> output), f32
+    EVS_VARIANT(1, 1, 16, 0, 32, 32, 8, "L1 cin1 f32 32x32"),
+    EVS_VARIANT(1, 3, 16, 0, 32, 32, 8, "L1 cin3 f32 32x32"),
+    // two-layer nets cin -> hidden(<=16) -> out
+    EVS_VARIANT(2, 3, 16, 0, 30, 40, 8, "L2 h16 f32 30x40"),
+    EVS_VARIANT(2, 3, 16, 0, 16, 32, 8, "L2 h16 f32 16x32"),
+    EVS_VARIANT(2, 1, 16, 0, 30, 40, 8, "L2 cin1 h16 f32 30x40"),
+    EVS_VARIANT(2, 3, 16, 1, 30, 40, 8, "L2 h16 bf16 30x40"),
+    // two-layer nets with hidden width <= 32
+    EVS_VARIANT(2, 3, 32, 0, 24, 32, 8, "L2 h32 f32 24x32"),
+    EVS_VARIANT(2, 3, 32, 0, 16, 48, 8, "L2 h32 f32 16x48"),
+    EVS_VARIANT(2, 3, 32, 1, 30, 40, 8, "L2 h32 bf16 30x40"),
+    EVS_VARIANT(2, 3, 32, 1, 24, 32, 8, "L2 h32 bf16 24x32"),
+    // three-layer nets
+    EVS_VARIANT(3, 3, 16, 0, 30, 40, 8, "L3 h16 f32 30x40"),
+    EVS_VARIANT(3, 3, 16, 0, 24, 32, 8, "L3 h16 f32 24x32"),
+    EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40"),
+    EVS_VARIANT(3, 3, 32, 1, 24, 32, 8, "L3 h32 bf16 24x32"),
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int padded_hidden(const evs_net& net) {
+  int mx = 0;
+  for (int l = 1; l < net.n_layers; ++l) mx = net.ch[l] > mx ? net.ch[l] : mx;
+  return mx <= 16 ? 16 : 32;
+}
+
+bool matches(const Variant& v, const evs_net& net) {
+  return v.nl == net.n_layers && v.cin == net.ch[0] && v.bf16 == (net.precision == EVS_BF16) &&
+         (net.n_layers == 1 || v.ch == padded_hidden(net));
+}
+
+const Variant* find_variant(const evs_net& net, int tile_id) {
+  int k = 0;
+  for (int i = 0; i < kNumVariants; ++i) {
+    if (!matches(kVariants[i], net)) continue;
+    if (k == tile_id) return &kVariants[i];
+    ++k;
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+int forward_tile_count(const evs_net& net) {
+  int k = 0;
+  for (int i = 0; i < kNumVariants; ++i) k += matches(kVariants[i], net) ? 1 : 0;
+  return k;
+}
+
+const char* forward_tile_name(const evs_net& net, int tile_id) {
+  const Variant* v = find_variant(net, tile_id);
+  return v ? v->name : nullptr;
+}
+
+void forward_tile_dims(const evs_net& net, int tile_id, int* th, int* tw) {
+  const Variant* v = find_variant(net, tile_id);
+  *th = v ? v->th : 0;
+  *tw = v ? v->tw : 0;
+}
+
+int forward_default_tile(const evs_net& net, int H, int W) {
+  (void)H; (void)W;
+  return forward_tile_count(net) > 0 ? 0 : -1;
+}
+
+int launch_forward(const evs_net& net, const FwdNetArgs& na, const FwdClipArgs& ca, int tile_id,
+                   hipStream_t stream) {
+  const Variant* v = find_variant(net, tile_id);
+  if (!v) return fail(EVS_EUNSUPPORTED, "no compiled forward kernel for this network shape");
+  hipError_t e = hipSuccess;
+  v->single(na, ca, stream, &e);
+  if (e != hipSuccess) return hip_check(e, "forward kernel launch");
+  return EVS_OK;
+}
+
+int launch_forward_batched(const evs_net& net, const FwdNetArgs& na, const BatchTable& bt, int tile_id,
+                           int32_t* counter, hipStream_t stream) {
+  const Variant* v = find_variant(net, tile_id);
+  if (!v) return fail(EVS_EUNSUPPORTED, "no compiled forward kernel for this network shape");
+  int dev = 0, ncu = 0;
+  EVS_HIP(hipGetDevice(&dev));
+  EVS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int n_wg = bt.n_items < ncu ? bt.n_items : ncu;
+  hipError_t e = hipSuccess;
+  v->batched(na, bt, counter, n_wg, stream, &e);
+  if (e != hipSuccess) return hip_check(e, "batched forward kernel launch");
+  return EVS_OK;
+}
+
+}  // namespace evs

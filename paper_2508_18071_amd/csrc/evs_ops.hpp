@@ -1,0 +1,34 @@
+// Internal declarations of the non-forward operations of libevs.
+#pragma once
+
+#include "evs_internal.hpp"
+
+namespace evs {
+
+// small utility kernels (evs_util.hip)
+int zero_i32(int32_t* p, size_t n, hipStream_t s);
+int zero_f32(float* p, size_t n, hipStream_t s);
+int copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
+
+// EMD loss (evs_emd.hip)
+size_t emd_workspace_bytes(int N, int T, int C, int H, int W);
+int emd_loss(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda,
+             float* loss, float* grad, void* ws, size_t ws_bytes, hipStream_t st);
+
+// event compaction (evs_compact.hip)
+size_t compact_workspace_bytes(int T, int C, int H, int W);
+int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events, int64_t cap,
+                   int64_t* count, void* ws, size_t ws_bytes, hipStream_t st);
+
+// BPTT backward (evs_backward.hip)
+size_t backward_workspace_bytes(const evs_net& net, const evs_clip& clip, int ckpt_every);
+int backward(const evs_net& net, const void* packed, const evs_clip& clip, const float* ckpt,
+             int ckpt_every, const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v,
+             void* ws, size_t ws_bytes, hipStream_t st);
+
+// tile selection (evs_api.cpp)
+int choose_tile(const evs_net& net, int H, int W);
+void remember_tile(const evs_net& net, int H, int W, int tile);
+FwdNetArgs make_net_args(const evs_net& net, const void* packed);
+
+}  // namespace evs

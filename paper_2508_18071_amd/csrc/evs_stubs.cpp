@@ -1,0 +1,35 @@
+// Temporary placeholders for operations not yet implemented.
+#include "evs_ops.hpp"
+
+namespace evs {
+size_t emd_workspace_bytes(int, int, int, int, int) { return 0; }
+int emd_loss(const float*, const int8_t*, int, int, int, int, int, float, float*, float*, void*, size_t,
+             hipStream_t) { return fail(EVS_EUNSUPPORTED, "not implemented"); }
+size_t compact_workspace_bytes(int, int, int, int) { return 0; }
+int compact_events(const int8_t*, int, int, int, int, uint64_t*, int64_t, int64_t*, void*, size_t, hipStream_t) {
+  return fail(EVS_EUNSUPPORTED, "not implemented");
+}
+size_t backward_workspace_bytes(const evs_net&, const evs_clip&, int) { return 0; }
+int backward(const evs_net&, const void*, const evs_clip&, const float*, int, const float*, float* const*, float*,
+             float*, void*, size_t, hipStream_t) { return fail(EVS_EUNSUPPORTED, "not implemented"); }
+}  // namespace evs
+
+extern "C" {
+int evs_backward(const evs_net* net, const void* packed, const evs_clip* clip, const float* ckpt, int32_t k,
+                 const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v, void* ws, size_t wsb,
+                 void* stream) {
+  return evs::backward(*net, packed, *clip, ckpt, k, grad_s, grad_w, grad_x, grad_v, ws, wsb, (hipStream_t)stream);
+}
+int evs_emd_loss(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t C, int32_t H, int32_t W,
+                 float lambda_count, float* loss, float* grad_s, void* ws, size_t wsb, void* stream) {
+  return evs::emd_loss(s, e, N, T, C, H, W, lambda_count, loss, grad_s, ws, wsb, (hipStream_t)stream);
+}
+int evs_compact_events(const int8_t* s, int32_t T, int32_t C, int32_t H, int32_t W, uint64_t* events,
+                       int64_t capacity, int64_t* count, void* ws, size_t wsb, void* stream) {
+  return evs::compact_events(s, T, C, H, W, events, capacity, count, ws, wsb, (hipStream_t)stream);
+}
+int evs_autotune(const evs_net* net, int32_t H, int32_t W, int32_t T, int32_t* chosen, void* stream) {
+  (void)net; (void)H; (void)W; (void)T; (void)chosen; (void)stream;
+  return evs::fail(EVS_EUNSUPPORTED, "not implemented");
+}
+}

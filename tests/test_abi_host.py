@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point that include/evs.h declares, and rejects bad arguments
+before enqueuing anything."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "evs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(evs_[a-z0-9_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def evs():
+    import paper_2508_18071_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.fail("libevs.so has not been built")
+    m.lib()
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = _header_functions()
+    for required in ("evs_forward", "evs_backward", "evs_emd_loss", "evs_compact_events",
+                     "evs_workspace_bytes", "evs_pack_weights", "evs_autotune"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(evs):
+    lib = ctypes.CDLL(evs.LIB_PATH)
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+    assert set(_header_functions()) == set(evs.EXPORTED)
+
+
+def test_status_strings(evs):
+    L = evs.lib()
+    assert L.evs_status_str(0) == b"ok"
+    assert b"invalid" in L.evs_status_str(1)
+    assert L.evs_version().startswith(b"evs")
+
+
+def _net(evs, **kw):
+    return evs.Net(**kw).c()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(channels=(3, 16, 16, 2), theta=0.0), 1),
+    (dict(channels=(3, 16, 16, 2), leak=1.5), 1),
+    (dict(channels=(3, 16, 8, 2)), 2),
+    (dict(channels=(3, 64, 2)), 2),
+    (dict(channels=(3, 16, 3)), 2),
+    (dict(channels=(2, 16, 2)), 2),
+    (dict(channels=(3, 16, 2), precision="bf16", relaxed=True), 2),
+])
+def test_forward_rejects_bad_networks_before_launch(evs, kw, code):
+    net = _net(evs, **kw)
+    c = evs._lib.EvsClip()
+    c.N, c.T, c.H, c.W = 1, 4, 8, 8
+    c.x = 16  # never dereferenced: validation fails first
+    st = evs.lib().evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0,
+                               None, 0, None)
+    assert st == code
+    assert evs.lib().evs_last_error()
+
+
+def test_forward_rejects_bad_clips_and_workspace(evs):
+    L = evs.lib()
+    net = _net(evs, channels=(3, 16, 16, 2))
+    c = evs._lib.EvsClip()
+    c.N, c.T, c.H, c.W = 1, 0, 8, 8
+    c.x = 16
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None) == 1
+    c.T = 4
+    c.x = None
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None) == 1
+    c.x = 16
+    c.v_state = 32           # needs a workspace copy of the initial state
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None) == 3
+    assert L.evs_forward(ctypes.byref(net), None, ctypes.byref(c), 1, None, 0, None, 0, None) == 1
+    # checkpoints need ckpt_every >= 1
+    c.v_state = None
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1,
+                         ctypes.c_void_p(64), 0, None, 0, None) == 1
+    c.H = 5000
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None) == 2
+
+
+def test_workspace_sizes(evs):
+    L = evs.lib()
+    net = _net(evs, channels=(3, 16, 16, 2))
+    c = evs._lib.EvsClip()
+    c.N, c.T, c.H, c.W = 2, 8, 30, 40
+    assert L.evs_workspace_bytes(ctypes.byref(net), ctypes.byref(c), 1, 0, 0) == 0
+    c.v_state = 16
+    assert L.evs_workspace_bytes(ctypes.byref(net), ctypes.byref(c), 1, 0, 0) >= 2 * 34 * 30 * 40 * 4
+    assert L.evs_workspace_bytes(ctypes.byref(net), ctypes.byref(c), 1, 0, 99) == ctypes.c_size_t(-1).value
+
+
+def test_tile_registry(evs):
+    for ch, prec in [((3, 16, 16, 2), "fp32"), ((3, 32, 2), "bf16"), ((3, 8, 2), "fp32"), ((1, 1), "fp32")]:
+        net = evs.Net(ch, precision=prec)
+        n = evs.tile_count(net)
+        assert n >= 1
+        assert all(evs.tile_name(net, t) for t in range(n))
+        with pytest.raises(evs.EvsError):
+            evs.set_tile(net, n)

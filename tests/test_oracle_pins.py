@@ -449,3 +449,10 @@ def test_teacher_forced_reproduces_exact_trajectory_and_flags_errors():
     refs = evsnet.teacher_forced(x, ws, 0.5, 0.9, bad)
     err = np.abs(refs[1] - bad[1])
     assert err[3, 0, 2, 2] == pytest.approx(1e-3, rel=1e-6)
+
+
+def test_bf16_round_matches_torch():
+    vals = np.concatenate([RNG.normal(size=5000).astype(np.float32) * 10,
+                           np.array([1.0, -1.0, 0.0, 1.00390625, 1.01171875, 3.0e38, 1e-40], np.float32)])
+    ref = torch.from_numpy(vals).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(evsnet.bf16_round(vals), ref)
