@@ -33,10 +33,13 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 constexpr int align16(int b) { return (b + 15) & ~15; }
 
-template <int NL_, int CIN_, int CH_, bool BF16_, int TH_, int TW_, int NW_>
+// FULL_ = true compiles the training/debug features (h traces, membrane
+// checkpoints, relaxed spikes); the inference build leaves them out so that
+// the hot loop carries no dead address arithmetic.
+template <int NL_, int CIN_, int CH_, bool BF16_, int TH_, int TW_, int NW_, bool FULL_>
 struct Cfg {
   static constexpr int NL = NL_, CIN = CIN_, CH = CH_, TH = TH_, TW = TW_, NW = NW_;
-  static constexpr bool BF16 = BF16_;
+  static constexpr bool BF16 = BF16_, FULL = FULL_;
   static constexpr int CO = 2;                       // output channels (max)
   static constexpr int NH = NL - 1;                  // hidden layers
   static constexpr int CHT = TH + 2 * NL, CWT = TW + 2 * NL;
@@ -60,8 +63,6 @@ struct Cfg {
   static constexpr int XS_BYTES = align16(CIN * NPIXL * XELEM);
   static constexpr int SP_BYTES = NH >= 1 ? align16(NPIXL * CH * XELEM) : 0;
   static constexpr int WL_FLOATS = 9 * (NH >= 1 ? CH : CIN) * CO;
-  static constexpr int LDS_BYTES = XS_BYTES + SP_BYTES + WL_FLOATS * 4;
-  static_assert(LDS_BYTES <= 160 * 1024, "tile does not fit in LDS");
   static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
   static_assert(NB1 <= 32 && NB2 <= 32 && NOUT <= 32 && (BF16 ? 8 * KS1 : KS1) <= 32, "mask words overflow");
   static constexpr int toff(int tau) { return (tau / 3 - 1) * CWT + (tau % 3 - 1); }
@@ -75,7 +76,7 @@ __device__ inline f4 mfma_bf16(u4 a, u4 b, f4 c) {
                                                  __builtin_bit_cast(bf8, b), c, 0, 0, 0);
 }
 
-__device__ inline float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+__device__ inline float sigm(float z) { return __frcp_rn(1.0f + __expf(-z)); }
 
 // BiLIF fire + reset (Eq. 2-3): returns the spike, updates v in place (v
 // holds the charged potential h on entry).
@@ -97,17 +98,6 @@ __device__ inline unsigned pack_bf16x2(float lo, float hi) {
 }
 
 // ------------------------------------------------------------------ weights
-// Weight fragments of the MFMA layers, loaded once per workgroup.
-template <class C>
-struct Frags {
-  // layer 1 (hidden, input x): A[cout][K], K = tap * CIN + c
-  float a1f[C::MB][C::BF16 ? 1 : C::KS1];
-  u4 a1b[C::MB][C::BF16 ? C::KS1 : 1];
-  // layer 2 (hidden->hidden): A[cout][K], K = tap * CH + ci
-  float a2f[C::NH >= 2 && !C::BF16 ? C::MB : 1][C::NH >= 2 && !C::BF16 ? C::KS2 : 1];
-  u4 a2b[C::NH >= 2 && C::BF16 ? C::MB : 1][C::NH >= 2 && C::BF16 ? C::KS2 : 1];
-};
-
 __device__ inline float wget(const FwdNetArgs& na, int layer, int co, int ci, int tap, bool bf) {
   // layer 0-based; real channel bounds checked by the caller
   const int cin = na.ch[layer];
@@ -115,91 +105,90 @@ __device__ inline float wget(const FwdNetArgs& na, int layer, int co, int ci, in
   return bf ? round_bf16(w) : w;
 }
 
+// LDS layout of one workgroup (byte offsets).
 template <class C>
-__device__ void load_frags(const FwdNetArgs& na, Frags<C>& F, int lane) {
-  const int i = lane & 15, g = lane >> 4;
+struct Layout {
+  static constexpr int XS = 0;                                  // x tile [CIN][NPIXL]
+  static constexpr int SP = XS + C::XS_BYTES;                   // spikes [NPIXL][CH]
+  static constexpr int WL = SP + C::SP_BYTES;                   // out weights [9][CI][2] f32
+  static constexpr int FR1 = WL + align16(C::WL_FLOATS * 4);    // layer-1 A fragments
+  static constexpr int FR1_BYTES = C::NH >= 1 ? C::KS1 * C::MB * 64 * (C::BF16 ? 16 : 4) : 0;
+  static constexpr int FR2 = FR1 + FR1_BYTES;                   // layer-2 A fragments
+  static constexpr int FR2_BYTES = C::NH >= 2 ? C::KS2 * C::MB * 64 * (C::BF16 ? 16 : 4) : 0;
+  static constexpr int TOTAL = FR2 + FR2_BYTES;
+  static_assert(TOTAL <= 160 * 1024, "tile does not fit in LDS");
+};
+
+// Fill the weight areas of LDS: output-layer weights wl[tap][ci][co] (co
+// padded to 2) and the MFMA A-operand fragments of the hidden layers in the
+// per-lane order the k-step loops read them.
+template <class C>
+__device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
+  using Lo = Layout<C>;
+  {
+    float* wl = reinterpret_cast<float*>(lds + Lo::WL);
+    const int L = na.n_layers - 1;
+    const int cin = na.ch[L], cout = na.ch[L + 1];
+    constexpr int CI = C::NH >= 1 ? C::CH : C::CIN;
+    for (int e = threadIdx.x; e < C::WL_FLOATS; e += C::NT) {
+      const int co = e % 2, ci = (e / 2) % CI, tap = e / (2 * CI);
+      wl[e] = (co < cout && ci < cin) ? wget(na, L, co, ci, tap, C::BF16) : 0.f;
+    }
+  }
   if constexpr (C::NH >= 1) {
     const int c1 = na.ch[1];
-#pragma unroll
-    for (int m = 0; m < C::MB; ++m) {
-      const int co = 16 * m + i;
+    // entry (q, m, lane): row co = 16m + lane%16, lane group g = lane/16
+    for (int e = threadIdx.x; e < C::KS1 * C::MB * 64; e += C::NT) {
+      const int lane = e % 64, m = (e / 64) % C::MB, q = e / (64 * C::MB);
+      const int co = 16 * m + (lane & 15), g = lane >> 4;
       if constexpr (!C::BF16) {
-#pragma unroll
-        for (int q = 0; q < C::KS1; ++q) {
-          const int K = 4 * q + g;
-          float w = 0.f;
-          if (K < C::K1 && co < c1) w = wget(na, 0, co, K % C::CIN, K / C::CIN, false);
-          F.a1f[m][q] = w;
-        }
+        const int K = 4 * q + g;
+        reinterpret_cast<float*>(lds + Lo::FR1)[e] =
+            (K < C::K1 && co < c1) ? wget(na, 0, co, K % C::CIN, K / C::CIN, false) : 0.f;
       } else {
-#pragma unroll
-        for (int q = 0; q < C::KS1; ++q) {
-          unsigned wd[4];
-#pragma unroll
-          for (int e2 = 0; e2 < 4; ++e2) {
-            float ww[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int K = 32 * q + 8 * g + 2 * e2 + h;
-              ww[h] = (K < C::K1 && co < c1) ? wget(na, 0, co, K % C::CIN, K / C::CIN, true) : 0.f;
-            }
-            wd[e2] = pack_bf16x2(ww[0], ww[1]);
+        unsigned wd[4];
+        for (int e2 = 0; e2 < 4; ++e2) {
+          float ww[2];
+          for (int h = 0; h < 2; ++h) {
+            const int K = 32 * q + 8 * g + 2 * e2 + h;
+            ww[h] = (K < C::K1 && co < c1) ? wget(na, 0, co, K % C::CIN, K / C::CIN, true) : 0.f;
           }
-          F.a1b[m][q] = u4{wd[0], wd[1], wd[2], wd[3]};
+          wd[e2] = pack_bf16x2(ww[0], ww[1]);
         }
+        reinterpret_cast<u4*>(lds + Lo::FR1)[e] = u4{wd[0], wd[1], wd[2], wd[3]};
       }
     }
   }
   if constexpr (C::NH >= 2) {
     const int c1 = na.ch[1], c2 = na.ch[2];
-#pragma unroll
-    for (int m = 0; m < C::MB; ++m) {
-      const int co = 16 * m + i;
-      if constexpr (!C::BF16) {
-#pragma unroll
-        for (int tau = 0; tau < 9; ++tau) {
-#pragma unroll
-          for (int q = 0; q < C::CH / 4; ++q) {
-            const int ci = 4 * g + (q & 3) + 16 * (q >> 2);
-            F.a2f[m][tau * (C::CH / 4) + q] =
-                (co < c2 && ci < c1) ? wget(na, 1, co, ci, tau, false) : 0.f;
+    if constexpr (!C::BF16) {
+      // entry ((tau, hh, m, lane), q4): k-step (tau, 4hh+q4), input channel 4g + q4 + 16hh
+      for (int e = threadIdx.x; e < 9 * (C::CH / 16) * C::MB * 64 * 4; e += C::NT) {
+        const int q4 = e % 4, lane = (e / 4) % 64, m = (e / 256) % C::MB;
+        const int hh = (e / (256 * C::MB)) % (C::CH / 16), tau = e / (256 * C::MB * (C::CH / 16));
+        const int co = 16 * m + (lane & 15), g = lane >> 4;
+        const int ci = 4 * g + q4 + 16 * hh;
+        reinterpret_cast<float*>(lds + Lo::FR2)[e] = (co < c2 && ci < c1) ? wget(na, 1, co, ci, tau, false) : 0.f;
+      }
+    } else {
+      for (int e = threadIdx.x; e < C::KS2 * C::MB * 64; e += C::NT) {
+        const int lane = e % 64, m = (e / 64) % C::MB, q = e / (64 * C::MB);
+        const int co = 16 * m + (lane & 15), g = lane >> 4;
+        int tau, cib;
+        if constexpr (C::CH == 32) { tau = q; cib = 8 * g; }
+        else { tau = 2 * q + (g >> 1); cib = 8 * (g & 1); }
+        unsigned wd[4];
+        for (int e2 = 0; e2 < 4; ++e2) {
+          float ww[2];
+          for (int h = 0; h < 2; ++h) {
+            const int ci = cib + 2 * e2 + h;
+            ww[h] = (tau < 9 && co < c2 && ci < c1) ? wget(na, 1, co, ci, tau, true) : 0.f;
           }
+          wd[e2] = pack_bf16x2(ww[0], ww[1]);
         }
-      } else {
-#pragma unroll
-        for (int q = 0; q < C::KS2; ++q) {
-          int tau, cib;
-          if constexpr (C::CH == 32) { tau = q; cib = 8 * g; }
-          else { tau = 2 * q + (g >> 1); cib = 8 * (g & 1); }
-          unsigned wd[4];
-#pragma unroll
-          for (int e2 = 0; e2 < 4; ++e2) {
-            float ww[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int ci = cib + 2 * e2 + h;
-              ww[h] = (tau < 9 && co < c2 && ci < c1) ? wget(na, 1, co, ci, tau, true) : 0.f;
-            }
-            wd[e2] = pack_bf16x2(ww[0], ww[1]);
-          }
-          F.a2b[m][q] = u4{wd[0], wd[1], wd[2], wd[3]};
-        }
+        reinterpret_cast<u4*>(lds + Lo::FR2)[e] = u4{wd[0], wd[1], wd[2], wd[3]};
       }
     }
-  }
-}
-
-// Output-layer weights into LDS as wl[tap][ci][co] (co padded to 2).
-template <class C>
-__device__ void load_out_weights(const FwdNetArgs& na, float* wl) {
-  const int L = na.n_layers - 1;
-  const int cin = na.ch[L], cout = na.ch[L + 1];
-  constexpr int CI = C::NH >= 1 ? C::CH : C::CIN;
-  for (int e = threadIdx.x; e < C::WL_FLOATS; e += C::NT) {
-    const int co = e % 2, ci = (e / 2) % CI, tap = e / (2 * CI);
-    float w = 0.f;
-    if (co < cout && ci < cin) w = wget(na, L, co, ci, tap, C::BF16);
-    wl[e] = w;
   }
 }
 
@@ -208,19 +197,105 @@ struct Tile {
   int n, ty0, tx0;
 };
 
+__device__ __forceinline__ int tap_off(int tau, int cwt) {
+  const int ty = tau / 3;
+  return (ty - 1) * cwt + (tau - 3 * ty - 1);
+}
+
+// Hidden-layer epilogue for one 16-pixel block: st holds the charged
+// potentials h of MB x 4 (channel, pixel) pairs of this lane; fire, reset,
+// write spikes to LDS and, optionally, h to the trace.
 template <class C>
-struct Lds {
-  float* xsf;            // [CIN][NPIXL] f32      (BF16: unused)
-  uint16_t* xsb;         // [CIN][NPIXL] bf16     (FP32: unused)
-  float* spf;            // [NPIXL][CH] f32
-  uint16_t* spb;         // [NPIXL][CH] bf16
-  float* wl;             // output-layer weights
-};
+__device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int pr, bool valid, int g,
+                                                float theta, float alpha, bool relaxed, float* trace_t,
+                                                int cl, int choff, int gy0, int gx0, int W, size_t HW) {
+  if (C::FULL && trace_t && valid) {
+    const int row = pr / C::CWT, col = pr % C::CWT;
+    if (row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
+      const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int co = 16 * m + 4 * g + r;
+          if (co < cl) trace_t[(size_t)(choff + co) * HW + pix] = st[m][r];
+        }
+    }
+  }
+  const int p = C::PADF + pr;
+#pragma unroll
+  for (int m = 0; m < C::MB; ++m) {
+    f4 s;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float v = st[m][r];
+      s[r] = bilif(v, theta, alpha, C::FULL && relaxed);
+      st[m][r] = v;
+    }
+    if (!valid) s = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (C::BF16) {
+      uint2 w2 = {pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
+      *reinterpret_cast<uint2*>(lds + Layout<C>::SP + ((size_t)p * C::CH + 16 * m + 4 * g) * 2) = w2;
+    } else {
+      *reinterpret_cast<f4*>(lds + Layout<C>::SP + ((size_t)p * C::CH + 16 * m + 4 * g) * 4) = s;
+    }
+  }
+}
+
+// Write the membrane state of the interior pixels of a hidden layer.
+template <class C, int NB>
+__device__ __forceinline__ void write_hidden_state(const f4 (&st)[NB][C::MB], unsigned vm, int layer, int wave,
+                                                   int j, int g, float* dst, int cl, int choff, int gy0,
+                                                   int gx0, int W, size_t HW) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int pr = layer * C::CWT + 16 * (wave + C::NW * i) + j;
+    const int row = pr / C::CWT, col = pr % C::CWT;
+    if (((vm >> i) & 1u) && row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
+      const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int co = 16 * m + 4 * g + r;
+          if (co < cl) dst[(size_t)(choff + co) * HW + pix] = st[i][m][r];
+        }
+    }
+  }
+}
+
+template <class C, int NB>
+__device__ __forceinline__ void read_hidden_state(f4 (&st)[NB][C::MB], unsigned vm, int layer, int wave, int j,
+                                                  int g, const float* src, int cl, int choff, int gy0, int gx0,
+                                                  int W, size_t HW) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m) {
+      f4 v = {0.f, 0.f, 0.f, 0.f};
+      if (src && ((vm >> i) & 1u)) {
+        const int pr = layer * C::CWT + 16 * (wave + C::NW * i) + j;
+        const size_t pix = (size_t)(gy0 + pr / C::CWT) * W + (gx0 + pr % C::CWT);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int co = 16 * m + 4 * g + r;
+          if (co < cl) v[r] = src[(size_t)(choff + co) * HW + pix];
+        }
+      }
+      st[i][m] = v;
+    }
+}
 
 // Process one tile over frames [0, T) of one clip.
 template <class C>
-__device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl,
-                         const Frags<C>& F, const Lds<C>& S) {
+__device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl, char* lds) {
+  using Lo = Layout<C>;
+  float* const xsf = reinterpret_cast<float*>(lds + Lo::XS);
+  uint16_t* const xsb = reinterpret_cast<uint16_t*>(lds + Lo::XS);
+  const float* const spf = reinterpret_cast<const float*>(lds + Lo::SP);
+  const uint16_t* const spb = reinterpret_cast<const uint16_t*>(lds + Lo::SP);
+  const float* const wl = reinterpret_cast<const float*>(lds + Lo::WL);
+
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -235,7 +310,7 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
   const int choff2 = c1, choffo = (C::NH == 0) ? 0 : (C::NH == 1 ? c1 : c1 + c2);
   const int gy0 = tl.ty0 - C::NL, gx0 = tl.tx0 - C::NL;   // image coords of canvas (0,0)
 
-  // ---- per-lane geometry: validity masks of hidden blocks
+  // ---- validity masks of this lane's hidden-layer block pixels
   unsigned vm1 = 0, vm2 = 0;
   if constexpr (C::NH >= 1) {
 #pragma unroll
@@ -259,7 +334,7 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
       vm2 |= (ok ? 1u : 0u) << i;
     }
   }
-  // output pixels of this lane
+  // ---- output pixels of this lane
   int op[C::NOUT];
   unsigned ovm = 0;
 #pragma unroll
@@ -267,42 +342,9 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
     const int q = tid + C::NT * k;
     const int ty = q / C::TW, tx = q % C::TW;
     const bool inq = q < C::TH * C::TW;
-    op[k] = inq ? (C::NL + ty) * C::CWT + (C::NL + tx) : C::NL * C::CWT + C::NL;
+    op[k] = C::PADF + (inq ? (C::NL + ty) * C::CWT + (C::NL + tx) : C::NL * C::CWT + C::NL);
     const int gy = tl.ty0 + ty, gx = tl.tx0 + tx;
     ovm |= ((inq && gy < H && gx < W) ? 1u : 0u) << k;
-  }
-
-  // ---- layer-1 B-operand gather offsets (relative to the block pixel)
-  int xo1[C::BF16 ? 8 * C::KS1 : C::KS1];
-  unsigned xk1 = 0;   // bit set: gather slot holds a real (tap, channel)
-  if constexpr (!C::BF16) {
-#pragma unroll
-    for (int q = 0; q < C::KS1; ++q) {
-      const int K = 4 * q + g;
-      const int tap = K / C::CIN, c = K % C::CIN;
-      xo1[q] = K < C::K1 ? c * C::NPIXL + (tap / 3 - 1) * C::CWT + (tap % 3 - 1) : 0;
-      xk1 |= (K < C::K1 ? 1u : 0u) << q;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < C::KS1; ++q)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int K = 32 * q + 8 * g + e;
-        const int tap = K / C::CIN, c = K % C::CIN;
-        xo1[8 * q + e] = K < C::K1 ? c * C::NPIXL + (tap / 3 - 1) * C::CWT + (tap % 3 - 1) : 0;
-        xk1 |= (K < C::K1 ? 1u : 0u) << (8 * q + e);
-      }
-  }
-  // BF16 CH=16 hidden->hidden: tap per (k-step, lane group)
-  int so2[C::NH >= 2 && C::BF16 && C::CH == 16 ? C::KS2 : 1];
-  if constexpr (C::NH >= 2 && C::BF16 && C::CH == 16) {
-#pragma unroll
-    for (int q = 0; q < C::KS2; ++q) {
-      int tau = 2 * q + (g >> 1);
-      if (tau > 8) tau = 8;              // zero weights in that slot
-      so2[q] = ((tau / 3 - 1) * C::CWT + (tau % 3 - 1)) * C::CH + 8 * (g & 1);
-    }
   }
 
   // ---- state registers
@@ -310,42 +352,8 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
   f4 st2[C::NB2][C::MB];
   float so[C::NOUT][2];
   const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * sumc * HW : nullptr;
-  if constexpr (C::NH >= 1) {
-#pragma unroll
-    for (int i = 0; i < C::NB1; ++i)
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m) {
-        f4 v = {0.f, 0.f, 0.f, 0.f};
-        if (vin && ((vm1 >> i) & 1u)) {
-          const int pr = C::CWT + 16 * (wave + C::NW * i) + j;
-          const size_t pix = (size_t)(gy0 + pr / C::CWT) * W + (gx0 + pr % C::CWT);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int co = 16 * m + 4 * g + r;
-            if (co < c1) v[r] = vin[(size_t)co * HW + pix];
-          }
-        }
-        st1[i][m] = v;
-      }
-  }
-  if constexpr (C::NH >= 2) {
-#pragma unroll
-    for (int i = 0; i < C::NB2; ++i)
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m) {
-        f4 v = {0.f, 0.f, 0.f, 0.f};
-        if (vin && ((vm2 >> i) & 1u)) {
-          const int pr = 2 * C::CWT + 16 * (wave + C::NW * i) + j;
-          const size_t pix = (size_t)(gy0 + pr / C::CWT) * W + (gx0 + pr % C::CWT);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int co = 16 * m + 4 * g + r;
-            if (co < c2) v[r] = vin[(size_t)(choff2 + co) * HW + pix];
-          }
-        }
-        st2[i][m] = v;
-      }
-  }
+  if constexpr (C::NH >= 1) read_hidden_state<C, C::NB1>(st1, vm1, 1, wave, j, g, vin, c1, 0, gy0, gx0, W, HW);
+  if constexpr (C::NH >= 2) read_hidden_state<C, C::NB2>(st2, vm2, 2, wave, j, g, vin, c2, choff2, gy0, gx0, W, HW);
 #pragma unroll
   for (int k = 0; k < C::NOUT; ++k) {
     so[k][0] = so[k][1] = 0.f;
@@ -358,71 +366,37 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
     }
   }
 
-  // ---- x staging
+  // ---- x staging (register prefetch of the next frame)
   const float* xclip = ca.x + (size_t)tl.n * T * C::CIN * HW;
   float xpf[C::XPF];
-  auto load_x = [&](int t) {
-    const float* xf = xclip + (size_t)t * C::CIN * HW;
-#pragma unroll
-    for (int k = 0; k < C::XPF; ++k) {
-      const int e = tid + C::NT * k;
-      const int c = e / C::NPIX, rem = e % C::NPIX;
-      const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;
-      float v = 0.f;
-      if (e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = xf[(size_t)c * HW + (size_t)gy * W + gx];
-      xpf[k] = v;
-    }
-  };
-  auto store_x = [&]() {
-#pragma unroll
-    for (int k = 0; k < C::XPF; ++k) {
-      const int e = tid + C::NT * k;
-      if (e < C::XN) {
-        const int c = e / C::NPIX, rem = e % C::NPIX;
-        if constexpr (C::BF16) S.xsb[c * C::NPIXL + C::PADF + rem] = f32_to_bf16_rne(xpf[k]);
-        else S.xsf[c * C::NPIXL + C::PADF + rem] = xpf[k];
-      }
-    }
-  };
+#define EVS_LOAD_X(tt)                                                                          \
+  do {                                                                                          \
+    const float* xf = xclip + (size_t)(tt) * C::CIN * HW;                                       \
+    _Pragma("unroll") for (int k = 0; k < C::XPF; ++k) {                                        \
+      const int e = tid + C::NT * k;                                                            \
+      const int c = e / C::NPIX, rem = e % C::NPIX;                                             \
+      const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;                               \
+      float v = 0.f;                                                                            \
+      if (e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = xf[(size_t)c * HW + (size_t)gy * W + gx]; \
+      xpf[k] = v;                                                                               \
+    }                                                                                           \
+  } while (0)
+#define EVS_STORE_X()                                                                           \
+  do {                                                                                          \
+    _Pragma("unroll") for (int k = 0; k < C::XPF; ++k) {                                        \
+      const int e = tid + C::NT * k;                                                            \
+      if (e < C::XN) {                                                                          \
+        const int c = e / C::NPIX, rem = e % C::NPIX;                                           \
+        if constexpr (C::BF16) xsb[c * C::NPIXL + C::PADF + rem] = f32_to_bf16_rne(xpf[k]);    \
+        else xsf[c * C::NPIXL + C::PADF + rem] = xpf[k];                                        \
+      }                                                                                         \
+    }                                                                                           \
+  } while (0)
 
   const int nseg = ca.ckpt_every > 0 ? cdiv(T, ca.ckpt_every) : 0;
-  // writes the current state (before frame t) of interior pixels to dst
-  // ([sumC][H][W] for this clip)
-  auto write_state = [&](float* dst) {
-    if constexpr (C::NH >= 1) {
-#pragma unroll
-      for (int i = 0; i < C::NB1; ++i) {
-        const int pr = C::CWT + 16 * (wave + C::NW * i) + j;
-        const int row = pr / C::CWT, col = pr % C::CWT;
-        if (((vm1 >> i) & 1u) && row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
-          const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
-#pragma unroll
-          for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int co = 16 * m + 4 * g + r;
-              if (co < c1) dst[(size_t)co * HW + pix] = st1[i][m][r];
-            }
-        }
-      }
-    }
-    if constexpr (C::NH >= 2) {
-#pragma unroll
-      for (int i = 0; i < C::NB2; ++i) {
-        const int pr = 2 * C::CWT + 16 * (wave + C::NW * i) + j;
-        const int row = pr / C::CWT, col = pr % C::CWT;
-        if (((vm2 >> i) & 1u) && row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
-          const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
-#pragma unroll
-          for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int co = 16 * m + 4 * g + r;
-              if (co < c2) dst[(size_t)(choff2 + co) * HW + pix] = st2[i][m][r];
-            }
-        }
-      }
-    }
+  auto write_state = [&](float* dst) __attribute__((always_inline)) {
+    if constexpr (C::NH >= 1) write_hidden_state<C, C::NB1>(st1, vm1, 1, wave, j, g, dst, c1, 0, gy0, gx0, W, HW);
+    if constexpr (C::NH >= 2) write_hidden_state<C, C::NB2>(st2, vm2, 2, wave, j, g, dst, c2, choff2, gy0, gx0, W, HW);
 #pragma unroll
     for (int k = 0; k < C::NOUT; ++k) {
       if ((ovm >> k) & 1u) {
@@ -435,84 +409,80 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
     }
   };
 
-  // hidden-layer BiLIF epilogue on st (holding h): spikes -> LDS, trace
-  auto hidden_epilogue = [&](f4 (&st)[C::MB], int layer /*1 or 2*/, int b, bool valid, int cl, int choff,
-                             float* trace_t) {
-    const int pr = layer * C::CWT + 16 * b + j;
-#pragma unroll
-    for (int m = 0; m < C::MB; ++m) {
-      f4 s;
-      if (trace_t && valid) {
-        const int row = pr / C::CWT, col = pr % C::CWT;
-        if (row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
-          const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int co = 16 * m + 4 * g + r;
-            if (co < cl) trace_t[(size_t)(choff + co) * HW + pix] = st[m][r];
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float v = st[m][r];
-        s[r] = bilif(v, theta, alpha, relaxed);
-        st[m][r] = v;
-      }
-      if (!valid) s = f4{0.f, 0.f, 0.f, 0.f};
-      const int p = C::PADF + pr;
-      if constexpr (C::BF16) {
-        uint2 w2 = {pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
-        *reinterpret_cast<uint2*>(S.spb + (size_t)p * C::CH + 16 * m + 4 * g) = w2;
-      } else {
-        *reinterpret_cast<f4*>(S.spf + (size_t)p * C::CH + 16 * m + 4 * g) = s;
-      }
-    }
-  };
+  // block pixel bases (canvas index incl. front pad) of block i: pbase + 16*NW*i
+  const int p1base = C::PADF + C::CWT + 16 * wave + j;
+  const int p2base = C::PADF + 2 * C::CWT + 16 * wave + j;
 
   // ---- prologue: frame 0 into LDS, frame 1 into registers
-  load_x(0);
-  store_x();
-  if (T > 1) load_x(1);
+  EVS_LOAD_X(0);
+  EVS_STORE_X();
+  if (T > 1) EVS_LOAD_X(1);
   __syncthreads();
 
   for (int t = 0; t < T; ++t) {
-    if (ca.ckpt && (t % ca.ckpt_every) == 0)
-      write_state(ca.ckpt + ((size_t)tl.n * nseg + t / ca.ckpt_every) * sumc * HW);
-    float* trace_t = ca.h_trace ? ca.h_trace + ((size_t)tl.n * T + t) * sumc * HW : nullptr;
+    float* trace_t = nullptr;
+    if constexpr (C::FULL) {
+      if (ca.ckpt && (t % ca.ckpt_every) == 0)
+        write_state(ca.ckpt + ((size_t)tl.n * nseg + t / ca.ckpt_every) * sumc * HW);
+      trace_t = ca.h_trace ? ca.h_trace + ((size_t)tl.n * T + t) * sumc * HW : nullptr;
+    }
 
     if constexpr (C::NH >= 1) {
-      // ================= layer 1: x -> hidden (MFMA)
+      // ================= layer 1: x -> hidden (MFMA), K = tap * CIN + c
 #pragma unroll
       for (int i = 0; i < C::NB1; ++i)
 #pragma unroll
         for (int m = 0; m < C::MB; ++m) st1[i][m] *= leak;
-#pragma unroll
+#pragma unroll 1
       for (int q = 0; q < C::KS1; ++q) {
+        if constexpr (!C::BF16) {
+          const float* fr = reinterpret_cast<const float*>(lds + Lo::FR1) + q * C::MB * 64 + lane;
+          float a[C::MB];
 #pragma unroll
-        for (int i = 0; i < C::NB1; ++i) {
-          const int b = wave + C::NW * i;
-          if (b < C::NPB1) {
-            const int p = C::PADF + C::CWT + 16 * b + j;
-            if constexpr (!C::BF16) {
-              const int o = xo1[q];
-              const float xv = S.xsf[p + o];
-              const float bv = ((xk1 >> q) & 1u) ? xv : 0.f;
+          for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
+          const int K = 4 * q + g;
+          const bool kv = K < C::K1;
+          const int tap = K / C::CIN, c = K - tap * C::CIN;
+          const int o = kv ? c * C::NPIXL + tap_off(tap, C::CWT) : 0;
 #pragma unroll
-              for (int m = 0; m < C::MB; ++m) st1[i][m] = mfma_f32(F.a1f[m][q], bv, st1[i][m]);
-            } else {
+          for (int i = 0; i < C::NB1; ++i) {
+            if (wave + C::NW * i < C::NPB1) {
+              const float xv = xsf[p1base + 16 * C::NW * i + o];
+              const float bv = kv ? xv : 0.f;
+#pragma unroll
+              for (int m = 0; m < C::MB; ++m) st1[i][m] = mfma_f32(a[m], bv, st1[i][m]);
+            }
+          }
+        } else {
+          const u4* fr = reinterpret_cast<const u4*>(lds + Lo::FR1) + q * C::MB * 64 + lane;
+          u4 a[C::MB];
+#pragma unroll
+          for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
+          int o[8];
+          unsigned kvm = 0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int K = 32 * q + 8 * g + e;
+            const int tap = K / C::CIN, c = K - tap * C::CIN;
+            const bool kv = K < C::K1;
+            o[e] = kv ? c * C::NPIXL + tap_off(tap, C::CWT) : 0;
+            kvm |= (kv ? 1u : 0u) << e;
+          }
+#pragma unroll
+          for (int i = 0; i < C::NB1; ++i) {
+            if (wave + C::NW * i < C::NPB1) {
+              const int p = p1base + 16 * C::NW * i;
               unsigned wd[4];
 #pragma unroll
               for (int e2 = 0; e2 < 4; ++e2) {
-                const int o0 = xo1[8 * q + 2 * e2], o1 = xo1[8 * q + 2 * e2 + 1];
-                const unsigned r0 = S.xsb[p + o0], r1 = S.xsb[p + o1];
-                const unsigned lo = ((xk1 >> (8 * q + 2 * e2)) & 1u) ? r0 : 0u;
-                const unsigned hi = ((xk1 >> (8 * q + 2 * e2 + 1)) & 1u) ? r1 : 0u;
+                const unsigned r0 = xsb[p + o[2 * e2]], r1 = xsb[p + o[2 * e2 + 1]];
+                const unsigned lo = ((kvm >> (2 * e2)) & 1u) ? r0 : 0u;
+                const unsigned hi = ((kvm >> (2 * e2 + 1)) & 1u) ? r1 : 0u;
                 wd[e2] = lo | (hi << 16);
               }
               const u4 bv = {wd[0], wd[1], wd[2], wd[3]};
 #pragma unroll
-              for (int m = 0; m < C::MB; ++m) st1[i][m] = mfma_bf16(F.a1b[m][q], bv, st1[i][m]);
+              for (int m = 0; m < C::MB; ++m) st1[i][m] = mfma_bf16(a[m], bv, st1[i][m]);
             }
           }
         }
@@ -520,53 +490,66 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
 #pragma unroll
       for (int i = 0; i < C::NB1; ++i) {
         const int b = wave + C::NW * i;
-        if (b < C::NPB1) hidden_epilogue(st1[i], 1, b, (vm1 >> i) & 1u, c1, 0, trace_t);
+        if (b < C::NPB1)
+          hidden_epilogue<C>(st1[i], lds, C::CWT + 16 * b + j, (vm1 >> i) & 1u, g, theta, alpha, relaxed,
+                             trace_t, c1, 0, gy0, gx0, W, HW);
       }
       __syncthreads();                                   // B1: s1 visible, xs free
-      if (t + 1 < T) store_x();
-      if (t + 2 < T) load_x(t + 2);
+      if (t + 1 < T) EVS_STORE_X();
+      if (t + 2 < T) EVS_LOAD_X(t + 2);
     }
 
     if constexpr (C::NH >= 2) {
-      // ================= layer 2: hidden -> hidden (MFMA)
+      // ================= layer 2: hidden -> hidden (MFMA), K = tap * CH + ci
 #pragma unroll
       for (int i = 0; i < C::NB2; ++i)
 #pragma unroll
         for (int m = 0; m < C::MB; ++m) st2[i][m] *= leak;
       if constexpr (!C::BF16) {
-#pragma unroll
+#pragma unroll 1
         for (int tau = 0; tau < 9; ++tau) {
+          const int to = tap_off(tau, C::CWT);
 #pragma unroll
-          for (int i = 0; i < C::NB2; ++i) {
-            const int b = wave + C::NW * i;
-            if (b < C::NPB2) {
-              const int p = C::PADF + 2 * C::CWT + 16 * b + j + C::toff(tau);
+          for (int hh = 0; hh < C::CH / 16; ++hh) {
+            const f4* fr = reinterpret_cast<const f4*>(lds + Lo::FR2) +
+                           ((tau * (C::CH / 16) + hh) * C::MB) * 64 + lane;
+            f4 a[C::MB];
 #pragma unroll
-              for (int hh = 0; hh < C::CH / 16; ++hh) {
-                const f4 bv = *reinterpret_cast<const f4*>(S.spf + (size_t)p * C::CH + 16 * hh + 4 * g);
+            for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
+#pragma unroll
+            for (int i = 0; i < C::NB2; ++i) {
+              if (wave + C::NW * i < C::NPB2) {
+                const f4 bv = *reinterpret_cast<const f4*>(
+                    spf + (size_t)(p2base + 16 * C::NW * i + to) * C::CH + 16 * hh + 4 * g);
 #pragma unroll
                 for (int q4 = 0; q4 < 4; ++q4)
 #pragma unroll
-                  for (int m = 0; m < C::MB; ++m)
-                    st2[i][m] = mfma_f32(F.a2f[m][tau * (C::CH / 4) + 4 * hh + q4], bv[q4], st2[i][m]);
+                  for (int m = 0; m < C::MB; ++m) st2[i][m] = mfma_f32(a[m][q4], bv[q4], st2[i][m]);
               }
             }
           }
         }
       } else {
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < C::KS2; ++q) {
+          const u4* fr = reinterpret_cast<const u4*>(lds + Lo::FR2) + q * C::MB * 64 + lane;
+          u4 a[C::MB];
+#pragma unroll
+          for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
+          int o;
+          if constexpr (C::CH == 32) {
+            o = tap_off(q, C::CWT) * C::CH + 8 * g;
+          } else {
+            int tau = 2 * q + (g >> 1);
+            tau = tau > 8 ? 8 : tau;                     // zero weights in that slot
+            o = tap_off(tau, C::CWT) * C::CH + 8 * (g & 1);
+          }
 #pragma unroll
           for (int i = 0; i < C::NB2; ++i) {
-            const int b = wave + C::NW * i;
-            if (b < C::NPB2) {
-              const int p = C::PADF + 2 * C::CWT + 16 * b + j;
-              int o;
-              if constexpr (C::CH == 32) o = C::toff(q) * C::CH + 8 * g;
-              else o = so2[q];
-              const u4 bv = *reinterpret_cast<const u4*>(S.spb + (size_t)p * C::CH + o);
+            if (wave + C::NW * i < C::NPB2) {
+              const u4 bv = *reinterpret_cast<const u4*>(spb + (size_t)(p2base + 16 * C::NW * i) * C::CH + o);
 #pragma unroll
-              for (int m = 0; m < C::MB; ++m) st2[i][m] = mfma_bf16(F.a2b[m][q], bv, st2[i][m]);
+              for (int m = 0; m < C::MB; ++m) st2[i][m] = mfma_bf16(a[m], bv, st2[i][m]);
             }
           }
         }
@@ -575,26 +558,28 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
 #pragma unroll
       for (int i = 0; i < C::NB2; ++i) {
         const int b = wave + C::NW * i;
-        if (b < C::NPB2) hidden_epilogue(st2[i], 2, b, (vm2 >> i) & 1u, c2, choff2, trace_t);
+        if (b < C::NPB2)
+          hidden_epilogue<C>(st2[i], lds, 2 * C::CWT + 16 * b + j, (vm2 >> i) & 1u, g, theta, alpha, relaxed,
+                             trace_t, c2, choff2, gy0, gx0, W, HW);
       }
       __syncthreads();                                   // B3: s2 visible
     }
 
-    // ================= output layer (VALU)
+    // ================= output layer (VALU), weights broadcast from LDS
     {
       float u[C::NOUT][2];
 #pragma unroll
       for (int k = 0; k < C::NOUT; ++k) { u[k][0] = leak * so[k][0]; u[k][1] = leak * so[k][1]; }
-#pragma unroll
+#pragma unroll 1
       for (int tau = 0; tau < 9; ++tau) {
-        const int to = C::toff(tau);
+        const int to = tap_off(tau, C::CWT);
         if constexpr (C::NH == 0) {
 #pragma unroll
           for (int c = 0; c < C::CIN; ++c) {
-            const float w0 = S.wl[(tau * C::CIN + c) * 2], w1 = S.wl[(tau * C::CIN + c) * 2 + 1];
+            const float w0 = wl[(tau * C::CIN + c) * 2], w1 = wl[(tau * C::CIN + c) * 2 + 1];
 #pragma unroll
             for (int k = 0; k < C::NOUT; ++k) {
-              const float xv = S.xsf[c * C::NPIXL + C::PADF + op[k] + to];
+              const float xv = xsf[c * C::NPIXL + op[k] + to];
               u[k][0] = fmaf(w0, xv, u[k][0]);
               u[k][1] = fmaf(w1, xv, u[k][1]);
             }
@@ -602,11 +587,11 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
         } else if constexpr (!C::BF16) {
 #pragma unroll
           for (int c4 = 0; c4 < C::CH / 4; ++c4) {
-            const f4 wa = *reinterpret_cast<const f4*>(S.wl + (tau * C::CH + 4 * c4) * 2);
-            const f4 wb = *reinterpret_cast<const f4*>(S.wl + (tau * C::CH + 4 * c4) * 2 + 4);
+            const f4 wa = *reinterpret_cast<const f4*>(wl + (tau * C::CH + 4 * c4) * 2);
+            const f4 wb = *reinterpret_cast<const f4*>(wl + (tau * C::CH + 4 * c4) * 2 + 4);
 #pragma unroll
             for (int k = 0; k < C::NOUT; ++k) {
-              const f4 sv = *reinterpret_cast<const f4*>(S.spf + (size_t)(C::PADF + op[k] + to) * C::CH + 4 * c4);
+              const f4 sv = *reinterpret_cast<const f4*>(spf + (size_t)(op[k] + to) * C::CH + 4 * c4);
               u[k][0] = fmaf(wa[0], sv[0], u[k][0]); u[k][1] = fmaf(wa[1], sv[0], u[k][1]);
               u[k][0] = fmaf(wa[2], sv[1], u[k][0]); u[k][1] = fmaf(wa[3], sv[1], u[k][1]);
               u[k][0] = fmaf(wb[0], sv[2], u[k][0]); u[k][1] = fmaf(wb[1], sv[2], u[k][1]);
@@ -618,10 +603,10 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
           for (int c8 = 0; c8 < C::CH / 8; ++c8) {
             f4 wv[4];
 #pragma unroll
-            for (int z = 0; z < 4; ++z) wv[z] = *reinterpret_cast<const f4*>(S.wl + (tau * C::CH + 8 * c8) * 2 + 4 * z);
+            for (int z = 0; z < 4; ++z) wv[z] = *reinterpret_cast<const f4*>(wl + (tau * C::CH + 8 * c8) * 2 + 4 * z);
 #pragma unroll
             for (int k = 0; k < C::NOUT; ++k) {
-              const u4 raw = *reinterpret_cast<const u4*>(S.spb + (size_t)(C::PADF + op[k] + to) * C::CH + 8 * c8);
+              const u4 raw = *reinterpret_cast<const u4*>(spb + (size_t)(op[k] + to) * C::CH + 8 * c8);
 #pragma unroll
               for (int z = 0; z < 4; ++z) {
                 const float s0 = __builtin_bit_cast(float, raw[z] << 16);
@@ -640,13 +625,13 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
         const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
 #pragma unroll
         for (int co = 0; co < 2; ++co) {
-          if (ok && co < cout && trace_t) trace_t[(size_t)(choffo + co) * HW + pix] = u[k][co];
+          if (C::FULL && ok && co < cout && trace_t) trace_t[(size_t)(choffo + co) * HW + pix] = u[k][co];
           float v = u[k][co];
-          const float s = bilif(v, theta, alpha, relaxed);
+          const float s = bilif(v, theta, alpha, C::FULL && relaxed);
           so[k][co] = v;
           if (ok && co < cout && ca.s_out) {
             const size_t o = (((size_t)tl.n * T + t) * cout + co) * HW + pix;
-            if (ca.s_fp32) reinterpret_cast<float*>(ca.s_out)[o] = s;
+            if (C::FULL && ca.s_fp32) reinterpret_cast<float*>(ca.s_out)[o] = s;
             else reinterpret_cast<int8_t*>(ca.s_out)[o] = (int8_t)s;
           }
         }
@@ -654,25 +639,22 @@ __device__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile
     }
     if constexpr (C::NH == 0) {
       __syncthreads();
-      if (t + 1 < T) store_x();
-      if (t + 2 < T) load_x(t + 2);
+      if (t + 1 < T) EVS_STORE_X();
+      if (t + 2 < T) EVS_LOAD_X(t + 2);
     }
     __syncthreads();                                     // B4: spikes / xs consumed
   }
   if (ca.v_out) write_state(ca.v_out + (size_t)tl.n * sumc * HW);
+#undef EVS_LOAD_X
+#undef EVS_STORE_X
 }
 
 template <class C>
-__device__ void init_lds(const FwdNetArgs& na, Lds<C>& S, char* lds) {
-  S.xsf = reinterpret_cast<float*>(lds);
-  S.xsb = reinterpret_cast<uint16_t*>(lds);
-  S.spf = reinterpret_cast<float*>(lds + C::XS_BYTES);
-  S.spb = reinterpret_cast<uint16_t*>(lds + C::XS_BYTES);
-  S.wl = reinterpret_cast<float*>(lds + C::XS_BYTES + C::SP_BYTES);
+__device__ __forceinline__ void init_lds(const FwdNetArgs& na, char* lds) {
   // zero canvas and pads once: pads are read only by junk (masked) pixels
   unsigned* z = reinterpret_cast<unsigned*>(lds);
   for (int e = threadIdx.x; e < (C::XS_BYTES + C::SP_BYTES) / 4; e += C::NT) z[e] = 0u;
-  load_out_weights<C>(na, S.wl);
+  load_weights<C>(na, lds);
 }
 
 // XCD-aware tile order: the hardware deals workgroups round-robin over the
@@ -687,11 +669,8 @@ __device__ inline int xcd_remap(int b, int n) {
 
 template <class C>
 __global__ __launch_bounds__(C::NT) void fwd_kernel(FwdNetArgs na, FwdClipArgs ca) {
-  __shared__ __attribute__((aligned(16))) char lds[C::LDS_BYTES];
-  Lds<C> S;
-  init_lds<C>(na, S, lds);
-  Frags<C> F;
-  load_frags<C>(na, F, threadIdx.x & 63);
+  __shared__ __attribute__((aligned(16))) char lds[Layout<C>::TOTAL];
+  init_lds<C>(na, lds);
   __syncthreads();
   const int ntiles = ca.tiles_x * ca.tiles_y;
   const int tile = xcd_remap(blockIdx.x, ntiles);
@@ -699,19 +678,16 @@ __global__ __launch_bounds__(C::NT) void fwd_kernel(FwdNetArgs na, FwdClipArgs c
   tl.n = blockIdx.y;
   tl.ty0 = (tile / ca.tiles_x) * C::TH;
   tl.tx0 = (tile % ca.tiles_x) * C::TW;
-  run_tile<C>(na, ca, tl, F, S);
+  run_tile<C>(na, ca, tl, lds);
 }
 
 // Persistent batched kernel: workgroups pop (clip, tile) items from a device
 // counter; items are ordered clip by clip, clips longest-first.
 template <class C>
 __global__ __launch_bounds__(C::NT) void fwd_batched_kernel(FwdNetArgs na, BatchTable bt, int32_t* counter) {
-  __shared__ __attribute__((aligned(16))) char lds[C::LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) char lds[Layout<C>::TOTAL];
   __shared__ int item_sh;
-  Lds<C> S;
-  init_lds<C>(na, S, lds);
-  Frags<C> F;
-  load_frags<C>(na, F, threadIdx.x & 63);
+  init_lds<C>(na, lds);
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
@@ -732,7 +708,7 @@ __global__ __launch_bounds__(C::NT) void fwd_batched_kernel(FwdNetArgs na, Batch
     unsigned* z = reinterpret_cast<unsigned*>(lds);
     for (int e = threadIdx.x; e < (C::XS_BYTES + C::SP_BYTES) / 4; e += C::NT) z[e] = 0u;
     __syncthreads();
-    run_tile<C>(na, ca, tl, F, S);
+    run_tile<C>(na, ca, tl, lds);
   }
 }
 
@@ -740,7 +716,8 @@ __global__ __launch_bounds__(C::NT) void fwd_batched_kernel(FwdNetArgs na, Batch
 struct Variant {
   int nl, cin, ch, bf16, th, tw;
   const char* name;
-  void (*single)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
+  void (*single_fast)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
+  void (*single_full)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*batched)(const FwdNetArgs&, const BatchTable&, int32_t*, int, hipStream_t, hipError_t*);
 };
 
@@ -757,29 +734,35 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
   *err = hipGetLastError();
 }
 
-#define EVS_VARIANT(NL, CIN, CH, BF, TH, TW, NW, NAME)                                     \
-  Variant{NL, CIN, CH, BF, TH, TW, NAME, &launch_single<Cfg<NL, CIN, CH, (bool)BF, TH, TW, NW>>, \
-          &launch_batched<Cfg<NL, CIN, CH, (bool)BF, TH, TW, NW>>}
+#define EVS_CFG(NL, CIN, CH, BF, TH, TW, FULL) Cfg<NL, CIN, CH, (bool)BF, TH, TW, 8, FULL>
+// a tile variant: inference kernel + training/debug kernel (+ batched kernel)
+#define EVS_VARIANT(NL, CIN, CH, BF, TH, TW, NAME)                                  \
+  Variant{NL, CIN, CH, BF, TH, TW, NAME, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, false)>, \
+          &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, true)>, nullptr}
+#define EVS_VARIANT_B(NL, CIN, CH, BF, TH, TW, NAME)                                \
+  Variant{NL, CIN, CH, BF, TH, TW, NAME, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, false)>, \
+          &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, true)>,                   \
+          &launch_batched<EVS_CFG(NL, CIN, CH, BF, TH, TW, false)>}
 
 const Variant kVariants[] = {
     // single-layer nets (input -> output), f32
-    EVS_VARIANT(1, 1, 16, 0, 32, 32, 8, "L1 cin1 f32 32x32"),
-    EVS_VARIANT(1, 3, 16, 0, 32, 32, 8, "L1 cin3 f32 32x32"),
-    // two-layer nets cin -> hidden(<=16) -> out
-    EVS_VARIANT(2, 3, 16, 0, 30, 40, 8, "L2 h16 f32 30x40"),
-    EVS_VARIANT(2, 3, 16, 0, 16, 32, 8, "L2 h16 f32 16x32"),
-    EVS_VARIANT(2, 1, 16, 0, 30, 40, 8, "L2 cin1 h16 f32 30x40"),
-    EVS_VARIANT(2, 3, 16, 1, 30, 40, 8, "L2 h16 bf16 30x40"),
+    EVS_VARIANT(1, 1, 16, 0, 32, 32, "L1 cin1 f32 32x32"),
+    EVS_VARIANT(1, 3, 16, 0, 32, 32, "L1 cin3 f32 32x32"),
+    // two-layer nets cin -> hidden(<=16) -> out (first = default tile)
+    EVS_VARIANT(2, 3, 16, 0, 16, 32, "L2 h16 f32 16x32"),
+    EVS_VARIANT(2, 3, 16, 0, 30, 40, "L2 h16 f32 30x40"),
+    EVS_VARIANT(2, 1, 16, 0, 30, 40, "L2 cin1 h16 f32 30x40"),
+    EVS_VARIANT(2, 3, 16, 1, 30, 40, "L2 h16 bf16 30x40"),
     // two-layer nets with hidden width <= 32
-    EVS_VARIANT(2, 3, 32, 0, 24, 32, 8, "L2 h32 f32 24x32"),
-    EVS_VARIANT(2, 3, 32, 0, 16, 48, 8, "L2 h32 f32 16x48"),
-    EVS_VARIANT(2, 3, 32, 1, 30, 40, 8, "L2 h32 bf16 30x40"),
-    EVS_VARIANT(2, 3, 32, 1, 24, 32, 8, "L2 h32 bf16 24x32"),
+    EVS_VARIANT(2, 3, 32, 0, 24, 32, "L2 h32 f32 24x32"),
+    EVS_VARIANT(2, 3, 32, 0, 16, 48, "L2 h32 f32 16x48"),
+    EVS_VARIANT_B(2, 3, 32, 1, 24, 32, "L2 h32 bf16 24x32"),
+    EVS_VARIANT_B(2, 3, 32, 1, 30, 40, "L2 h32 bf16 30x40"),
     // three-layer nets
-    EVS_VARIANT(3, 3, 16, 0, 30, 40, 8, "L3 h16 f32 30x40"),
-    EVS_VARIANT(3, 3, 16, 0, 24, 32, 8, "L3 h16 f32 24x32"),
-    EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40"),
-    EVS_VARIANT(3, 3, 32, 1, 24, 32, 8, "L3 h32 bf16 24x32"),
+    EVS_VARIANT_B(3, 3, 16, 0, 24, 32, "L3 h16 f32 24x32"),
+    EVS_VARIANT(3, 3, 16, 0, 30, 40, "L3 h16 f32 30x40"),
+    EVS_VARIANT(3, 3, 16, 1, 30, 40, "L3 h16 bf16 30x40"),
+    EVS_VARIANT(3, 3, 32, 1, 24, 32, "L3 h32 bf16 24x32"),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -833,7 +816,8 @@ int launch_forward(const evs_net& net, const FwdNetArgs& na, const FwdClipArgs& 
   const Variant* v = find_variant(net, tile_id);
   if (!v) return fail(EVS_EUNSUPPORTED, "no compiled forward kernel for this network shape");
   hipError_t e = hipSuccess;
-  v->single(na, ca, stream, &e);
+  const bool full = ca.h_trace || ca.ckpt || na.relaxed || ca.s_fp32;
+  (full ? v->single_full : v->single_fast)(na, ca, stream, &e);
   if (e != hipSuccess) return hip_check(e, "forward kernel launch");
   return EVS_OK;
 }
@@ -842,6 +826,7 @@ int launch_forward_batched(const evs_net& net, const FwdNetArgs& na, const Batch
                            int32_t* counter, hipStream_t stream) {
   const Variant* v = find_variant(net, tile_id);
   if (!v) return fail(EVS_EUNSUPPORTED, "no compiled forward kernel for this network shape");
+  if (!v->batched) return fail(EVS_EUNSUPPORTED, "no batched kernel compiled for this tile variant");
   int dev = 0, ncu = 0;
   EVS_HIP(hipGetDevice(&dev));
   EVS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));

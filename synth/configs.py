@@ -64,21 +64,28 @@ WORKLOADS = {
 def make_clip(wl: Workload, device="cpu", t0: int = 0, T: int | None = None,
               y0: int = 0, x0: int = 0, H: int | None = None, W: int | None = None,
               spp: int | None = None, scene_seed: int | None = None,
-              noise_seed: int | None = None, clean: bool = False) -> torch.Tensor:
-    """Input window [T,3,H,W] float32 of workload ``wl`` at absolute offsets."""
+              noise_seed: int | None = None, clean: bool = False, out: torch.Tensor | None = None,
+              chunk_pixels: int = 1 << 24) -> torch.Tensor:
+    """Input window [T,3,H,W] float32 of workload ``wl`` at absolute offsets.
+
+    Frames are generated in chunks of about ``chunk_pixels`` pixels (bounded
+    temporaries) and written into ``out`` if given."""
     T = wl.T if T is None else T
     H = wl.H if H is None else H
     W = wl.W if W is None else W
     spp = wl.spp if spp is None else spp
     ss = wl.scene_seed if scene_seed is None else scene_seed
     ns = wl.noise_seed if noise_seed is None else noise_seed
-    if wl.scene == "disc":
-        c = moving_disc(T, H, W, t0=t0, y0=y0, x0=x0, device=device)
-    else:
-        c = textured_planes(T, H, W, seed=ss, t0=t0, y0=y0, x0=x0, device=device)
-    if clean:
-        return c
-    return spp_noise(c, spp, ns, t0=t0, y0=y0, x0=x0)
+    out = torch.empty(T, 3, H, W, dtype=torch.float32, device=device) if out is None else out
+    step = max(1, chunk_pixels // (H * W))
+    for c0 in range(0, T, step):
+        c1 = min(T, c0 + step)
+        if wl.scene == "disc":
+            c = moving_disc(c1 - c0, H, W, t0=t0 + c0, y0=y0, x0=x0, device=device)
+        else:
+            c = textured_planes(c1 - c0, H, W, seed=ss, t0=t0 + c0, y0=y0, x0=x0, device=device)
+        out[c0:c1] = c if clean else spp_noise(c, spp, ns, t0=t0 + c0, y0=y0, x0=x0)
+    return out
 
 
 def train_crops(wl: Workload, device="cpu", seed: int = 3, n: int | None = None):
