@@ -1,0 +1,154 @@
+// Bidirectional, polarity-split EMD loss with spike-count term and its
+// (sub)gradient (arXiv 2508.18071, Sec. 3.3, Eq. 7-11).
+//
+// One thread owns one (clip, pixel) and both polarity sequences over time.
+// With d_t = S_t - E_t, D_i = sum_{t<=i} d_t (prefix) and the suffix sums
+// R_m = D_{T-1} - D_{m-1}, the loss of a sequence is (1/2T) sum_i |D_i| + |R_i|
+// and its gradient is (1/2T) [ sum_{i>=j} sgn D_i + sum_{m<=j} sgn R_m ].
+// Three streaming passes over time (total, loss + suffix signs, gradient)
+// keep the per-thread state O(1) for any T; reads are coalesced across the
+// pixel dimension.  Per-thread losses are summed in a fixed order (block
+// tree, then one block over the partials), so the loss is reproducible.
+#include "evs_ops.hpp"
+
+namespace evs {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
+
+// S^k_t for k = 0 (ON) / 1 (OFF)
+__device__ inline float s_pol(const float* s, size_t off, int C, int k, size_t cstride) {
+  if (C == 2) return s[off + k * cstride];
+  const float v = s[off];
+  return k == 0 ? (v > 0.f ? v : 0.f) : (v < 0.f ? -v : 0.f);
+}
+
+__global__ __launch_bounds__(kThreads) void k_emd(const float* __restrict__ s, const int8_t* __restrict__ e,
+                                                 int N, int T, int C, int HW, float lambda,
+                                                 float* __restrict__ grad, double* __restrict__ partial) {
+  const long long gid = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long total_px = (long long)N * HW;
+  double loss = 0.0;
+  if (gid < total_px) {
+    const int n = (int)(gid / HW);
+    const int px = (int)(gid - (long long)n * HW);
+    const size_t sfr = (size_t)C * HW, efr = (size_t)2 * HW;
+    const size_t sbase = (size_t)n * T * sfr + px, ebase = (size_t)n * T * efr + px;
+    const float inv2t = 0.5f / (float)T;
+    // pass 1: totals per polarity and spike/target counts
+    float tot[2] = {0.f, 0.f};
+    float cnt_s = 0.f, cnt_e = 0.f;
+    for (int t = 0; t < T; ++t) {
+      for (int k = 0; k < 2; ++k) {
+        const float sv = s_pol(s, sbase + t * sfr, C, k, HW);
+        const float ev = (float)e[ebase + t * efr + k * HW];
+        tot[k] += sv - ev;
+        cnt_s += fabsf(sv);
+        cnt_e += ev;
+      }
+    }
+    const float cdiff = cnt_s - cnt_e;
+    // pass 2: loss and the total of sgn D (the gradient's reverse sums start there)
+    float D[2] = {0.f, 0.f};
+    float sumsgnD[2] = {0.f, 0.f};
+    double l = 0.0;
+    for (int t = 0; t < T; ++t) {
+      for (int k = 0; k < 2; ++k) {
+        const float sv = s_pol(s, sbase + t * sfr, C, k, HW);
+        const float ev = (float)e[ebase + t * efr + k * HW];
+        const float R = tot[k] - D[k];            // suffix sum from t
+        D[k] += sv - ev;
+        l += (double)fabsf(D[k]) + (double)fabsf(R);
+        sumsgnD[k] += sgnf(D[k]);
+      }
+    }
+    loss = l * (double)inv2t + (double)lambda * (double)fabsf(cdiff);
+    // pass 3: gradient
+    if (grad) {
+      const float lam_sg = lambda * sgnf(cdiff);
+      float Dp[2] = {0.f, 0.f};
+      float revD[2] = {sumsgnD[0], sumsgnD[1]};   // sum_{i>=t} sgn D_i
+      float fwdR[2] = {0.f, 0.f};                 // sum_{m<=t} sgn R_m
+      for (int t = 0; t < T; ++t) {
+        float g[2];
+        float sv[2];
+        for (int k = 0; k < 2; ++k) {
+          sv[k] = s_pol(s, sbase + t * sfr, C, k, HW);
+          const float ev = (float)e[ebase + t * efr + k * HW];
+          const float R = tot[k] - Dp[k];
+          fwdR[k] += sgnf(R);
+          g[k] = (revD[k] + fwdR[k]) * inv2t + lam_sg * sgnf(sv[k]);
+          Dp[k] += sv[k] - ev;
+          revD[k] -= sgnf(Dp[k]);
+        }
+        if (C == 2) {
+          grad[sbase + t * sfr] = g[0];
+          grad[sbase + t * sfr + HW] = g[1];
+        } else {
+          const float v = s[sbase + t * sfr];
+          // d/dS of the split parts: S+ = S [S>0], S- = -S [S<0]
+          grad[sbase + t * sfr] = v > 0.f ? g[0] : (v < 0.f ? -g[1] : 0.f);
+        }
+      }
+    }
+  }
+  // fixed-order block reduction
+  __shared__ double red[kThreads];
+  red[threadIdx.x] = loss;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int n, float* __restrict__ out) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  // each thread sums a contiguous run, then a fixed tree
+  const int per = (n + 1023) / 1024;
+  const int b = threadIdx.x * per;
+  for (int i = b; i < b + per && i < n; ++i) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)red[0];
+}
+
+}  // namespace
+
+size_t emd_workspace_bytes(int N, int T, int C, int H, int W) {
+  (void)T; (void)C;
+  const long long px = (long long)N * H * W;
+  const long long blocks = (px + kThreads - 1) / kThreads;
+  return align256((size_t)blocks * sizeof(double));
+}
+
+int emd_loss(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda,
+             float* loss, float* grad, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!s || !e || !loss) return fail(EVS_EINVAL, "emd_loss: s, e and loss must be non-NULL");
+  if (N < 1 || T < 1 || H < 1 || W < 1) return fail(EVS_EINVAL, "emd_loss: sizes must be >= 1");
+  if (C != 1 && C != 2) return fail(EVS_EUNSUPPORTED, "emd_loss: C must be 1 or 2");
+  if ((long long)H * W > (1LL << 30)) return fail(EVS_EOVERFLOW, "emd_loss: frame too large");
+  if (!(lambda >= 0.f)) return fail(EVS_EINVAL, "emd_loss: lambda must be >= 0");
+  const size_t need = emd_workspace_bytes(N, T, C, H, W);
+  if (!ws || ws_bytes < need) return fail(EVS_EWORKSPACE, "emd_loss: workspace too small");
+  const long long px = (long long)N * H * W;
+  const long long blocks = (px + kThreads - 1) / kThreads;
+  if (blocks > (1LL << 30)) return fail(EVS_EOVERFLOW, "emd_loss: too many pixels");
+  double* partial = reinterpret_cast<double*>(ws);
+  hipLaunchKernelGGL(k_emd, dim3((unsigned)blocks), dim3(kThreads), 0, st, s, e, N, T, C, H * W, lambda, grad,
+                     partial);
+  EVS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, (int)blocks, loss);
+  EVS_HIP(hipGetLastError());
+  return EVS_OK;
+}
+
+}  // namespace evs

@@ -2,13 +2,6 @@
 #include "evs_ops.hpp"
 
 namespace evs {
-size_t emd_workspace_bytes(int, int, int, int, int) { return 0; }
-int emd_loss(const float*, const int8_t*, int, int, int, int, int, float, float*, float*, void*, size_t,
-             hipStream_t) { return fail(EVS_EUNSUPPORTED, "not implemented"); }
-size_t compact_workspace_bytes(int, int, int, int) { return 0; }
-int compact_events(const int8_t*, int, int, int, int, uint64_t*, int64_t, int64_t*, void*, size_t, hipStream_t) {
-  return fail(EVS_EUNSUPPORTED, "not implemented");
-}
 size_t backward_workspace_bytes(const evs_net&, const evs_clip&, int) { return 0; }
 int backward(const evs_net&, const void*, const evs_clip&, const float*, int, const float*, float* const*, float*,
              float*, void*, size_t, hipStream_t) { return fail(EVS_EUNSUPPORTED, "not implemented"); }
