@@ -144,7 +144,7 @@ int evs_pack_weights(const evs_net* net, const float* const* w, void* packed, vo
 
 /* Forward pass (Sec. 3.3, Eq. 2-3 with 3x3 convolution layers).
  *   clips, n_clips  host array of clip descriptors.  n_clips = 1 runs the
- *           single-clip kernel over N x tiles.  n_clips > 1 (at most 64)
+ *           single-clip kernel over N x tiles.  n_clips > 1 (at most 24)
  *           runs the persistent batched kernel: (clip, tile) work items in
  *           longest-first order are taken from a device counter in `ws`.
  *   ckpt    NULL, or (n_clips = 1 only) [N][ceil(T/ckpt_every)][sum C][H][W]

@@ -192,7 +192,7 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
   if (st) return st;
   if (!packed) return fail(EVS_EINVAL, "packed weights are NULL");
   if (!clips || n_clips < 1 || n_clips > kMaxBatchClips)
-    return fail(EVS_EINVAL, "n_clips must be 1..32");
+    return fail(EVS_EINVAL, "n_clips must be 1..24");
   for (int i = 0; i < n_clips; ++i)
     if ((st = validate_clip(*net, clips[i], true))) return st;
   if (ckpt && (ckpt_every < 1 || n_clips != 1)) return fail(EVS_EINVAL, "ckpt needs ckpt_every >= 1 and one clip");
@@ -215,6 +215,10 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
     ca.N = c.N; ca.T = c.T; ca.H = c.H; ca.W = c.W;
     ca.tiles_x = (c.W + tw - 1) / tw;
     ca.tiles_y = (c.H + th - 1) / th;
+    const int64_t HW = (int64_t)c.H * c.W;
+    ca.x_nstride = (int64_t)c.T * net->ch[0] * HW;
+    ca.vin_nstride = (int64_t)sumc * HW;
+    ca.trace_nstride = (int64_t)c.T * sumc * HW;
     if (c.v_state) {
       // the initial state is read from a private copy so that workgroups
       // writing the final state cannot race with halo reads of the initial one

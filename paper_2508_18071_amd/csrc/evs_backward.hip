@@ -1,0 +1,404 @@
+// Surrogate-gradient BPTT backward of EvSNet (arXiv 2508.18071, Sec. 3.3,
+// Eq. 4), with membrane checkpoints every k frames.
+//
+// Segments of k frames are visited from the last to the first.  For each:
+//   1. the forward kernel recomputes the segment's charged potentials h of
+//      every layer from the segment's checkpoint (bit-identical to the
+//      original forward: same kernel, same state);
+//   2. for layers L..1: a reverse-time adjoint scan per neuron
+//          g_h = (G - theta g_v) psi(h) + g_v     (G psi(h) + g_v detached)
+//          g_v <- leak * g_h
+//      with g_v carried across segment boundaries;
+//   3. the weight gradient dW[co][ci][tap] = sum_t,p g_h[co][p] s_in[ci][p+tap]
+//      as per-tile partial sums in registers, reduced in a fixed order (no
+//      float atomics: results are bitwise reproducible);
+//   4. the incoming gradient of the layer below, G = conv_transpose(g_h, W)
+//      (grad_x for layer 1).
+// Spikes fed to dW are recomputed from h with the forward's own device
+// function, so they equal the forward's spikes bit for bit.
+#include "evs_device.hpp"
+#include "evs_ops.hpp"
+
+namespace evs {
+namespace {
+
+constexpr int TT = 16;            // pixel tile edge of the conv kernels
+constexpr int NTH = TT * TT;      // threads per workgroup
+
+inline int pad_in(int c) { return c <= 4 ? 4 : (c <= 16 ? 16 : 32); }
+inline int pad_out(int c) { return c <= 2 ? 2 : (c <= 16 ? 16 : 32); }
+
+__device__ inline float wq(const float* w, int idx, bool bf) {
+  const float v = w[idx];
+  return bf ? round_bf16(v) : v;
+}
+
+// ---------------------------------------------------------------- adjoint scan
+__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ hseg, int sumc, int choff, int C,
+                                                 int len, int N, int HW, const float* __restrict__ G,
+                                                 long long G_nstride, long long G_tstride,
+                                                 float* __restrict__ gh, float* __restrict__ gv, float theta,
+                                                 float leak, float alpha, int detach) {
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long total = (long long)N * C * HW;
+  if (idx >= total) return;
+  const int p = (int)(idx % HW);
+  const int c = (int)((idx / HW) % C);
+  const int n = (int)(idx / ((long long)HW * C));
+  float* gvp = gv + ((size_t)n * sumc + choff + c) * HW + p;
+  float g_v = *gvp;
+  for (int t = len - 1; t >= 0; --t) {
+    const float h = hseg[(((size_t)n * len + t) * sumc + choff + c) * HW + p];
+    const float Gv = G[(size_t)n * G_nstride + (size_t)t * G_tstride + (size_t)c * HW + p];
+    const float psi = surrogate(h, theta, alpha);
+    const float g_h = detach ? fmaf(Gv, psi, g_v) : fmaf(fmaf(-theta, g_v, Gv), psi, g_v);
+    gh[(((size_t)n * len + t) * C + c) * HW + p] = g_h;
+    g_v = leak * g_h;
+  }
+  *gvp = g_v;
+}
+
+// ---------------------------------------------------------------- conv transpose
+// out[n][t][ci][y][x] = sum_{co,tap} W[co][ci][tap] * gh[n][t][co][y-dy][x-dx]
+template <int CINP, int COUTP>
+__global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int Cout, int Cin, int len,
+                                               int H, int W, int tiles_x, const float* __restrict__ w, int bf,
+                                               float* __restrict__ out, long long out_nstride,
+                                               long long out_tstride) {
+  __shared__ float ghs[COUTP][TT + 2][TT + 2];
+  __shared__ __attribute__((aligned(16))) float wls[9][COUTP][CINP];
+  const int tile = blockIdx.x, t = blockIdx.y, n = blockIdx.z;
+  const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
+  const int HW = H * W;
+  const float* g = gh + ((size_t)n * len + t) * Cout * HW;
+  for (int e = threadIdx.x; e < COUTP * (TT + 2) * (TT + 2); e += NTH) {
+    const int co = e / ((TT + 2) * (TT + 2)), r = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+    const int y = ty0 - 1 + r, x = tx0 - 1 + cc;
+    ghs[co][r][cc] = (co < Cout && y >= 0 && y < H && x >= 0 && x < W) ? g[(size_t)co * HW + y * W + x] : 0.f;
+  }
+  for (int e = threadIdx.x; e < 9 * COUTP * CINP; e += NTH) {
+    const int ci = e % CINP, co = (e / CINP) % COUTP, tap = e / (CINP * COUTP);
+    wls[tap][co][ci] = (co < Cout && ci < Cin) ? wq(w, (co * Cin + ci) * 9 + tap, bf) : 0.f;
+  }
+  __syncthreads();
+  const int ty = threadIdx.x / TT, tx = threadIdx.x % TT;
+  float acc[CINP];
+#pragma unroll
+  for (int ci = 0; ci < CINP; ++ci) acc[ci] = 0.f;
+  for (int co = 0; co < Cout; ++co) {
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const float gv = ghs[co][ty + 1 - dy][tx + 1 - dx];
+#pragma unroll
+      for (int ci = 0; ci < CINP; ++ci) acc[ci] = fmaf(wls[tap][co][ci], gv, acc[ci]);
+    }
+  }
+  const int y = ty0 + ty, x = tx0 + tx;
+  if (y < H && x < W) {
+    float* o = out + (size_t)n * out_nstride + (size_t)t * out_tstride + (size_t)y * W + x;
+#pragma unroll
+    for (int ci = 0; ci < CINP; ++ci)
+      if (ci < Cin) o[(size_t)ci * HW] = acc[ci];
+  }
+}
+
+// ---------------------------------------------------------------- weight gradient
+// Per (tile, clip) workgroup over all frames of the segment: partial
+// dW[co][ci][tap] in registers; s_in is x (layer 1) or the spikes of the
+// layer below recomputed from its h.
+template <int CINP, int COUTP>
+__global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+                                            int W, int tiles_x, const float* __restrict__ x,
+                                            long long x_nstride, int bf_x, const float* __restrict__ hseg,
+                                            int sumc, int choff_in, float theta, float alpha, int relaxed,
+                                            float* __restrict__ partial) {
+  constexpr int P = CINP * COUTP;                     // (co, ci) pairs
+  constexpr int PPT = P >= NTH ? P / NTH : 1;         // pairs per thread
+  constexpr int TPP = P >= NTH ? 1 : NTH / P;         // threads per pair
+  __shared__ float ghs[COUTP][TT * TT];
+  __shared__ float ss[CINP][TT + 2][TT + 2];
+  __shared__ float red[TPP > 1 ? NTH * 9 : 1];
+  const int tile = blockIdx.x, n = blockIdx.y;
+  const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
+  const int HW = H * W;
+  float acc[PPT][9];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) acc[k][tap] = 0.f;
+  const int sub = TPP > 1 ? threadIdx.x / P : 0;      // pixel subset of this thread
+  for (int t = 0; t < len; ++t) {
+    __syncthreads();
+    const float* g = gh + ((size_t)n * len + t) * Cout * HW;
+    for (int e = threadIdx.x; e < COUTP * TT * TT; e += NTH) {
+      const int co = e / (TT * TT), r = (e / TT) % TT, cc = e % TT;
+      const int y = ty0 + r, xx = tx0 + cc;
+      ghs[co][r * TT + cc] = (co < Cout && y < H && xx < W) ? g[(size_t)co * HW + y * W + xx] : 0.f;
+    }
+    for (int e = threadIdx.x; e < CINP * (TT + 2) * (TT + 2); e += NTH) {
+      const int ci = e / ((TT + 2) * (TT + 2)), r = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+      const int y = ty0 - 1 + r, xx = tx0 - 1 + cc;
+      float v = 0.f;
+      if (ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W) {
+        if (hseg) {
+          const float h = hseg[(((size_t)n * len + t) * sumc + choff_in + ci) * HW + (size_t)y * W + xx];
+          v = spike_of(h, theta, alpha, relaxed != 0);
+        } else {
+          v = x[(size_t)n * x_nstride + ((size_t)t * Cin + ci) * HW + (size_t)y * W + xx];
+          if (bf_x) v = round_bf16(v);
+        }
+      }
+      ss[ci][r][cc] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int pr = (TPP > 1 ? threadIdx.x % P : threadIdx.x + NTH * k);
+      const int co = pr / CINP, ci = pr % CINP;
+      for (int p = sub; p < TT * TT; p += TPP) {
+        const float gvv = ghs[co][p];
+        const int py = p / TT, px = p % TT;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+          acc[k][tap] = fmaf(gvv, ss[ci][py + tap / 3][px + tap % 3], acc[k][tap]);
+      }
+    }
+  }
+  float* out = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * P * 9;
+  if constexpr (TPP > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) red[threadIdx.x * 9 + tap] = acc[0][tap];
+    __syncthreads();
+    if (threadIdx.x < P) {
+      for (int tap = 0; tap < 9; ++tap) {
+        float sacc = 0.f;
+        for (int s2 = 0; s2 < TPP; ++s2) sacc += red[(s2 * P + threadIdx.x) * 9 + tap];
+        out[threadIdx.x * 9 + tap] = sacc;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) out[(threadIdx.x + NTH * k) * 9 + tap] = acc[k][tap];
+  }
+}
+
+// acc[e] += sum_b partial[b][e] in block order (e over padded pairs x 9)
+__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ partial, int nblocks, int E,
+                                                   float* __restrict__ acc) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= E) return;
+  float s = 0.f;
+  for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * E + e];
+  acc[e] += s;
+}
+
+// grad_w[co][ci][tap] (real layout) from the padded accumulator
+__global__ void k_dw_out(const float* __restrict__ acc, int Cout, int Cin, int CINP, float* __restrict__ gw) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= Cout * Cin * 9) return;
+  const int tap = e % 9, ci = (e / 9) % Cin, co = e / (9 * Cin);
+  gw[e] = acc[(co * CINP + ci) * 9 + tap];
+}
+
+template <int CINP, int COUTP>
+void launch_convT(dim3 g, hipStream_t st, const float* gh, int Cout, int Cin, int len, int H, int W, int tx,
+                  const float* w, int bf, float* out, long long ons, long long ots) {
+  hipLaunchKernelGGL((k_convT<CINP, COUTP>), g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, w, bf, out, ons,
+                     ots);
+}
+template <int CINP, int COUTP>
+void launch_dw(dim3 g, hipStream_t st, const float* gh, int Cout, int Cin, int len, int H, int W, int tx,
+               const float* x, long long xns, int bfx, const float* hseg, int sumc, int choff_in, float theta,
+               float alpha, int relaxed, float* partial) {
+  hipLaunchKernelGGL((k_dw<CINP, COUTP>), g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, x, xns, bfx, hseg,
+                     sumc, choff_in, theta, alpha, relaxed, partial);
+}
+
+#define EVS_DISPATCH_PAD(CI, CO, CALL)                                   \
+  do {                                                                   \
+    if (CI == 4 && CO == 2) CALL(4, 2);                                  \
+    else if (CI == 4 && CO == 16) CALL(4, 16);                           \
+    else if (CI == 4 && CO == 32) CALL(4, 32);                           \
+    else if (CI == 16 && CO == 2) CALL(16, 2);                           \
+    else if (CI == 16 && CO == 16) CALL(16, 16);                         \
+    else if (CI == 16 && CO == 32) CALL(16, 32);                         \
+    else if (CI == 32 && CO == 2) CALL(32, 2);                           \
+    else if (CI == 32 && CO == 16) CALL(32, 16);                         \
+    else CALL(32, 32);                                                   \
+  } while (0)
+
+struct BwdLayout {
+  size_t hseg, gv, gh, ga, gb, partial, acc, total;
+  int k, nseg, cmax, tiles_x, tiles_y;
+};
+
+BwdLayout layout(const evs_net& net, const evs_clip& c, int k) {
+  BwdLayout L{};
+  const size_t HW = (size_t)c.H * c.W;
+  const int sumc = real_sum_channels(net);
+  int cmax = 0, emax = 0, accsum = 0;
+  for (int l = 1; l <= net.n_layers; ++l) {
+    cmax = net.ch[l] > cmax ? net.ch[l] : cmax;
+    const int e = pad_in(net.ch[l - 1]) * pad_out(net.ch[l]) * 9;
+    emax = e > emax ? e : emax;
+    accsum += e;
+  }
+  L.k = k;
+  L.nseg = (c.T + k - 1) / k;
+  L.cmax = cmax;
+  L.tiles_x = (c.W + TT - 1) / TT;
+  L.tiles_y = (c.H + TT - 1) / TT;
+  const size_t nblk = (size_t)L.tiles_x * L.tiles_y * c.N;
+  size_t o = 0;
+  L.hseg = o; o += align256((size_t)c.N * k * sumc * HW * 4);
+  L.gv = o; o += align256((size_t)c.N * sumc * HW * 4);
+  L.gh = o; o += align256((size_t)c.N * k * cmax * HW * 4);
+  L.ga = o; o += align256((size_t)c.N * k * cmax * HW * 4);
+  L.gb = o; o += align256((size_t)c.N * k * cmax * HW * 4);
+  L.partial = o; o += align256(nblk * emax * 4);
+  L.acc = o; o += align256((size_t)accsum * 4);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+size_t backward_workspace_bytes(const evs_net& net, const evs_clip& clip, int ckpt_every) {
+  if (validate_clip(net, clip, false) != EVS_OK || ckpt_every < 1) return (size_t)-1;
+  return layout(net, clip, ckpt_every < clip.T ? ckpt_every : clip.T).total;
+}
+
+int backward(const evs_net& net, const void* packed, const evs_clip& clip, const float* ckpt, int ckpt_every,
+             const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v, void* ws, size_t ws_bytes,
+             hipStream_t st) {
+  int rc = validate_net(&net);
+  if (rc) return rc;
+  if ((rc = validate_clip(net, clip, true))) return rc;
+  if (!packed || !ckpt || !grad_s || !grad_w) return fail(EVS_EINVAL, "backward: NULL argument");
+  if (ckpt_every < 1) return fail(EVS_EINVAL, "backward: ckpt_every must be >= 1");
+  for (int l = 0; l < net.n_layers; ++l)
+    if (!grad_w[l]) return fail(EVS_EINVAL, "backward: NULL grad_w entry");
+  const int k = ckpt_every < clip.T ? ckpt_every : clip.T;
+  const BwdLayout Lo = layout(net, clip, k);
+  if (!ws || ws_bytes < Lo.total) return fail(EVS_EWORKSPACE, "backward: workspace too small");
+  // the checkpoints were written with ceil(T / ckpt_every) segments
+  const int nseg_ck = (clip.T + ckpt_every - 1) / ckpt_every;
+  char* w8 = reinterpret_cast<char*>(ws);
+  float* hseg = reinterpret_cast<float*>(w8 + Lo.hseg);
+  float* gv = reinterpret_cast<float*>(w8 + Lo.gv);
+  float* gh = reinterpret_cast<float*>(w8 + Lo.gh);
+  float* Gbuf[2] = {reinterpret_cast<float*>(w8 + Lo.ga), reinterpret_cast<float*>(w8 + Lo.gb)};
+  float* partial = reinterpret_cast<float*>(w8 + Lo.partial);
+  float* acc = reinterpret_cast<float*>(w8 + Lo.acc);
+  const int N = clip.N, T = clip.T, H = clip.H, W = clip.W, L = net.n_layers;
+  const long long HW = (long long)H * W;
+  const int sumc = real_sum_channels(net);
+  const int cin0 = net.ch[0], cout = net.ch[L];
+  const bool bf = net.precision == EVS_BF16;
+  const FwdNetArgs na = make_net_args(net, packed);
+  const float* wbase = reinterpret_cast<const float*>(packed);
+  int choff[4] = {0, 0, 0, 0};
+  for (int l = 1; l < L; ++l) choff[l] = choff[l - 1] + net.ch[l];   // choff[l-1] = offset of layer l
+  int accofs[4] = {0, 0, 0, 0};
+  for (int l = 1; l <= L; ++l) accofs[l] = accofs[l - 1] + pad_in(net.ch[l - 1]) * pad_out(net.ch[l]) * 9;
+
+  if ((rc = zero_f32(gv, (size_t)N * sumc * HW, st))) return rc;
+  if ((rc = zero_f32(acc, (size_t)accofs[L], st))) return rc;
+  const int tile = choose_tile(net, H, W);
+  int th = 0, tw = 0;
+  forward_tile_dims(net, tile, &th, &tw);
+  if (th == 0) return fail(EVS_EUNSUPPORTED, "backward: no forward kernel for this network");
+  const dim3 gconv((unsigned)(Lo.tiles_x * Lo.tiles_y), 1, (unsigned)N);
+
+  for (int s = Lo.nseg - 1; s >= 0; --s) {
+    const int t0 = s * k;
+    const int len = (t0 + k <= T ? k : T - t0);
+    // 1. recompute the segment's potentials from its checkpoint
+    FwdClipArgs ca{};
+    ca.x = clip.x + (size_t)t0 * cin0 * HW;
+    ca.x_nstride = (long long)T * cin0 * HW;
+    // checkpoint index: the forward stored one state every ckpt_every frames
+    if (t0 % ckpt_every != 0) return fail(EVS_EINVAL, "backward: segment start is not a checkpoint");
+    ca.v_in = ckpt + (size_t)(t0 / ckpt_every) * sumc * HW;
+    ca.vin_nstride = (long long)nseg_ck * sumc * HW;
+    ca.h_trace = hseg;
+    ca.trace_nstride = (long long)len * sumc * HW;
+    ca.N = N; ca.T = len; ca.H = H; ca.W = W;
+    ca.tiles_x = (W + tw - 1) / tw;
+    ca.tiles_y = (H + th - 1) / th;
+    if ((rc = launch_forward(net, na, ca, tile, st))) return rc;
+
+    // 2-4. layers L..1
+    const float* G = grad_s + (size_t)t0 * cout * HW;
+    long long G_ns = (long long)T * cout * HW, G_ts = (long long)cout * HW;
+    int gsel = 0;
+    for (int l = L; l >= 1; --l) {
+      const int C = net.ch[l], Cin = net.ch[l - 1];
+      const long long tot = (long long)N * C * HW;
+      hipLaunchKernelGGL(k_adjoint, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, hseg, sumc,
+                         choff[l - 1], C, len, N, (int)HW, G, G_ns, G_ts, gh, gv, net.theta, net.leak,
+                         net.surr_alpha, net.detach_reset);
+      EVS_HIP(hipGetLastError());
+      // weight gradient partials for this segment, then fixed-order reduction
+      const int CI = pad_in(Cin), CO = pad_out(C);
+      const dim3 gdw((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)N);
+      const float* hin = l >= 2 ? hseg : nullptr;
+      const int choff_in = l >= 2 ? choff[l - 2] : 0;
+#define EVS_CALL_DW(A, B)                                                                              \
+  launch_dw<A, B>(gdw, st, gh, C, Cin, len, H, W, Lo.tiles_x, clip.x + (size_t)t0 * cin0 * HW,          \
+                  (long long)T * cin0 * HW, bf ? 1 : 0, hin, sumc, choff_in, net.theta, net.surr_alpha, \
+                  net.relaxed, partial)
+      EVS_DISPATCH_PAD(CI, CO, EVS_CALL_DW);
+#undef EVS_CALL_DW
+      EVS_HIP(hipGetLastError());
+      const int E = CI * CO * 9;
+      hipLaunchKernelGGL(k_dw_reduce, dim3((E + 255) / 256), dim3(256), 0, st, partial,
+                         Lo.tiles_x * Lo.tiles_y * N, E, acc + accofs[l - 1]);
+      EVS_HIP(hipGetLastError());
+      // gradient for the layer below (or the input)
+      if (l >= 2 || grad_x) {
+        float* out;
+        long long ons, ots;
+        if (l >= 2) {
+          out = Gbuf[gsel];
+          ons = (long long)len * Cin * HW;
+          ots = (long long)Cin * HW;
+        } else {
+          out = grad_x + (size_t)t0 * cin0 * HW;
+          ons = (long long)T * cin0 * HW;
+          ots = (long long)cin0 * HW;
+        }
+        const dim3 gct((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)len, (unsigned)N);
+        const float* wl = wbase + na.wofs[l - 1];
+#define EVS_CALL_CT(A, B) launch_convT<A, B>(gct, st, gh, C, Cin, len, H, W, Lo.tiles_x, wl, bf ? 1 : 0, out, ons, ots)
+        EVS_DISPATCH_PAD(CI, CO, EVS_CALL_CT);
+#undef EVS_CALL_CT
+        EVS_HIP(hipGetLastError());
+        if (l >= 2) {
+          G = out;
+          G_ns = ons;
+          G_ts = ots;
+          gsel ^= 1;
+        }
+      }
+    }
+  }
+  // outputs
+  for (int l = 1; l <= L; ++l) {
+    const int E = net.ch[l] * net.ch[l - 1] * 9;
+    hipLaunchKernelGGL(k_dw_out, dim3((E + 255) / 256), dim3(256), 0, st, acc + accofs[l - 1], net.ch[l],
+                       net.ch[l - 1], pad_in(net.ch[l - 1]), grad_w[l - 1]);
+    EVS_HIP(hipGetLastError());
+  }
+  if (grad_v) {
+    if ((rc = copy_f32(grad_v, gv, (size_t)N * sumc * HW, st))) return rc;
+  }
+  (void)gconv;
+  return EVS_OK;
+}
+
+}  // namespace evs

@@ -1,11 +1,6 @@
-// Temporary placeholders for operations not yet implemented.
+// extern "C" entry points of the non-forward operations (declared in
+// include/evs.h); each forwards to its implementation file.
 #include "evs_ops.hpp"
-
-namespace evs {
-size_t backward_workspace_bytes(const evs_net&, const evs_clip&, int) { return 0; }
-int backward(const evs_net&, const void*, const evs_clip&, const float*, int, const float*, float* const*, float*,
-             float*, void*, size_t, hipStream_t) { return fail(EVS_EUNSUPPORTED, "not implemented"); }
-}  // namespace evs
 
 extern "C" {
 int evs_backward(const evs_net* net, const void* packed, const evs_clip* clip, const float* ckpt, int32_t k,

@@ -22,6 +22,7 @@
 //   * Only the HBM traffic of the algorithm remains: x in (12 B/px/frame)
 //     and the output spikes (int8).
 #include "evs_internal.hpp"
+#include "evs_device.hpp"
 
 namespace evs {
 namespace {
@@ -76,21 +77,6 @@ __device__ inline f4 mfma_bf16(u4 a, u4 b, f4 c) {
                                                  __builtin_bit_cast(bf8, b), c, 0, 0, 0);
 }
 
-__device__ inline float sigm(float z) { return __frcp_rn(1.0f + __expf(-z)); }
-
-// BiLIF fire + reset (Eq. 2-3): returns the spike, updates v in place (v
-// holds the charged potential h on entry).
-__device__ inline float bilif(float& v, float theta, float alpha, bool relaxed) {
-  const float h = v;
-  float s;
-  if (relaxed) {
-    s = sigm(alpha * (h - theta)) - sigm(alpha * (-h - theta));
-  } else {
-    s = h >= theta ? 1.0f : (h <= -theta ? -1.0f : 0.0f);
-  }
-  v = fmaf(-theta, s, h);
-  return s;
-}
 
 __device__ inline unsigned pack_bf16x2(float lo, float hi) {
   // spikes are exactly representable: take the upper halves of the floats
@@ -351,7 +337,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   f4 st1[C::NB1][C::MB];
   f4 st2[C::NB2][C::MB];
   float so[C::NOUT][2];
-  const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * sumc * HW : nullptr;
+  const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * ca.vin_nstride : nullptr;
   if constexpr (C::NH >= 1) read_hidden_state<C, C::NB1>(st1, vm1, 1, wave, j, g, vin, c1, 0, gy0, gx0, W, HW);
   if constexpr (C::NH >= 2) read_hidden_state<C, C::NB2>(st2, vm2, 2, wave, j, g, vin, c2, choff2, gy0, gx0, W, HW);
 #pragma unroll
@@ -367,7 +353,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   }
 
   // ---- x staging (register prefetch of the next frame)
-  const float* xclip = ca.x + (size_t)tl.n * T * C::CIN * HW;
+  const float* xclip = ca.x + (size_t)tl.n * ca.x_nstride;
   float xpf[C::XPF];
 #define EVS_LOAD_X(tt)                                                                          \
   do {                                                                                          \
@@ -424,7 +410,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     if constexpr (C::FULL) {
       if (ca.ckpt && (t % ca.ckpt_every) == 0)
         write_state(ca.ckpt + ((size_t)tl.n * nseg + t / ca.ckpt_every) * sumc * HW);
-      trace_t = ca.h_trace ? ca.h_trace + ((size_t)tl.n * T + t) * sumc * HW : nullptr;
+      trace_t = ca.h_trace ? ca.h_trace + (size_t)tl.n * ca.trace_nstride + (size_t)t * sumc * HW : nullptr;
     }
 
     if constexpr (C::NH >= 1) {

@@ -63,6 +63,8 @@ struct FwdClipArgs {
   int32_t s_fp32;
   int32_t ckpt_every;
   int32_t tiles_x, tiles_y;
+  // element strides between the clips of a batch (x, initial state, trace)
+  int64_t x_nstride, vin_nstride, trace_nstride;
 };
 
 struct FwdNetArgs {
@@ -76,7 +78,7 @@ struct FwdNetArgs {
 };
 
 // Batched (persistent) launch: a clip table passed by value.
-constexpr int kMaxBatchClips = 64;
+constexpr int kMaxBatchClips = 24;
 struct BatchTable {
   int32_t n_clips;
   int32_t n_items;                   // total (clip, tile) items
