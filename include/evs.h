@@ -59,7 +59,7 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
 
 /* Network description (host struct, read during the call only).
  *   n_layers   L in 1..3
- *   ch[0]      input channels Cin in 1..4 (3 for RGB)
+ *   ch[0]      input channels Cin: 3 (RGB) or 1
  *   ch[1..L-1] hidden widths, each in 1..32 (all hidden layers equal);
  *              widths are padded internally to 16 or 32 with zero weights
  *   ch[L]      output channels in 1..2.  With two outputs, channel 0 is the
@@ -216,6 +216,18 @@ const char* evs_tile_name(const evs_net* net, int32_t tile_id);
 
 /* Force a tile variant for later calls with `net` (-1 = automatic).      */
 int evs_set_tile(const evs_net* net, int32_t tile_id);
+
+/* hipGraph capture helpers.  evs_graph_begin starts capturing `stream`
+ * (must not be the NULL stream); every capture-safe call enqueued on it
+ * (evs_forward, evs_backward, evs_emd_loss, evs_compact_events) is recorded
+ * instead of run.  evs_graph_end stops the capture and instantiates the
+ * graph into *graph_exec (an opaque hipGraphExec_t owned by the caller);
+ * evs_graph_launch replays it on a stream; evs_graph_destroy frees it.
+ * A replay reuses the device pointers that were captured.                */
+int evs_graph_begin(void* stream);
+int evs_graph_end(void* stream, void** graph_exec);
+int evs_graph_launch(void* graph_exec, void* stream);
+int evs_graph_destroy(void* graph_exec);
 
 /* Static strings. */
 const char* evs_status_str(int status);

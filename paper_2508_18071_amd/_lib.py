@@ -66,6 +66,10 @@ _SIGS = [
     ("evs_tile_count", ctypes.c_int32, [ctypes.POINTER(EvsNet)]),
     ("evs_tile_name", ctypes.c_char_p, [ctypes.POINTER(EvsNet), ctypes.c_int32]),
     ("evs_set_tile", ctypes.c_int, [ctypes.POINTER(EvsNet), ctypes.c_int32]),
+    ("evs_graph_begin", ctypes.c_int, [_P]),
+    ("evs_graph_end", ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    ("evs_graph_launch", ctypes.c_int, [_P, _P]),
+    ("evs_graph_destroy", ctypes.c_int, [_P]),
     ("evs_status_str", ctypes.c_char_p, [ctypes.c_int]),
     ("evs_last_error", ctypes.c_char_p, []),
     ("evs_version", ctypes.c_char_p, []),

@@ -112,12 +112,14 @@ def workspace(net: Net, clips, op=_lib.EVS_OP_FORWARD, ckpt_every=0, device=None
 
 def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = False,
             v_state: torch.Tensor | None = None, trace: bool = False, ckpt_every: int = 0,
-            out: torch.Tensor | None = None, stream=None):
+            out: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None):
     """Run the network over x [N,T,Cin,H,W] (float32, on the GPU).
 
     Returns a dict: "s" [N,T,Cout,H,W] (int8 or float32), "h" (the charged
     potentials of all layers [N,T,sumC,H,W], if trace), "ckpt" (if
     ckpt_every > 0).  v_state [N,sumC,H,W] is read and overwritten in place.
+    ``ws`` is an optional preallocated workspace (needed under graph capture,
+    where nothing may be allocated).
     """
     if x.dim() == 4:
         x = x.unsqueeze(0)
@@ -137,7 +139,10 @@ def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = F
         nseg = (T + ckpt_every - 1) // ckpt_every
         ck = torch.empty(N, nseg, net.sum_c, H, W, dtype=torch.float32, device=dev)
     c = _clip(x, out, s_fp32, v_state, h)
-    ws, nb = workspace(net, [c], device=dev)
+    if ws is None:
+        ws, nb = workspace(net, [c], device=dev)
+    else:
+        nb = ws.numel()
     cn = net.c()
     check(lib().evs_forward(ctypes.byref(cn), packed.data_ptr(), ctypes.byref(c), 1,
                             ck.data_ptr() if ck is not None else None, ckpt_every,
@@ -244,3 +249,48 @@ def backward(net: Net, packed, x, ckpt, ckpt_every, grad_s, want_dx=False, want_
                              dv.data_ptr() if dv is not None else None, ws.data_ptr(), nb, _stream(stream)),
           "backward")
     return gws, dx, dv
+
+
+class Graph:
+    """A captured sequence of library calls, replayable with one launch.
+
+    Usage::
+
+        g = Graph(stream)            # a non-default torch.cuda.Stream
+        with g.capture():
+            forward_batched(..., stream=stream)
+        g.replay()
+    """
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.exec = None
+
+    def capture(self):
+        g = self
+
+        class _Ctx:
+            def __enter__(self_inner):
+                check(lib().evs_graph_begin(ctypes.c_void_p(g.stream.cuda_stream)), "graph_begin")
+                return g
+
+            def __exit__(self_inner, et, ev, tb):
+                h = ctypes.c_void_p()
+                st = lib().evs_graph_end(ctypes.c_void_p(g.stream.cuda_stream), ctypes.byref(h))
+                if et is None:
+                    check(st, "graph_end")
+                    g.exec = h
+                return False
+
+        return _Ctx()
+
+    def replay(self, stream=None):
+        s = self.stream if stream is None else stream
+        check(lib().evs_graph_launch(self.exec, ctypes.c_void_p(s.cuda_stream)), "graph_launch")
+
+    def __del__(self):
+        try:
+            if self.exec is not None:
+                lib().evs_graph_destroy(self.exec)
+        except Exception:
+            pass

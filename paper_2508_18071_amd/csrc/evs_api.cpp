@@ -70,6 +70,7 @@ std::tuple<int, int, int, int, int, int, int, int> shape_key(const evs_net& n, i
 }  // namespace
 
 int choose_tile(const evs_net& net, int H, int W) {
+  load_tile_cache_once();
   std::lock_guard<std::mutex> lk(g_tile_mu);
   auto f = g_forced.find(net_key(net));
   if (f != g_forced.end() && f->second >= 0) return f->second;
@@ -245,7 +246,12 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
   int big = 0;
   for (int i = 1; i < n_clips; ++i)
     if ((double)clips[i].H * clips[i].W > (double)clips[big].H * clips[big].W) big = i;
-  const int tile = choose_tile(*net, clips[big].H, clips[big].W);
+  const int tile = forward_batched_tile(*net, choose_tile(*net, clips[big].H, clips[big].W));
+  if (tile < 0) return fail(EVS_EUNSUPPORTED, "no batched kernel compiled for this network");
+  if (net->relaxed) return fail(EVS_EUNSUPPORTED, "batched forward: relaxed spikes not supported");
+  for (int i = 0; i < n_clips; ++i)
+    if (clips[i].s_fp32 || clips[i].h_trace)
+      return fail(EVS_EUNSUPPORTED, "batched forward: int8 spikes only, no traces");
   // longest-first order of clips: the work per tile is proportional to T
   int order[kMaxBatchClips];
   for (int i = 0; i < n_clips; ++i) order[i] = i;

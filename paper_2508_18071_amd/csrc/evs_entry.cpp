@@ -16,8 +16,4 @@ int evs_compact_events(const int8_t* s, int32_t T, int32_t C, int32_t H, int32_t
                        int64_t capacity, int64_t* count, void* ws, size_t wsb, void* stream) {
   return evs::compact_events(s, T, C, H, W, events, capacity, count, ws, wsb, (hipStream_t)stream);
 }
-int evs_autotune(const evs_net* net, int32_t H, int32_t W, int32_t T, int32_t* chosen, void* stream) {
-  (void)net; (void)H; (void)W; (void)T; (void)chosen; (void)stream;
-  return evs::fail(EVS_EUNSUPPORTED, "not implemented");
-}
 }

@@ -735,7 +735,7 @@ const Variant kVariants[] = {
     EVS_VARIANT(1, 1, 16, 0, 32, 32, "L1 cin1 f32 32x32"),
     EVS_VARIANT(1, 3, 16, 0, 32, 32, "L1 cin3 f32 32x32"),
     // two-layer nets cin -> hidden(<=16) -> out (first = default tile)
-    EVS_VARIANT(2, 3, 16, 0, 16, 32, "L2 h16 f32 16x32"),
+    EVS_VARIANT_B(2, 3, 16, 0, 16, 32, "L2 h16 f32 16x32"),
     EVS_VARIANT(2, 3, 16, 0, 30, 40, "L2 h16 f32 30x40"),
     EVS_VARIANT(2, 1, 16, 0, 30, 40, "L2 cin1 h16 f32 30x40"),
     EVS_VARIANT(2, 3, 16, 1, 30, 40, "L2 h16 bf16 30x40"),
@@ -746,7 +746,7 @@ const Variant kVariants[] = {
     EVS_VARIANT_B(2, 3, 32, 1, 30, 40, "L2 h32 bf16 30x40"),
     // three-layer nets
     EVS_VARIANT_B(3, 3, 16, 0, 24, 32, "L3 h16 f32 24x32"),
-    EVS_VARIANT(3, 3, 16, 0, 30, 40, "L3 h16 f32 30x40"),
+    EVS_VARIANT_B(3, 3, 16, 0, 30, 40, "L3 h16 f32 30x40"),
     EVS_VARIANT(3, 3, 16, 1, 30, 40, "L3 h16 bf16 30x40"),
     EVS_VARIANT(3, 3, 32, 1, 24, 32, "L3 h32 bf16 24x32"),
 };
@@ -790,6 +790,15 @@ void forward_tile_dims(const evs_net& net, int tile_id, int* th, int* tw) {
   const Variant* v = find_variant(net, tile_id);
   *th = v ? v->th : 0;
   *tw = v ? v->tw : 0;
+}
+
+int forward_batched_tile(const evs_net& net, int preferred) {
+  const Variant* v = find_variant(net, preferred);
+  if (v && v->batched) return preferred;
+  const int n = forward_tile_count(net);
+  for (int t = 0; t < n; ++t)
+    if (find_variant(net, t)->batched) return t;
+  return -1;
 }
 
 int forward_default_tile(const evs_net& net, int H, int W) {

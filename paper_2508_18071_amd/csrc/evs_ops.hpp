@@ -9,6 +9,7 @@ namespace evs {
 int zero_i32(int32_t* p, size_t n, hipStream_t s);
 int zero_f32(float* p, size_t n, hipStream_t s);
 int copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
+int fill_uniform(float* p, size_t n, uint32_t seed, float lo, float hi, hipStream_t s);
 
 // EMD loss (evs_emd.hip)
 size_t emd_workspace_bytes(int N, int T, int C, int H, int W);
@@ -26,7 +27,8 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
              int ckpt_every, const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v,
              void* ws, size_t ws_bytes, hipStream_t st);
 
-// tile selection (evs_api.cpp)
+// tile selection (evs_api.cpp); the autotuner (evs_autotune.cpp)
+void load_tile_cache_once();
 int choose_tile(const evs_net& net, int H, int W);
 void remember_tile(const evs_net& net, int H, int W, int tile);
 FwdNetArgs make_net_args(const evs_net& net, const void* packed);

@@ -39,3 +39,21 @@ int copy_f32(float* d, const float* src, size_t n, hipStream_t s) {
 }
 
 }  // namespace evs
+
+namespace evs {
+namespace {
+__global__ void k_fill_hash(float* p, size_t n, uint32_t seed, float lo, float hi) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ seed;
+    h ^= h >> 16; h *= 0x7feb352du; h ^= h >> 15; h *= 0x846ca68bu; h ^= h >> 16;
+    p[i] = lo + (hi - lo) * ((float)(h >> 8) * (1.0f / 16777216.0f));
+  }
+}
+}  // namespace
+
+int fill_uniform(float* p, size_t n, uint32_t seed, float lo, float hi, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_hash, dim3(grid_for(n)), dim3(256), 0, s, p, n, seed, lo, hi);
+  EVS_HIP(hipGetLastError());
+  return EVS_OK;
+}
+}  // namespace evs
