@@ -92,6 +92,150 @@ def traffic_from_profile(kernel_key, launches_px):
     return ent.get("bytes_per_launch")
 
 
+def compact_ws_bytes(evs, out):
+    import ctypes
+    from paper_2508_18071_amd import _lib
+    T, C, H, W = out.shape[1:]
+    c = _lib.EvsClip()
+    c.N, c.T, c.H, c.W = 1, T, H, W
+    net = evs.Net((3, C)).c()
+    return int(evs.lib().evs_workspace_bytes(ctypes.byref(net), ctypes.byref(c), 1, 0, _lib.EVS_OP_COMPACT))
+
+
+def compact_into(evs, s, events, count, ws):
+    import ctypes
+    from paper_2508_18071_amd import _lib
+    T, C, H, W = s.shape
+    import torch
+    _lib.check(evs.lib().evs_compact_events(s.data_ptr(), T, C, H, W, events.data_ptr(), events.numel(),
+                                            count.data_ptr(), ws.data_ptr(), ws.numel(),
+                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "compact_events")
+
+
+def train_form(torch, synth, evs, dev, x720, args):
+    """Training step on 4 crops of 256x256 x 64 frames of the 720p clip:
+    forward with checkpoints every 16 frames, EMD loss against contrast-
+    crossing targets of the clean crops, BPTT backward; FP32 and BF16."""
+    wl = synth.WORKLOADS["train256"]
+    crops = synth.train_crops(wl)
+    xs, es = [], []
+    for (t0, y0, x0) in crops:
+        xs.append(x720[0, t0:t0 + wl.T, :, y0:y0 + wl.H, x0:x0 + wl.W])
+        clean = synth.make_clip(synth.WORKLOADS["planes720"], device=dev, t0=t0, T=wl.T, y0=y0, x0=x0,
+                                H=wl.H, W=wl.W, clean=True)
+        es.append(synth.contrast_events(clean))
+    xb = torch.stack(xs).contiguous()
+    eb = torch.stack(es).contiguous()
+    res = {"workload": "4 crops x 64 frames x 256x256 of the 720p clip, net 3->16->16->2, "
+                       "EMD loss vs contrast-crossing targets (C=0.2), BPTT with checkpoints every 16 frames",
+           "ckpt_every": 16}
+    flops_fwd = conv_flops_per_px(wl.channels) * xb.numel() // 3
+    for prec in ("fp32", "bf16"):
+        net = evs.Net(wl.channels, theta=wl.theta, leak=wl.leak, precision=prec)
+        packed = evs.pack_weights(net, [torch.from_numpy(w).to(dev) for w in wl.weights()])
+
+        def one():
+            o = evs.forward(net, packed, xb, s_fp32=True, ckpt_every=16)
+            loss, g = evs.emd_loss(o["s"], eb)
+            evs.backward(net, packed, xb, o["ckpt"], 16, g)
+            return loss
+
+        for _ in range(2):
+            one()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            tm = Timer(torch)
+            with tm:
+                loss = one()
+            ts.append(tm)
+        torch.cuda.synchronize()
+        ms = float(np.median([t.ms() for t in ts]))
+        # forward + recompute + input-gradient + weight-gradient convolutions
+        res[prec] = {"ms": round(ms, 3), "loss": round(float(loss), 3),
+                     "conv_tflops": round(4 * flops_fwd / (ms / 1e3) / 1e12, 2)}
+        log(f"train step {prec}: {ms:.2f} ms")
+    return res
+
+
+def batched_form(torch, synth, evs, dev, args):
+    """12 clips of uneven resolution and length (BF16 3->32->2): windows of
+    frames with state carried between windows, all windows captured in one
+    hipGraph; compared with a host loop of single-clip launches."""
+    table = synth.batch_clip_table()
+    wl3 = synth.WORKLOADS["planes720_w32"]
+    net = evs.Net(wl3.channels, theta=wl3.theta, leak=wl3.leak, precision="bf16")
+    packed = evs.pack_weights(net, [torch.from_numpy(w).to(dev) for w in wl3.weights()])
+    win = args.batch_window
+    log(f"batched: generating one {win}-frame window per clip")
+    xs, outs, vs = [], [], []
+    for c in table:
+        x = torch.empty(1, win, 3, c["H"], c["W"], device=dev)
+        synth.make_clip(wl3, device=dev, T=win, H=c["H"], W=c["W"], spp=c["spp"],
+                        scene_seed=c["scene_seed"], noise_seed=c["noise_seed"], out=x[0])
+        xs.append(x)
+        outs.append(torch.empty(1, win, 2, c["H"], c["W"], dtype=torch.int8, device=dev))
+        vs.append(torch.zeros(1, net.sum_c, c["H"], c["W"], device=dev))
+    tile = evs.autotune(net, 1080, 1920, T=8)
+    Tmax = max(c["T"] for c in table)
+    # workspaces: a private copy of each clip's initial state (+ the work counter)
+    al = lambda b: (b + 255) // 256 * 256
+    ws = torch.empty(sum(al(net.sum_c * c["H"] * c["W"] * 4) for c in table) + 256, dtype=torch.uint8, device=dev)
+    wss = torch.empty(max(al(net.sum_c * c["H"] * c["W"] * 4) for c in table), dtype=torch.uint8, device=dev)
+
+    def windows_batched():
+        for v in vs:
+            v.zero_()
+        for t0 in range(0, Tmax, win):
+            act = [i for i, c in enumerate(table) if t0 < c["T"]]
+            xw = [xs[i][:, :min(win, table[i]["T"] - t0)] for i in act]
+            ow = [outs[i][:, :min(win, table[i]["T"] - t0)] for i in act]
+            if len(act) > 1:
+                evs.forward_batched(net, packed, xw, ow, v_states=[vs[i] for i in act], ws=ws)
+            else:
+                evs.forward(net, packed, xw[0], v_state=vs[act[0]], out=ow[0], ws=wss)
+
+    def windows_single():
+        for v in vs:
+            v.zero_()
+        for i, c in enumerate(table):
+            for t0 in range(0, c["T"], win):
+                n = min(win, c["T"] - t0)
+                evs.forward(net, packed, xs[i][:, :n], v_state=vs[i], out=outs[i][:, :n], ws=wss)
+
+    px = sum(c["T"] * c["H"] * c["W"] for c in table)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        windows_batched()
+        torch.cuda.synchronize()
+        g = evs.Graph(stream)
+        with g.capture():
+            windows_batched()
+        g.replay()
+        torch.cuda.synchronize()
+        tm = Timer(torch)
+        with tm:
+            g.replay()
+        t_graph = tm.ms()
+        windows_single()
+        torch.cuda.synchronize()
+        tm = Timer(torch)
+        with tm:
+            windows_single()
+        t_single = tm.ms()
+    torch.cuda.synchronize()
+    log(f"batched graph {t_graph:.1f} ms, single-clip loop {t_single:.1f} ms")
+    return {"workload": "12 clips (batch table seed 4): resolutions 320x240..1920x1080, 100-2000 frames, "
+                        f"1-8 SPP; BF16 3->32->2; windows of {win} frames (each clip's first {win} frames "
+                        "replayed cyclically), state carried across windows",
+            "px_frames": px, "tile": evs.tile_name(net, tile),
+            "graph_ms": round(t_graph, 2),
+            "value": round(px / PX720 / (t_graph / 1e3), 1), "unit": "720p event-frames/s",
+            "single_clip_loop_ms": round(t_single, 2),
+            "single_clip_loop_value": round(px / PX720 / (t_single / 1e3), 1)}
+
+
 def cpu_baseline(x_host, ws, channels, theta, leak, frames):
     from oracle import evsnet
     try:
@@ -114,8 +258,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1000, help="clip length of the headline workload")
-    ap.add_argument("--forms", default="fp32,w32")
-    ap.add_argument("--cpu-frames", type=int, default=6)
+    ap.add_argument("--forms", default="fp32,compact,w32,train,batched")
+    ap.add_argument("--cpu-frames", type=int, default=16)
+    ap.add_argument("--batch-window", type=int, default=200, help="frames per window of the batched form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -144,7 +289,9 @@ def main():
     packed = evs.pack_weights(net, [torch.from_numpy(w).to(dev) for w in ws])
     out = torch.empty(1, T, chans[-1], wl.H, wl.W, dtype=torch.int8, device=dev)
     ev_cap = out.numel()
-    events = None
+    events = torch.empty(ev_cap, dtype=torch.int64, device=dev) if "compact" in forms else None
+    ev_count = torch.zeros(1, dtype=torch.int64, device=dev)
+    cws = torch.empty(compact_ws_bytes(evs, out), dtype=torch.uint8, device=dev) if "compact" in forms else None
 
     def step():
         tm = Timer(torch)
@@ -154,7 +301,7 @@ def main():
         if "compact" in forms:
             tc = Timer(torch)
             with tc:
-                evs.compact_events(out[0], capacity=ev_cap)
+                compact_into(evs, out[0], events, ev_count, cws)
         return tm, tc
 
     log("warmup")
@@ -200,7 +347,13 @@ def main():
         "forms": {},
     }
     if cmp_ms:
-        rec["forms"]["compaction_ms"] = round(float(np.mean(cmp_ms)), 3)
+        n_ev = int(ev_count)
+        cms = float(np.mean(cmp_ms))
+        # compaction reads the dense int8 spikes twice and writes 8 B per event
+        cbytes = 2 * out.numel() + 8 * n_ev
+        rec["forms"]["compaction"] = {"ms": round(cms, 3), "events": n_ev,
+                                      "hbm_gbs": round(cbytes / (cms / 1e3) / 1e9, 1),
+                                      "hbm_frac": round(cbytes / (cms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"fp32 3-16-16-2: {ms_per_step:.2f} ms/step, {value:.0f} fps, {achieved:.1f} TFLOP/s")
 
     # ------------------------------------------------------------ precision form 3->32->2
@@ -235,9 +388,22 @@ def main():
             log(f"w32 {prec}: {ms:.2f} ms, {px_frames / PX720 / (ms / 1e3):.0f} fps")
         del o3
 
+    if events is not None:
+        del events, cws
+    if "train" in forms:
+        del out
+        rec["forms"]["train_step"] = train_form(torch, synth, evs, dev, x, args)
+    if "batched" in forms:
+        del x
+        torch.cuda.empty_cache()
+        rec["forms"]["batched"] = batched_form(torch, synth, evs, dev, args)
+        x = None
+
     # ------------------------------------------------------------ CPU baseline
     if not args.no_cpu_baseline:
         log(f"CPU oracle on {args.cpu_frames} frames")
+        if x is None:
+            x = make_720p_clip(torch, synth, dev, args.cpu_frames)
         xh = x[0, :args.cpu_frames].cpu().numpy()
         rec["cpu_baseline"] = cpu_baseline(xh, ws, chans, wl.theta, wl.leak, args.cpu_frames)
     print(json.dumps(rec), flush=True)
