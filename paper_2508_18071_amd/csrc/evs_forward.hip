@@ -46,7 +46,6 @@ struct Cfg {
   static constexpr int CHT = TH + 2 * NL, CWT = TW + 2 * NL;
   static constexpr int NPIX = CHT * CWT;
   static constexpr int PADF = 32;                    // zeroed front pad (pixels)
-  static constexpr int NPIXL = PADF + NPIX + 48;     // canvas + pads
   static constexpr int NT = 64 * NW;
   static constexpr int MB = CH / 16;                 // 16-row output blocks
   static constexpr int npb(int l) { return cdiv((CHT - 2 * l) * CWT, 16); }
@@ -54,6 +53,12 @@ struct Cfg {
   static constexpr int NPB2 = NH >= 2 ? npb(2) : 1;
   static constexpr int NB1 = cdiv(NPB1, NW);
   static constexpr int NB2 = cdiv(NPB2, NW);
+  // Every wave runs all of its NB blocks (the tail blocks past the layer's
+  // region compute masked junk), so the canvas is padded to hold them and
+  // their 3x3 neighbourhood.
+  static constexpr int imax(int a, int b) { return a > b ? a : b; }
+  static constexpr int NPIXL =
+      PADF + imax(NPIX, imax(2 * CWT + 16 * NW * NB1 + 2, 3 * CWT + 16 * NW * NB2 + 2)) + 16;
   static constexpr int NOUT = cdiv(TH * TW, NT);
   static constexpr int XN = CIN * NPIX;
   static constexpr int XPF = cdiv(XN, NT);
@@ -61,7 +66,8 @@ struct Cfg {
   static constexpr int KS1 = BF16 ? cdiv(K1, 32) : cdiv(K1, 4);
   static constexpr int KS2 = BF16 ? (CH == 32 ? 9 : 5) : 9 * CH / 4;
   static constexpr int XELEM = BF16 ? 2 : 4;
-  static constexpr int XS_BYTES = align16(CIN * NPIXL * XELEM);
+  // x planes plus one all-zero plane read by the padded K slots of layer 1
+  static constexpr int XS_BYTES = align16((CIN + 1) * NPIXL * XELEM);
   static constexpr int SP_BYTES = NH >= 1 ? align16(NPIXL * CH * XELEM) : 0;
   static constexpr int WL_FLOATS = 9 * (NH >= 1 ? CH : CIN) * CO;
   static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
@@ -429,56 +435,49 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           const int K = 4 * q + g;
           const bool kv = K < C::K1;
           const int tap = K / C::CIN, c = K - tap * C::CIN;
-          const int o = kv ? c * C::NPIXL + tap_off(tap, C::CWT) : 0;
+          const int o = kv ? c * C::NPIXL + tap_off(tap, C::CWT) : C::CIN * C::NPIXL;
+          float bv[C::NB1];
 #pragma unroll
-          for (int i = 0; i < C::NB1; ++i) {
-            if (wave + C::NW * i < C::NPB1) {
-              const float xv = xsf[p1base + 16 * C::NW * i + o];
-              const float bv = kv ? xv : 0.f;
+          for (int i = 0; i < C::NB1; ++i) bv[i] = xsf[p1base + 16 * C::NW * i + o];
 #pragma unroll
-              for (int m = 0; m < C::MB; ++m) st1[i][m] = mfma_f32(a[m], bv, st1[i][m]);
-            }
-          }
+          for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+            for (int i = 0; i < C::NB1; ++i) st1[i][m] = mfma_f32(a[m], bv[i], st1[i][m]);
         } else {
           const u4* fr = reinterpret_cast<const u4*>(lds + Lo::FR1) + q * C::MB * 64 + lane;
           u4 a[C::MB];
 #pragma unroll
           for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
           int o[8];
-          unsigned kvm = 0;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const int K = 32 * q + 8 * g + e;
             const int tap = K / C::CIN, c = K - tap * C::CIN;
-            const bool kv = K < C::K1;
-            o[e] = kv ? c * C::NPIXL + tap_off(tap, C::CWT) : 0;
-            kvm |= (kv ? 1u : 0u) << e;
+            o[e] = K < C::K1 ? c * C::NPIXL + tap_off(tap, C::CWT) : C::CIN * C::NPIXL;
           }
+          u4 bv[C::NB1];
 #pragma unroll
           for (int i = 0; i < C::NB1; ++i) {
-            if (wave + C::NW * i < C::NPB1) {
-              const int p = p1base + 16 * C::NW * i;
-              unsigned wd[4];
+            const int p = p1base + 16 * C::NW * i;
+            unsigned wd[4];
 #pragma unroll
-              for (int e2 = 0; e2 < 4; ++e2) {
-                const unsigned r0 = xsb[p + o[2 * e2]], r1 = xsb[p + o[2 * e2 + 1]];
-                const unsigned lo = ((kvm >> (2 * e2)) & 1u) ? r0 : 0u;
-                const unsigned hi = ((kvm >> (2 * e2 + 1)) & 1u) ? r1 : 0u;
-                wd[e2] = lo | (hi << 16);
-              }
-              const u4 bv = {wd[0], wd[1], wd[2], wd[3]};
-#pragma unroll
-              for (int m = 0; m < C::MB; ++m) st1[i][m] = mfma_bf16(a[m], bv, st1[i][m]);
+            for (int e2 = 0; e2 < 4; ++e2) {
+              const unsigned r0 = xsb[p + o[2 * e2]], r1 = xsb[p + o[2 * e2 + 1]];
+              wd[e2] = r0 | (r1 << 16);
             }
+            bv[i] = u4{wd[0], wd[1], wd[2], wd[3]};
           }
+#pragma unroll
+          for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+            for (int i = 0; i < C::NB1; ++i) st1[i][m] = mfma_bf16(a[m], bv[i], st1[i][m]);
         }
       }
 #pragma unroll
       for (int i = 0; i < C::NB1; ++i) {
         const int b = wave + C::NW * i;
-        if (b < C::NPB1)
-          hidden_epilogue<C>(st1[i], lds, C::CWT + 16 * b + j, (vm1 >> i) & 1u, g, theta, alpha, relaxed,
-                             trace_t, c1, 0, gy0, gx0, W, HW);
+        hidden_epilogue<C>(st1[i], lds, C::CWT + 16 * b + j, (vm1 >> i) & 1u, g, theta, alpha, relaxed,
+                           trace_t, c1, 0, gy0, gx0, W, HW);
       }
       __syncthreads();                                   // B1: s1 visible, xs free
       if (t + 1 < T) EVS_STORE_X();
@@ -502,17 +501,17 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             f4 a[C::MB];
 #pragma unroll
             for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
+            f4 bv[C::NB2];
 #pragma unroll
-            for (int i = 0; i < C::NB2; ++i) {
-              if (wave + C::NW * i < C::NPB2) {
-                const f4 bv = *reinterpret_cast<const f4*>(
-                    spf + (size_t)(p2base + 16 * C::NW * i + to) * C::CH + 16 * hh + 4 * g);
+            for (int i = 0; i < C::NB2; ++i)
+              bv[i] = *reinterpret_cast<const f4*>(spf + (size_t)(p2base + 16 * C::NW * i + to) * C::CH + 16 * hh +
+                                                   4 * g);
 #pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4)
+            for (int q4 = 0; q4 < 4; ++q4)
 #pragma unroll
-                  for (int m = 0; m < C::MB; ++m) st2[i][m] = mfma_f32(a[m][q4], bv[q4], st2[i][m]);
-              }
-            }
+              for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+                for (int i = 0; i < C::NB2; ++i) st2[i][m] = mfma_f32(a[m][q4], bv[i][q4], st2[i][m]);
           }
         }
       } else {
@@ -530,23 +529,22 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             tau = tau > 8 ? 8 : tau;                     // zero weights in that slot
             o = tap_off(tau, C::CWT) * C::CH + 8 * (g & 1);
           }
+          u4 bv[C::NB2];
 #pragma unroll
-          for (int i = 0; i < C::NB2; ++i) {
-            if (wave + C::NW * i < C::NPB2) {
-              const u4 bv = *reinterpret_cast<const u4*>(spb + (size_t)(p2base + 16 * C::NW * i) * C::CH + o);
+          for (int i = 0; i < C::NB2; ++i)
+            bv[i] = *reinterpret_cast<const u4*>(spb + (size_t)(p2base + 16 * C::NW * i) * C::CH + o);
 #pragma unroll
-              for (int m = 0; m < C::MB; ++m) st2[i][m] = mfma_bf16(a[m], bv, st2[i][m]);
-            }
-          }
+          for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+            for (int i = 0; i < C::NB2; ++i) st2[i][m] = mfma_bf16(a[m], bv[i], st2[i][m]);
         }
       }
       __syncthreads();                                   // B2: all reads of s1 done
 #pragma unroll
       for (int i = 0; i < C::NB2; ++i) {
         const int b = wave + C::NW * i;
-        if (b < C::NPB2)
-          hidden_epilogue<C>(st2[i], lds, 2 * C::CWT + 16 * b + j, (vm2 >> i) & 1u, g, theta, alpha, relaxed,
-                             trace_t, c2, choff2, gy0, gx0, W, HW);
+        hidden_epilogue<C>(st2[i], lds, 2 * C::CWT + 16 * b + j, (vm2 >> i) & 1u, g, theta, alpha, relaxed,
+                           trace_t, c2, choff2, gy0, gx0, W, HW);
       }
       __syncthreads();                                   // B3: s2 visible
     }
@@ -740,8 +738,8 @@ const Variant kVariants[] = {
     EVS_VARIANT(2, 1, 16, 0, 30, 40, "L2 cin1 h16 f32 30x40"),
     EVS_VARIANT(2, 3, 16, 1, 30, 40, "L2 h16 bf16 30x40"),
     // two-layer nets with hidden width <= 32
-    EVS_VARIANT(2, 3, 32, 0, 24, 32, "L2 h32 f32 24x32"),
-    EVS_VARIANT(2, 3, 32, 0, 16, 48, "L2 h32 f32 16x48"),
+    EVS_VARIANT(2, 3, 32, 0, 22, 32, "L2 h32 f32 22x32"),
+    EVS_VARIANT(2, 3, 32, 0, 16, 44, "L2 h32 f32 16x44"),
     EVS_VARIANT_B(2, 3, 32, 1, 24, 32, "L2 h32 bf16 24x32"),
     EVS_VARIANT_B(2, 3, 32, 1, 30, 40, "L2 h32 bf16 30x40"),
     // three-layer nets
