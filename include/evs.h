@@ -98,8 +98,10 @@ typedef struct evs_net {
  *            all layers (layer-major): read as the initial state and
  *            overwritten with the state after frame T-1.  Splitting a clip
  *            at any frame and carrying v_state gives bit-identical spikes.
- *   h_trace  NULL, or [N][T][sum_l C_l][H][W] float32: the charged
- *            potential h of every layer at every frame (debug/training).   */
+ *   h_trace  NULL, or [N][T][sum_l C_l][h][w] float32: the charged
+ *            potential h of every layer at every frame (debug/training),
+ *            over the window trace_box = {y0, x0, h, w} of the frame, or over
+ *            the whole frame (h = H, w = W) when trace_box[2] == 0.        */
 typedef struct evs_clip {
   int32_t N, T, H, W;
   const float* x;
@@ -107,6 +109,7 @@ typedef struct evs_clip {
   int32_t s_fp32;
   float* v_state;
   float* h_trace;
+  int32_t trace_box[4];
 } evs_clip;
 
 /* Event record produced by evs_compact_events, packed in a uint64:

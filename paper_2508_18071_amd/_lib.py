@@ -38,6 +38,7 @@ class EvsClip(ctypes.Structure):
         ("s_fp32", ctypes.c_int32),
         ("v_state", ctypes.c_void_p),
         ("h_trace", ctypes.c_void_p),
+        ("trace_box", ctypes.c_int32 * 4),
     ]
 
 

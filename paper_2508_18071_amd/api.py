@@ -59,9 +59,12 @@ def _stream(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _clip(x, s_out=None, s_fp32=False, v_state=None, h_trace=None):
+def _clip(x, s_out=None, s_fp32=False, v_state=None, h_trace=None, trace_box=None):
     N, T, _, H, W = x.shape
     c = EvsClip()
+    if trace_box is not None:
+        for i in range(4):
+            c.trace_box[i] = int(trace_box[i])
     c.N, c.T, c.H, c.W = N, T, H, W
     c.x = x.data_ptr()
     c.s_out = s_out.data_ptr() if s_out is not None else None
@@ -112,14 +115,16 @@ def workspace(net: Net, clips, op=_lib.EVS_OP_FORWARD, ckpt_every=0, device=None
 
 def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = False,
             v_state: torch.Tensor | None = None, trace: bool = False, ckpt_every: int = 0,
-            out: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None):
+            out: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None,
+            trace_box=None):
     """Run the network over x [N,T,Cin,H,W] (float32, on the GPU).
 
     Returns a dict: "s" [N,T,Cout,H,W] (int8 or float32), "h" (the charged
     potentials of all layers [N,T,sumC,H,W], if trace), "ckpt" (if
     ckpt_every > 0).  v_state [N,sumC,H,W] is read and overwritten in place.
     ``ws`` is an optional preallocated workspace (needed under graph capture,
-    where nothing may be allocated).
+    where nothing may be allocated).  ``trace_box`` = (y0, x0, h, w) limits
+    the trace to that window of the frame.
     """
     if x.dim() == 4:
         x = x.unsqueeze(0)
@@ -133,12 +138,13 @@ def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = F
     cout = net.channels[-1]
     if out is None:
         out = torch.empty(N, T, cout, H, W, dtype=torch.float32 if s_fp32 else torch.int8, device=dev)
-    h = torch.empty(N, T, net.sum_c, H, W, dtype=torch.float32, device=dev) if trace else None
+    th, tw = (trace_box[2], trace_box[3]) if trace_box is not None else (H, W)
+    h = torch.empty(N, T, net.sum_c, th, tw, dtype=torch.float32, device=dev) if trace else None
     ck = None
     if ckpt_every > 0:
         nseg = (T + ckpt_every - 1) // ckpt_every
         ck = torch.empty(N, nseg, net.sum_c, H, W, dtype=torch.float32, device=dev)
-    c = _clip(x, out, s_fp32, v_state, h)
+    c = _clip(x, out, s_fp32, v_state, h, trace_box)
     if ws is None:
         ws, nb = workspace(net, [c], device=dev)
     else:

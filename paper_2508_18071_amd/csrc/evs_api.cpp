@@ -51,6 +51,11 @@ int validate_clip(const evs_net& net, const evs_clip& c, bool need_x) {
   if ((double)c.N * c.T * net.ch[0] * c.H * c.W > 9.0e18) return fail(EVS_EOVERFLOW, "clip too large");
   if (need_x && !c.x) return fail(EVS_EINVAL, "clip x is NULL");
   if (net.relaxed && c.s_out && !c.s_fp32) return fail(EVS_EINVAL, "relaxed spikes need s_fp32 = 1");
+  if (c.trace_box[2] > 0 || c.trace_box[3] > 0) {
+    const int* b = c.trace_box;
+    if (b[0] < 0 || b[1] < 0 || b[2] < 1 || b[3] < 1 || b[0] + b[2] > c.H || b[1] + b[3] > c.W)
+      return fail(EVS_EINVAL, "trace_box must lie inside the frame");
+  }
   return EVS_OK;
 }
 
@@ -219,7 +224,12 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
     const int64_t HW = (int64_t)c.H * c.W;
     ca.x_nstride = (int64_t)c.T * net->ch[0] * HW;
     ca.vin_nstride = (int64_t)sumc * HW;
-    ca.trace_nstride = (int64_t)c.T * sumc * HW;
+    if (c.trace_box[2] > 0) {
+      ca.tb_y0 = c.trace_box[0]; ca.tb_x0 = c.trace_box[1]; ca.tb_h = c.trace_box[2]; ca.tb_w = c.trace_box[3];
+    } else {
+      ca.tb_y0 = 0; ca.tb_x0 = 0; ca.tb_h = c.H; ca.tb_w = c.W;
+    }
+    ca.trace_nstride = (int64_t)c.T * sumc * ca.tb_h * ca.tb_w;
     if (c.v_state) {
       // the initial state is read from a private copy so that workgroups
       // writing the final state cannot race with halo reads of the initial one

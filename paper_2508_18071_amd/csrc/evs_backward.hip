@@ -327,6 +327,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
     ca.vin_nstride = (long long)nseg_ck * sumc * HW;
     ca.h_trace = hseg;
     ca.trace_nstride = (long long)len * sumc * HW;
+    ca.tb_y0 = 0; ca.tb_x0 = 0; ca.tb_h = H; ca.tb_w = W;
     ca.N = N; ca.T = len; ca.H = H; ca.W = W;
     ca.tiles_x = (W + tw - 1) / tw;
     ca.tiles_y = (H + th - 1) / th;

@@ -197,20 +197,29 @@ __device__ __forceinline__ int tap_off(int tau, int cwt) {
 // Hidden-layer epilogue for one 16-pixel block: st holds the charged
 // potentials h of MB x 4 (channel, pixel) pairs of this lane; fire, reset,
 // write spikes to LDS and, optionally, h to the trace.
+// Window of the image whose potentials go to the trace.
+struct TraceBox {
+  int y0, x0, h, w;
+  __device__ bool has(int gy, int gx) const { return gy >= y0 && gy < y0 + h && gx >= x0 && gx < x0 + w; }
+  __device__ size_t idx(int gy, int gx) const { return (size_t)(gy - y0) * w + (gx - x0); }
+  __device__ size_t plane() const { return (size_t)h * w; }
+};
+
 template <class C>
 __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int pr, bool valid, int g,
                                                 float theta, float alpha, bool relaxed, float* trace_t,
-                                                int cl, int choff, int gy0, int gx0, int W, size_t HW) {
+                                                int cl, int choff, int gy0, int gx0, const TraceBox& tb) {
   if (C::FULL && trace_t && valid) {
     const int row = pr / C::CWT, col = pr % C::CWT;
-    if (row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
-      const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
+    const int gy = gy0 + row, gx = gx0 + col;
+    if (row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW && tb.has(gy, gx)) {
+      const size_t pix = tb.idx(gy, gx);
 #pragma unroll
       for (int m = 0; m < C::MB; ++m)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int co = 16 * m + 4 * g + r;
-          if (co < cl) trace_t[(size_t)(choff + co) * HW + pix] = st[m][r];
+          if (co < cl) trace_t[(size_t)(choff + co) * tb.plane() + pix] = st[m][r];
         }
     }
   }
@@ -386,6 +395,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   } while (0)
 
   const int nseg = ca.ckpt_every > 0 ? cdiv(T, ca.ckpt_every) : 0;
+  const TraceBox tb{ca.tb_y0, ca.tb_x0, ca.tb_h, ca.tb_w};
   auto write_state = [&](float* dst) __attribute__((always_inline)) {
     if constexpr (C::NH >= 1) write_hidden_state<C, C::NB1>(st1, vm1, 1, wave, j, g, dst, c1, 0, gy0, gx0, W, HW);
     if constexpr (C::NH >= 2) write_hidden_state<C, C::NB2>(st2, vm2, 2, wave, j, g, dst, c2, choff2, gy0, gx0, W, HW);
@@ -416,7 +426,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     if constexpr (C::FULL) {
       if (ca.ckpt && (t % ca.ckpt_every) == 0)
         write_state(ca.ckpt + ((size_t)tl.n * nseg + t / ca.ckpt_every) * sumc * HW);
-      trace_t = ca.h_trace ? ca.h_trace + (size_t)tl.n * ca.trace_nstride + (size_t)t * sumc * HW : nullptr;
+      trace_t = ca.h_trace ? ca.h_trace + (size_t)tl.n * ca.trace_nstride + (size_t)t * sumc * tb.plane()
+                           : nullptr;
     }
 
     if constexpr (C::NH >= 1) {
@@ -477,7 +488,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       for (int i = 0; i < C::NB1; ++i) {
         const int b = wave + C::NW * i;
         hidden_epilogue<C>(st1[i], lds, C::CWT + 16 * b + j, (vm1 >> i) & 1u, g, theta, alpha, relaxed,
-                           trace_t, c1, 0, gy0, gx0, W, HW);
+                           trace_t, c1, 0, gy0, gx0, tb);
       }
       __syncthreads();                                   // B1: s1 visible, xs free
       if (t + 1 < T) EVS_STORE_X();
@@ -544,7 +555,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       for (int i = 0; i < C::NB2; ++i) {
         const int b = wave + C::NW * i;
         hidden_epilogue<C>(st2[i], lds, 2 * C::CWT + 16 * b + j, (vm2 >> i) & 1u, g, theta, alpha, relaxed,
-                           trace_t, c2, choff2, gy0, gx0, W, HW);
+                           trace_t, c2, choff2, gy0, gx0, tb);
       }
       __syncthreads();                                   // B3: s2 visible
     }
@@ -609,7 +620,10 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
 #pragma unroll
         for (int co = 0; co < 2; ++co) {
-          if (C::FULL && ok && co < cout && trace_t) trace_t[(size_t)(choffo + co) * HW + pix] = u[k][co];
+          if (C::FULL && ok && co < cout && trace_t) {
+            const int gy = tl.ty0 + q / C::TW, gx = tl.tx0 + q % C::TW;
+            if (tb.has(gy, gx)) trace_t[(size_t)(choffo + co) * tb.plane() + tb.idx(gy, gx)] = u[k][co];
+          }
           float v = u[k][co];
           const float s = bilif(v, theta, alpha, C::FULL && relaxed);
           so[k][co] = v;
@@ -652,7 +666,7 @@ __device__ inline int xcd_remap(int b, int n) {
 }
 
 template <class C>
-__global__ __launch_bounds__(C::NT) void fwd_kernel(FwdNetArgs na, FwdClipArgs ca) {
+__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void fwd_kernel(FwdNetArgs na, FwdClipArgs ca) {
   __shared__ __attribute__((aligned(16))) char lds[Layout<C>::TOTAL];
   init_lds<C>(na, lds);
   __syncthreads();
@@ -668,7 +682,7 @@ __global__ __launch_bounds__(C::NT) void fwd_kernel(FwdNetArgs na, FwdClipArgs c
 // Persistent batched kernel: workgroups pop (clip, tile) items from a device
 // counter; items are ordered clip by clip, clips longest-first.
 template <class C>
-__global__ __launch_bounds__(C::NT) void fwd_batched_kernel(FwdNetArgs na, BatchTable bt, int32_t* counter) {
+__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void fwd_batched_kernel(FwdNetArgs na, BatchTable bt, int32_t* counter) {
   __shared__ __attribute__((aligned(16))) char lds[Layout<C>::TOTAL];
   __shared__ int item_sh;
   init_lds<C>(na, lds);
@@ -718,35 +732,47 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
   *err = hipGetLastError();
 }
 
-#define EVS_CFG(NL, CIN, CH, BF, TH, TW, FULL) Cfg<NL, CIN, CH, (bool)BF, TH, TW, 8, FULL>
+#define EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, FULL) Cfg<NL, CIN, CH, (bool)BF, TH, TW, NW, FULL>
 // a tile variant: inference kernel + training/debug kernel (+ batched kernel)
-#define EVS_VARIANT(NL, CIN, CH, BF, TH, TW, NAME)                                  \
-  Variant{NL, CIN, CH, BF, TH, TW, NAME, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, false)>, \
-          &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, true)>, nullptr}
-#define EVS_VARIANT_B(NL, CIN, CH, BF, TH, TW, NAME)                                \
-  Variant{NL, CIN, CH, BF, TH, TW, NAME, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, false)>, \
-          &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, true)>,                   \
-          &launch_batched<EVS_CFG(NL, CIN, CH, BF, TH, TW, false)>}
+#define EVS_VARIANT(NL, CIN, CH, BF, TH, TW, NW, NAME)                                              \
+  Variant{NL, CIN, CH, BF, TH, TW, NAME, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, false)>, \
+          &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, true)>, nullptr}
+#define EVS_VARIANT_B(NL, CIN, CH, BF, TH, TW, NW, NAME)                                            \
+  Variant{NL, CIN, CH, BF, TH, TW, NAME, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, false)>, \
+          &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, true)>,                               \
+          &launch_batched<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, false)>}
 
+// Tile variants per network shape; the first one of a shape is its default.
+// 4-wave variants are small enough (LDS <= 80 KB) for two workgroups per CU,
+// whose MFMA and VALU phases then overlap.
 const Variant kVariants[] = {
     // single-layer nets (input -> output), f32
-    EVS_VARIANT(1, 1, 16, 0, 32, 32, "L1 cin1 f32 32x32"),
-    EVS_VARIANT(1, 3, 16, 0, 32, 32, "L1 cin3 f32 32x32"),
-    // two-layer nets cin -> hidden(<=16) -> out (first = default tile)
-    EVS_VARIANT_B(2, 3, 16, 0, 16, 32, "L2 h16 f32 16x32"),
-    EVS_VARIANT(2, 3, 16, 0, 30, 40, "L2 h16 f32 30x40"),
-    EVS_VARIANT(2, 1, 16, 0, 30, 40, "L2 cin1 h16 f32 30x40"),
-    EVS_VARIANT(2, 3, 16, 1, 30, 40, "L2 h16 bf16 30x40"),
+    EVS_VARIANT(1, 1, 16, 0, 32, 32, 8, "L1 cin1 f32 32x32 w8"),
+    EVS_VARIANT(1, 3, 16, 0, 32, 32, 8, "L1 cin3 f32 32x32 w8"),
+    // two-layer nets cin -> hidden(<=16) -> out
+    EVS_VARIANT_B(2, 3, 16, 0, 16, 32, 8, "L2 h16 f32 16x32 w8"),
+    EVS_VARIANT(2, 3, 16, 0, 30, 40, 8, "L2 h16 f32 30x40 w8"),
+    EVS_VARIANT(2, 3, 16, 0, 20, 32, 4, "L2 h16 f32 20x32 w4"),
+    EVS_VARIANT(2, 1, 16, 0, 30, 40, 8, "L2 cin1 h16 f32 30x40 w8"),
+    EVS_VARIANT(2, 3, 16, 1, 30, 40, 8, "L2 h16 bf16 30x40 w8"),
     // two-layer nets with hidden width <= 32
-    EVS_VARIANT(2, 3, 32, 0, 22, 32, "L2 h32 f32 22x32"),
-    EVS_VARIANT(2, 3, 32, 0, 16, 44, "L2 h32 f32 16x44"),
-    EVS_VARIANT_B(2, 3, 32, 1, 24, 32, "L2 h32 bf16 24x32"),
-    EVS_VARIANT_B(2, 3, 32, 1, 30, 40, "L2 h32 bf16 30x40"),
+    EVS_VARIANT(2, 3, 32, 0, 22, 32, 8, "L2 h32 f32 22x32 w8"),
+    EVS_VARIANT(2, 3, 32, 0, 16, 44, 8, "L2 h32 f32 16x44 w8"),
+    EVS_VARIANT_B(2, 3, 32, 1, 24, 32, 8, "L2 h32 bf16 24x32 w8"),
+    EVS_VARIANT_B(2, 3, 32, 1, 30, 40, 8, "L2 h32 bf16 30x40 w8"),
+    EVS_VARIANT_B(2, 3, 32, 1, 16, 32, 4, "L2 h32 bf16 16x32 w4"),
+    EVS_VARIANT_B(2, 3, 32, 1, 20, 32, 4, "L2 h32 bf16 20x32 w4"),
+    EVS_VARIANT(2, 3, 32, 1, 12, 32, 4, "L2 h32 bf16 12x32 w4"),
     // three-layer nets
-    EVS_VARIANT_B(3, 3, 16, 0, 24, 32, "L3 h16 f32 24x32"),
-    EVS_VARIANT_B(3, 3, 16, 0, 30, 40, "L3 h16 f32 30x40"),
-    EVS_VARIANT(3, 3, 16, 1, 30, 40, "L3 h16 bf16 30x40"),
-    EVS_VARIANT(3, 3, 32, 1, 24, 32, "L3 h32 bf16 24x32"),
+    EVS_VARIANT_B(3, 3, 16, 0, 24, 32, 8, "L3 h16 f32 24x32 w8"),
+    EVS_VARIANT_B(3, 3, 16, 0, 30, 40, 8, "L3 h16 f32 30x40 w8"),
+    EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
+    EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
+    EVS_VARIANT(3, 3, 16, 0, 12, 36, 4, "L3 h16 f32 12x36 w4"),
+    EVS_VARIANT(3, 3, 16, 0, 10, 32, 4, "L3 h16 f32 10x32 w4"),
+    EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40 w8"),
+    EVS_VARIANT(3, 3, 16, 1, 16, 32, 4, "L3 h16 bf16 16x32 w4"),
+    EVS_VARIANT(3, 3, 32, 1, 24, 32, 8, "L3 h32 bf16 24x32 w8"),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

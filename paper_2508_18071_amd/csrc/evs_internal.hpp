@@ -65,6 +65,8 @@ struct FwdClipArgs {
   int32_t tiles_x, tiles_y;
   // element strides between the clips of a batch (x, initial state, trace)
   int64_t x_nstride, vin_nstride, trace_nstride;
+  // image window recorded in h_trace (the whole frame by default)
+  int32_t tb_y0, tb_x0, tb_h, tb_w;
 };
 
 struct FwdNetArgs {

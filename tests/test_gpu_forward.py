@@ -216,3 +216,21 @@ def test_relaxed_forward_matches_oracle(evs):
     h = split_layers(out["h"][0].cpu().numpy(), channels)
     for hd, hr in zip(h, ref["h"]):
         assert np.abs(hd - hr).max() / np.abs(hr).max() < 1e-4
+
+
+@pytest.mark.parametrize("channels,prec", [((3, 16, 16, 2), "fp32"), ((3, 32, 2), "bf16")])
+def test_inference_kernel_equals_traced_kernel_and_trace_window(evs, channels, prec):
+    """The inference build (no traces) and the training/debug build emit the
+    same spikes bit for bit; a windowed trace equals that window of the
+    full trace."""
+    x, ws = make_inputs(channels, 6, 70, 90)
+    net = evs.Net(channels, theta=THETA, leak=LEAK, precision=prec)
+    packed = evs.pack_weights(net, [torch.from_numpy(w).cuda() for w in ws])
+    xg = x.cuda()
+    fast = evs.forward(net, packed, xg)
+    full = evs.forward(net, packed, xg, trace=True)
+    win = evs.forward(net, packed, xg, trace=True, trace_box=(13, 29, 20, 31))
+    torch.cuda.synchronize()
+    assert torch.equal(fast["s"], full["s"])
+    assert torch.equal(win["s"], full["s"])
+    assert torch.equal(win["h"], full["h"][:, :, :, 13:33, 29:60])
