@@ -276,6 +276,16 @@ def main():
     evs.lib()
     dev = torch.device("cuda:0")
     forms = set(args.forms.split(","))
+    if forms == {"copy"}:
+        # calibration for HBM-traffic counters: one plain device copy of
+        # exactly 2 GiB read + 2 GiB written
+        a = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
     T = args.frames
     wl = synth.WORKLOADS["planes720"]
     log(f"generating {T} frames of 1280x720x3 on the GPU")
