@@ -53,13 +53,23 @@ struct Cfg {
   static constexpr int NPB2 = NH >= 2 ? npb(2) : 1;
   static constexpr int NB1 = cdiv(NPB1, NW);
   static constexpr int NB2 = cdiv(NPB2, NW);
+  // BF16 nets run the output layer on MFMA too (16-row blocks, Cout rows
+  // used); FP32 nets run it on the VALU, one lane per output pixel.
+  static constexpr bool OMF = BF16 && NH >= 1;
+  static constexpr int NPBO = cdiv(TH * CWT, 16);    // output blocks (rows NL..NL+TH-1)
+  static constexpr int NBO = OMF ? cdiv(NPBO, NW) : 1;
+  static constexpr int KSO = CH == 32 ? 9 : 5;
   // Every wave runs all of its NB blocks (the tail blocks past the layer's
   // region compute masked junk), so the canvas is padded to hold them and
   // their 3x3 neighbourhood.
   static constexpr int imax(int a, int b) { return a > b ? a : b; }
+  // wave-specialised schedule: layer-1 blocks over 4 waves, layer-2 blocks over 4
+  static constexpr int NB1V = cdiv(NPB1, 4), NB2M = cdiv(NPB2, 4);
   static constexpr int NPIXL =
-      PADF + imax(NPIX, imax(2 * CWT + 16 * NW * NB1 + 2, 3 * CWT + 16 * NW * NB2 + 2)) + 16;
-  static constexpr int NOUT = cdiv(TH * TW, NT);
+      PADF + imax(imax(imax(NPIX, (NL + 1) * CWT + 16 * NW * NBO + 2),
+                       imax(2 * CWT + 16 * NW * NB1 + 2, 3 * CWT + 16 * NW * NB2 + 2)),
+                  imax(2 * CWT + 64 * NB1V + 2, 3 * CWT + 64 * NB2M + 2)) + 16;
+  static constexpr int NOUT = OMF ? 1 : cdiv(TH * TW, NT);
   static constexpr int XN = CIN * NPIX;
   static constexpr int XPF = cdiv(XN, NT);
   static constexpr int K1 = 9 * CIN;
@@ -68,10 +78,20 @@ struct Cfg {
   static constexpr int XELEM = BF16 ? 2 : 4;
   // x planes plus one all-zero plane read by the padded K slots of layer 1
   static constexpr int XS_BYTES = align16((CIN + 1) * NPIXL * XELEM);
-  static constexpr int SP_BYTES = NH >= 1 ? align16(NPIXL * CH * XELEM) : 0;
+  // The FP32 three-layer inference kernel runs a software pipeline (output
+  // layer of frame t-1 fused into the layer-2 MFMA loop of frame t) and keeps
+  // separate layer-1 / layer-2 spike buffers.  Spikes are exact in bf16, so
+  // the pipelined and BF16 kernels store them in 16 bits.
+  static constexpr bool PIPE = !BF16 && NH == 2 && !FULL && NW == 8 && CH == 16;
+  static constexpr bool SPB16 = BF16;                            // layer-1 (shared) buffer in bf16
+  static constexpr int SELEM = SPB16 ? 2 : 4;
+  static constexpr int SP1_BYTES = NH >= 1 ? align16(NPIXL * CH * SELEM) : 0;
+  static constexpr int SP2_OFF = PIPE ? SP1_BYTES : 0;          // layer-2 buffer (bf16) inside SP
+  static constexpr int SP_BYTES = SP1_BYTES + (PIPE ? align16(NPIXL * CH * 2) : 0);
   static constexpr int WL_FLOATS = 9 * (NH >= 1 ? CH : CIN) * CO;
   static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
-  static_assert(NB1 <= 32 && NB2 <= 32 && NOUT <= 32 && (BF16 ? 8 * KS1 : KS1) <= 32, "mask words overflow");
+  static_assert(NB1 <= 32 && NB2 <= 32 && NBO <= 32 && NOUT <= 32 && (BF16 ? 8 * KS1 : KS1) <= 32,
+                "mask words overflow");
   static constexpr int toff(int tau) { return (tau / 3 - 1) * CWT + (tau % 3 - 1); }
 };
 
@@ -107,7 +127,9 @@ struct Layout {
   static constexpr int FR1_BYTES = C::NH >= 1 ? C::KS1 * C::MB * 64 * (C::BF16 ? 16 : 4) : 0;
   static constexpr int FR2 = FR1 + FR1_BYTES;                   // layer-2 A fragments
   static constexpr int FR2_BYTES = C::NH >= 2 ? C::KS2 * C::MB * 64 * (C::BF16 ? 16 : 4) : 0;
-  static constexpr int TOTAL = FR2 + FR2_BYTES;
+  static constexpr int FR3 = FR2 + FR2_BYTES;                   // output-layer A fragments (MFMA form)
+  static constexpr int FR3_BYTES = C::OMF ? C::KSO * 64 * 16 : 0;
+  static constexpr int TOTAL = FR3 + FR3_BYTES;
   static_assert(TOTAL <= 160 * 1024, "tile does not fit in LDS");
 };
 
@@ -184,6 +206,34 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
   }
 }
 
+// A fragments of the output layer in its MFMA form (BF16 nets): rows are the
+// output channels (16 rows, Cout used), K = (tap, ci) laid out like the
+// hidden->hidden layer.
+template <class C>
+__device__ __forceinline__ void load_out_frags(const FwdNetArgs& na, char* lds) {
+  if constexpr (C::OMF) {
+    const int L = na.n_layers - 1;
+    const int cin = na.ch[L], cout = na.ch[L + 1];
+    for (int e = threadIdx.x; e < C::KSO * 64; e += C::NT) {
+      const int lane = e % 64, q = e / 64;
+      const int co = lane & 15, g = lane >> 4;
+      int tau, cib;
+      if constexpr (C::CH == 32) { tau = q; cib = 8 * g; }
+      else { tau = 2 * q + (g >> 1); cib = 8 * (g & 1); }
+      unsigned wd[4];
+      for (int e2 = 0; e2 < 4; ++e2) {
+        float ww[2];
+        for (int h = 0; h < 2; ++h) {
+          const int ci = cib + 2 * e2 + h;
+          ww[h] = (tau < 9 && co < cout && ci < cin) ? wget(na, L, co, ci, tau, true) : 0.f;
+        }
+        wd[e2] = pack_bf16x2(ww[0], ww[1]);
+      }
+      reinterpret_cast<u4*>(lds + Layout<C>::FR3)[e] = u4{wd[0], wd[1], wd[2], wd[3]};
+    }
+  }
+}
+
 // ------------------------------------------------------------------ tile
 struct Tile {
   int n, ty0, tx0;
@@ -205,8 +255,8 @@ struct TraceBox {
   __device__ size_t plane() const { return (size_t)h * w; }
 };
 
-template <class C>
-__device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int pr, bool valid, int g,
+template <class C, bool B16 = C::SPB16>
+__device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int sp_off, int pr, bool valid, int g,
                                                 float theta, float alpha, bool relaxed, float* trace_t,
                                                 int cl, int choff, int gy0, int gx0, const TraceBox& tb) {
   if (C::FULL && trace_t && valid) {
@@ -234,11 +284,11 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
       st[m][r] = v;
     }
     if (!valid) s = f4{0.f, 0.f, 0.f, 0.f};
-    if constexpr (C::BF16) {
+    if constexpr (B16) {
       uint2 w2 = {pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
-      *reinterpret_cast<uint2*>(lds + Layout<C>::SP + ((size_t)p * C::CH + 16 * m + 4 * g) * 2) = w2;
+      *reinterpret_cast<uint2*>(lds + Layout<C>::SP + sp_off + ((size_t)p * C::CH + 16 * m + 4 * g) * 2) = w2;
     } else {
-      *reinterpret_cast<f4*>(lds + Layout<C>::SP + ((size_t)p * C::CH + 16 * m + 4 * g) * 4) = s;
+      *reinterpret_cast<f4*>(lds + Layout<C>::SP + sp_off + ((size_t)p * C::CH + 16 * m + 4 * g) * 4) = s;
     }
   }
 }
@@ -247,10 +297,10 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
 template <class C, int NB>
 __device__ __forceinline__ void write_hidden_state(const f4 (&st)[NB][C::MB], unsigned vm, int layer, int wave,
                                                    int j, int g, float* dst, int cl, int choff, int gy0,
-                                                   int gx0, int W, size_t HW) {
+                                                   int gx0, int W, size_t HW, int nw = C::NW) {
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int pr = layer * C::CWT + 16 * (wave + C::NW * i) + j;
+    const int pr = layer * C::CWT + 16 * (wave + nw * i) + j;
     const int row = pr / C::CWT, col = pr % C::CWT;
     if (((vm >> i) & 1u) && row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW) {
       const size_t pix = (size_t)(gy0 + row) * W + (gx0 + col);
@@ -268,14 +318,14 @@ __device__ __forceinline__ void write_hidden_state(const f4 (&st)[NB][C::MB], un
 template <class C, int NB>
 __device__ __forceinline__ void read_hidden_state(f4 (&st)[NB][C::MB], unsigned vm, int layer, int wave, int j,
                                                   int g, const float* src, int cl, int choff, int gy0, int gx0,
-                                                  int W, size_t HW) {
+                                                  int W, size_t HW, int nw = C::NW) {
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int m = 0; m < C::MB; ++m) {
       f4 v = {0.f, 0.f, 0.f, 0.f};
       if (src && ((vm >> i) & 1u)) {
-        const int pr = layer * C::CWT + 16 * (wave + C::NW * i) + j;
+        const int pr = layer * C::CWT + 16 * (wave + nw * i) + j;
         const size_t pix = (size_t)(gy0 + pr / C::CWT) * W + (gx0 + pr % C::CWT);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -287,9 +337,275 @@ __device__ __forceinline__ void read_hidden_state(f4 (&st)[NB][C::MB], unsigned 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wave-specialised schedule of the FP32 three-layer inference kernel.
+//
+// Waves 0-3 (one per SIMD) own layer 2: its membrane state and all of its
+// MFMAs.  Waves 4-7 own layer 1 and the output layer.  Per frame t:
+//   phase A   waves 0-3: fire/reset of layer 2 for frame t-1 (-> S2, bf16)
+//             waves 4-7: layer-1 MFMA + fire/reset for frame t (-> S1, f32)
+//   barrier;  all: stage x(t+1), prefetch x(t+2)
+//   phase B   waves 0-3: layer-2 MFMA of frame t (reads S1)
+//             waves 4-7: output layer of frame t-1 on the VALU (reads S2)
+//   barrier
+// In phase B every SIMD holds one MFMA-issuing wave and one VALU-issuing
+// wave, so the output layer runs under the MFMA work.  Each neuron sees the
+// same arithmetic in the same order as in the plain schedule: the results
+// are bit-identical.
+// ---------------------------------------------------------------------------
+template <class C>
+__device__ __forceinline__ void run_tile_pipe(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl,
+                                              char* lds) {
+  static_assert(C::NW == 8 && C::NH == 2 && !C::BF16 && !C::FULL, "specialised schedule: FP32, 3 layers, 8 waves");
+  using Lo = Layout<C>;
+  constexpr int NB1V = C::NB1V, NB2M = C::NB2M;
+  constexpr int NOV = cdiv(C::TH * C::TW, 256);
+  float* const xsf = reinterpret_cast<float*>(lds + Lo::XS);
+  const float* const s1f = reinterpret_cast<const float*>(lds + Lo::SP);
+  const uint16_t* const s2b = reinterpret_cast<const uint16_t*>(lds + Lo::SP + C::SP2_OFF);
+  const float* const wl = reinterpret_cast<const float*>(lds + Lo::WL);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool mrole = wave < 4;                       // layer-2 (MFMA) waves
+  const int rw = wave & 3;                           // index inside the role
+  const int j = lane & 15, g = lane >> 4;
+  const int H = ca.H, W = ca.W, T = ca.T;
+  const size_t HW = (size_t)H * W;
+  const int sumc = na.sum_c;
+  const float theta = na.theta, leak = na.leak, alpha = na.alpha;
+  const int c1 = na.ch[1], c2 = na.ch[2];
+  const int cout = na.ch[3];
+  const int choff2 = c1, choffo = c1 + c2;
+  const int gy0 = tl.ty0 - C::NL, gx0 = tl.tx0 - C::NL;
+  const TraceBox tb{0, 0, 0, 0};
+
+  // ---- block masks (layer 1: VALU waves, layer 2: MFMA waves)
+  unsigned vm1 = 0, vm2 = 0, ovm = 0;
+#pragma unroll
+  for (int i = 0; i < NB1V; ++i) {
+    const int b = rw + 4 * i;
+    const int pr = C::CWT + 16 * b + j;
+    const int row = pr / C::CWT, col = pr % C::CWT;
+    const int gy = gy0 + row, gx = gx0 + col;
+    vm1 |= ((b < C::NPB1 && row < C::CHT - 1 && gy >= 0 && gy < H && gx >= 0 && gx < W) ? 1u : 0u) << i;
+  }
+#pragma unroll
+  for (int i = 0; i < NB2M; ++i) {
+    const int b = rw + 4 * i;
+    const int pr = 2 * C::CWT + 16 * b + j;
+    const int row = pr / C::CWT, col = pr % C::CWT;
+    const int gy = gy0 + row, gx = gx0 + col;
+    vm2 |= ((b < C::NPB2 && row < C::CHT - 2 && gy >= 0 && gy < H && gx >= 0 && gx < W) ? 1u : 0u) << i;
+  }
+  const int vt = tid & 255;                          // lane index inside the VALU group
+  int op[NOV];
+#pragma unroll
+  for (int k = 0; k < NOV; ++k) {
+    const int q = vt + 256 * k;
+    const int ty = q / C::TW, tx = q % C::TW;
+    const bool inq = q < C::TH * C::TW;
+    op[k] = C::PADF + (inq ? (C::NL + ty) * C::CWT + (C::NL + tx) : C::NL * C::CWT + C::NL);
+    ovm |= ((inq && tl.ty0 + ty < H && tl.tx0 + tx < W) ? 1u : 0u) << k;
+  }
+
+  // ---- state: one register array, layer 1 in the VALU waves and layer 2
+  // in the MFMA waves (the roles never meet in one wave)
+  constexpr int NBS = NB1V > NB2M ? NB1V : NB2M;
+  f4 st[NBS][C::MB];
+  float so[NOV][2];
+  const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * ca.vin_nstride : nullptr;
+  if (!mrole) read_hidden_state<C, NBS>(st, vm1, 1, rw, j, g, vin, c1, 0, gy0, gx0, W, HW, 4);
+  else read_hidden_state<C, NBS>(st, vm2, 2, rw, j, g, vin, c2, choff2, gy0, gx0, W, HW, 4);
+#pragma unroll
+  for (int k = 0; k < NOV; ++k) {
+    so[k][0] = so[k][1] = 0.f;
+    if (!mrole && vin && ((ovm >> k) & 1u)) {
+      const int q = vt + 256 * k;
+      const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
+#pragma unroll
+      for (int co = 0; co < 2; ++co)
+        if (co < cout) so[k][co] = vin[(size_t)(choffo + co) * HW + pix];
+    }
+  }
+
+  // ---- x staging over all 512 threads
+  const float* xclip = ca.x + (size_t)tl.n * ca.x_nstride;
+  float xpf[C::XPF];
+  auto load_x = [&](int tt) __attribute__((always_inline)) {
+    const float* xf = xclip + (size_t)tt * C::CIN * HW;
+#pragma unroll
+    for (int k = 0; k < C::XPF; ++k) {
+      const int e = tid + C::NT * k;
+      const int c = e / C::NPIX, rem = e % C::NPIX;
+      const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;
+      float v = 0.f;
+      if (e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = xf[(size_t)c * HW + (size_t)gy * W + gx];
+      xpf[k] = v;
+    }
+  };
+  auto store_x = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < C::XPF; ++k) {
+      const int e = tid + C::NT * k;
+      if (e < C::XN) xsf[(e / C::NPIX) * C::NPIXL + C::PADF + e % C::NPIX] = xpf[k];
+    }
+  };
+
+  const int p1base = C::PADF + C::CWT + 16 * rw + j;
+  const int p2base = C::PADF + 2 * C::CWT + 16 * rw + j;
+
+  // layer 1 on the VALU waves: MFMA + fire/reset -> S1 (f32)
+  auto layer1 = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < NB1V; ++i)
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m) st[i][m] *= leak;
+#pragma unroll 1
+    for (int q = 0; q < C::KS1; ++q) {
+      const float* fr = reinterpret_cast<const float*>(lds + Lo::FR1) + q * C::MB * 64 + lane;
+      float a[C::MB];
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
+      const int K = 4 * q + g;
+      const int tap = K / C::CIN, c = K - tap * C::CIN;
+      const int o = K < C::K1 ? c * C::NPIXL + tap_off(tap, C::CWT) : C::CIN * C::NPIXL;
+      float bv[NB1V];
+#pragma unroll
+      for (int i = 0; i < NB1V; ++i) bv[i] = xsf[p1base + 64 * i + o];
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int i = 0; i < NB1V; ++i) st[i][m] = mfma_f32(a[m], bv[i], st[i][m]);
+    }
+#pragma unroll
+    for (int i = 0; i < NB1V; ++i)
+      hidden_epilogue<C, false>(st[i], lds, 0, C::CWT + 16 * (rw + 4 * i) + j, (vm1 >> i) & 1u, g, theta, alpha,
+                                false, nullptr, c1, 0, gy0, gx0, tb);
+  };
+  // layer-2 fire/reset on the MFMA waves -> S2 (bf16)
+  auto fire2 = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < NB2M; ++i)
+      hidden_epilogue<C, true>(st[i], lds, C::SP2_OFF, 2 * C::CWT + 16 * (rw + 4 * i) + j, (vm2 >> i) & 1u, g,
+                               theta, alpha, false, nullptr, c2, choff2, gy0, gx0, tb);
+  };
+  // layer-2 MFMA on the MFMA waves: per tap, the operand loads of the two
+  // halves of the blocks are issued before their MFMAs
+  auto layer2 = [&]() __attribute__((always_inline)) {
+    static_assert(C::CH == 16, "specialised schedule assumes 16 hidden channels");
+#pragma unroll
+    for (int i = 0; i < NB2M; ++i) st[i][0] *= leak;
+    const f4* fr = reinterpret_cast<const f4*>(lds + Lo::FR2) + lane;
+#pragma unroll 1
+    for (int tau = 0; tau < 9; ++tau) {
+      const int to = tap_off(tau, C::CWT);
+      const f4 a = fr[tau * 64];
+      f4 bv[NB2M];
+#pragma unroll
+      for (int i = 0; i < NB2M; ++i)
+        bv[i] = *reinterpret_cast<const f4*>(s1f + (size_t)(p2base + 64 * i + to) * C::CH + 4 * g);
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+        for (int i = 0; i < NB2M; ++i) st[i][0] = mfma_f32(a[q4], bv[i][q4], st[i][0]);
+    }
+  };
+  // output layer on the VALU waves (frame tt), spikes of layer 2 from S2
+  auto output = [&](int tt) __attribute__((always_inline)) {
+    float u[NOV][2];
+#pragma unroll
+    for (int k = 0; k < NOV; ++k) { u[k][0] = leak * so[k][0]; u[k][1] = leak * so[k][1]; }
+#pragma unroll 1
+    for (int tau = 0; tau < 9; ++tau) {
+      const int to = tap_off(tau, C::CWT);
+#pragma unroll
+      for (int c8 = 0; c8 < C::CH / 8; ++c8) {
+        f4 wv[4];
+#pragma unroll
+        for (int z = 0; z < 4; ++z) wv[z] = *reinterpret_cast<const f4*>(wl + (tau * C::CH + 8 * c8) * 2 + 4 * z);
+#pragma unroll
+        for (int k = 0; k < NOV; ++k) {
+          const u4 rw4 = *reinterpret_cast<const u4*>(s2b + (size_t)(op[k] + to) * C::CH + 8 * c8);
+#pragma unroll
+          for (int z = 0; z < 4; ++z) {
+            const float s0 = __builtin_bit_cast(float, rw4[z] << 16);
+            const float sh = __builtin_bit_cast(float, rw4[z] & 0xffff0000u);
+            u[k][0] = fmaf(wv[z][0], s0, u[k][0]); u[k][1] = fmaf(wv[z][1], s0, u[k][1]);
+            u[k][0] = fmaf(wv[z][2], sh, u[k][0]); u[k][1] = fmaf(wv[z][3], sh, u[k][1]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NOV; ++k) {
+      const bool ok = (ovm >> k) & 1u;
+      const int q = vt + 256 * k;
+      const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
+#pragma unroll
+      for (int co = 0; co < 2; ++co) {
+        float v = u[k][co];
+        const float sp = bilif(v, theta, alpha, false);
+        so[k][co] = v;
+        if (ok && co < cout && ca.s_out)
+          reinterpret_cast<int8_t*>(ca.s_out)[(((size_t)tl.n * T + tt) * cout + co) * HW + pix] = (int8_t)sp;
+      }
+    }
+  };
+
+  load_x(0);
+  store_x();
+  if (T > 1) load_x(1);
+  __syncthreads();
+  for (int t = 0; t < T; ++t) {
+    // phase A
+    if (mrole) {
+      if (t > 0) fire2();
+    } else {
+      layer1();
+    }
+    __syncthreads();
+    if (t + 1 < T) store_x();
+    if (t + 2 < T) load_x(t + 2);
+    // phase B
+    if (mrole) {
+      layer2();
+    } else {
+      if (t > 0) output(t - 1);
+    }
+    __syncthreads();
+  }
+  if (mrole) fire2();
+  __syncthreads();
+  if (!mrole) output(T - 1);
+  if (ca.v_out) {
+    float* dst = ca.v_out + (size_t)tl.n * sumc * HW;
+    if (!mrole) {
+      write_hidden_state<C, NBS>(st, vm1, 1, rw, j, g, dst, c1, 0, gy0, gx0, W, HW, 4);
+#pragma unroll
+      for (int k = 0; k < NOV; ++k) {
+        if ((ovm >> k) & 1u) {
+          const int q = vt + 256 * k;
+          const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
+#pragma unroll
+          for (int co = 0; co < 2; ++co)
+            if (co < cout) dst[(size_t)(choffo + co) * HW + pix] = so[k][co];
+        }
+      }
+    } else {
+      write_hidden_state<C, NBS>(st, vm2, 2, rw, j, g, dst, c2, choff2, gy0, gx0, W, HW, 4);
+    }
+  }
+}
+
 // Process one tile over frames [0, T) of one clip.
 template <class C>
 __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl, char* lds) {
+  if constexpr (C::PIPE) {
+    run_tile_pipe<C>(na, ca, tl, lds);
+    return;
+  }
   using Lo = Layout<C>;
   float* const xsf = reinterpret_cast<float*>(lds + Lo::XS);
   uint16_t* const xsb = reinterpret_cast<uint16_t*>(lds + Lo::XS);
@@ -348,17 +664,43 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     ovm |= ((inq && gy < H && gx < W) ? 1u : 0u) << k;
   }
 
+  // output blocks of the MFMA form: canvas rows NL..NL+TH-1, interior columns
+  unsigned vmo = 0;
+  if constexpr (C::OMF) {
+#pragma unroll
+    for (int i = 0; i < C::NBO; ++i) {
+      const int b = wave + C::NW * i;
+      const int pr = C::NL * C::CWT + 16 * b + j;
+      const int row = pr / C::CWT, col = pr % C::CWT;
+      const int gy = gy0 + row, gx = gx0 + col;
+      const bool ok = b < C::NPBO && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW && gy < H && gx < W;
+      vmo |= (ok ? 1u : 0u) << i;
+    }
+  }
+
   // ---- state registers
   f4 st1[C::NB1][C::MB];
   f4 st2[C::NB2][C::MB];
   float so[C::NOUT][2];
+  f4 sob[C::NBO];           // output state, MFMA form: rows = channels (lanes g == 0)
   const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * ca.vin_nstride : nullptr;
   if constexpr (C::NH >= 1) read_hidden_state<C, C::NB1>(st1, vm1, 1, wave, j, g, vin, c1, 0, gy0, gx0, W, HW);
   if constexpr (C::NH >= 2) read_hidden_state<C, C::NB2>(st2, vm2, 2, wave, j, g, vin, c2, choff2, gy0, gx0, W, HW);
 #pragma unroll
+  for (int i = 0; i < C::NBO; ++i) {
+    sob[i] = f4{0.f, 0.f, 0.f, 0.f};
+    if (C::OMF && vin && g == 0 && ((vmo >> i) & 1u)) {
+      const int pr = C::NL * C::CWT + 16 * (wave + C::NW * i) + j;
+      const size_t pix = (size_t)(gy0 + pr / C::CWT) * W + (gx0 + pr % C::CWT);
+#pragma unroll
+      for (int co = 0; co < 2; ++co)
+        if (co < cout) sob[i][co] = vin[(size_t)(choffo + co) * HW + pix];
+    }
+  }
+#pragma unroll
   for (int k = 0; k < C::NOUT; ++k) {
     so[k][0] = so[k][1] = 0.f;
-    if (vin && ((ovm >> k) & 1u)) {
+    if (!C::OMF && vin && ((ovm >> k) & 1u)) {
       const int q = tid + C::NT * k;
       const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
 #pragma unroll
@@ -401,12 +743,22 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     if constexpr (C::NH >= 2) write_hidden_state<C, C::NB2>(st2, vm2, 2, wave, j, g, dst, c2, choff2, gy0, gx0, W, HW);
 #pragma unroll
     for (int k = 0; k < C::NOUT; ++k) {
-      if ((ovm >> k) & 1u) {
+      if (!C::OMF && ((ovm >> k) & 1u)) {
         const int q = tid + C::NT * k;
         const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
 #pragma unroll
         for (int co = 0; co < 2; ++co)
           if (co < cout) dst[(size_t)(choffo + co) * HW + pix] = so[k][co];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < C::NBO; ++i) {
+      if (C::OMF && g == 0 && ((vmo >> i) & 1u)) {
+        const int pr = C::NL * C::CWT + 16 * (wave + C::NW * i) + j;
+        const size_t pix = (size_t)(gy0 + pr / C::CWT) * W + (gx0 + pr % C::CWT);
+#pragma unroll
+        for (int co = 0; co < 2; ++co)
+          if (co < cout) dst[(size_t)(choffo + co) * HW + pix] = sob[i][co];
       }
     }
   };
@@ -487,7 +839,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
       for (int i = 0; i < C::NB1; ++i) {
         const int b = wave + C::NW * i;
-        hidden_epilogue<C>(st1[i], lds, C::CWT + 16 * b + j, (vm1 >> i) & 1u, g, theta, alpha, relaxed,
+        hidden_epilogue<C>(st1[i], lds, 0, C::CWT + 16 * b + j, (vm1 >> i) & 1u, g, theta, alpha, relaxed,
                            trace_t, c1, 0, gy0, gx0, tb);
       }
       __syncthreads();                                   // B1: s1 visible, xs free
@@ -554,14 +906,60 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
       for (int i = 0; i < C::NB2; ++i) {
         const int b = wave + C::NW * i;
-        hidden_epilogue<C>(st2[i], lds, 2 * C::CWT + 16 * b + j, (vm2 >> i) & 1u, g, theta, alpha, relaxed,
+        hidden_epilogue<C>(st2[i], lds, 0, 2 * C::CWT + 16 * b + j, (vm2 >> i) & 1u, g, theta, alpha, relaxed,
                            trace_t, c2, choff2, gy0, gx0, tb);
       }
       __syncthreads();                                   // B3: s2 visible
     }
 
-    // ================= output layer (VALU), weights broadcast from LDS
+    if constexpr (C::OMF) {
+      // ================= output layer on MFMA (BF16), K = tap * CH + ci
+      const int pobase = C::PADF + C::NL * C::CWT + 16 * wave + j;
+#pragma unroll
+      for (int i = 0; i < C::NBO; ++i) sob[i] *= leak;
+#pragma unroll 1
+      for (int q = 0; q < C::KSO; ++q) {
+        const u4 a = reinterpret_cast<const u4*>(lds + Lo::FR3)[q * 64 + lane];
+        int o;
+        if constexpr (C::CH == 32) {
+          o = tap_off(q, C::CWT) * C::CH + 8 * g;
+        } else {
+          int tau = 2 * q + (g >> 1);
+          tau = tau > 8 ? 8 : tau;
+          o = tap_off(tau, C::CWT) * C::CH + 8 * (g & 1);
+        }
+        u4 bv[C::NBO];
+#pragma unroll
+        for (int i = 0; i < C::NBO; ++i)
+          bv[i] = *reinterpret_cast<const u4*>(spb + (size_t)(pobase + 16 * C::NW * i) * C::CH + o);
+#pragma unroll
+        for (int i = 0; i < C::NBO; ++i) sob[i] = mfma_bf16(a, bv[i], sob[i]);
+      }
+      if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < C::NBO; ++i) {
+          const bool ok = (vmo >> i) & 1u;
+          const int pr = C::NL * C::CWT + 16 * (wave + C::NW * i) + j;
+          const int gy = gy0 + pr / C::CWT, gx = gx0 + pr % C::CWT;
+          const size_t pix = (size_t)gy * W + gx;
+#pragma unroll
+          for (int co = 0; co < 2; ++co) {
+            if (C::FULL && ok && co < cout && trace_t && tb.has(gy, gx))
+              trace_t[(size_t)(choffo + co) * tb.plane() + tb.idx(gy, gx)] = sob[i][co];
+            float v = sob[i][co];
+            const float sp = bilif(v, theta, alpha, false);
+            sob[i][co] = v;
+            if (ok && co < cout && ca.s_out) {
+              const size_t o = (((size_t)tl.n * T + t) * cout + co) * HW + pix;
+              if (C::FULL && ca.s_fp32) reinterpret_cast<float*>(ca.s_out)[o] = sp;
+              else reinterpret_cast<int8_t*>(ca.s_out)[o] = (int8_t)sp;
+            }
+          }
+        }
+      }
+    } else
     {
+      // ================= output layer (VALU), weights broadcast from LDS
       float u[C::NOUT][2];
 #pragma unroll
       for (int k = 0; k < C::NOUT; ++k) { u[k][0] = leak * so[k][0]; u[k][1] = leak * so[k][1]; }
@@ -653,6 +1051,7 @@ __device__ __forceinline__ void init_lds(const FwdNetArgs& na, char* lds) {
   unsigned* z = reinterpret_cast<unsigned*>(lds);
   for (int e = threadIdx.x; e < (C::XS_BYTES + C::SP_BYTES) / 4; e += C::NT) z[e] = 0u;
   load_weights<C>(na, lds);
+  load_out_frags<C>(na, lds);
 }
 
 // XCD-aware tile order: the hardware deals workgroups round-robin over the
@@ -765,11 +1164,8 @@ const Variant kVariants[] = {
     EVS_VARIANT(2, 3, 32, 1, 12, 32, 4, "L2 h32 bf16 12x32 w4"),
     // three-layer nets
     EVS_VARIANT_B(3, 3, 16, 0, 24, 32, 8, "L3 h16 f32 24x32 w8"),
-    EVS_VARIANT_B(3, 3, 16, 0, 30, 40, 8, "L3 h16 f32 30x40 w8"),
     EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
     EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
-    EVS_VARIANT(3, 3, 16, 0, 12, 36, 4, "L3 h16 f32 12x36 w4"),
-    EVS_VARIANT(3, 3, 16, 0, 10, 32, 4, "L3 h16 f32 10x32 w4"),
     EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40 w8"),
     EVS_VARIANT(3, 3, 16, 1, 16, 32, 4, "L3 h16 bf16 16x32 w4"),
     EVS_VARIANT(3, 3, 32, 1, 24, 32, 8, "L3 h32 bf16 24x32 w8"),
