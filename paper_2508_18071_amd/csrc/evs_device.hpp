@@ -17,7 +17,10 @@ __device__ inline float bilif(float& v, float theta, float alpha, bool relaxed) 
   if (relaxed) {
     s = sigm_fast(alpha * (h - theta)) - sigm_fast(alpha * (-h - theta));
   } else {
-    s = h >= theta ? 1.0f : (h <= -theta ? -1.0f : 0.0f);
+    // h >= theta -> +1, h <= -theta -> -1, else 0 (theta > 0; a NaN h gives 0):
+    // one compare of |h| and the sign of h copied onto 1.0
+    const float sgn1 = __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, h) & 0x80000000u) | 0x3f800000u);
+    s = __builtin_fabsf(h) >= theta ? sgn1 : 0.0f;
   }
   v = fmaf(-theta, s, h);
   return s;

@@ -9,7 +9,8 @@ trajectory):
     |h_ref -+ theta| < 1e-3 (quantised reference for BF16);
   * the emitted output spikes equal the fire rule applied to the device's
     own potentials, bit for bit.
-Invariants (zero input, oddness, chunking, tile shape, batching) are exact.
+Invariants (zero input, chunking, tile shape, batching) are exact; oddness holds
+for spikes and to float32 rounding for potentials.
 """
 
 import numpy as np
@@ -100,27 +101,23 @@ def test_zero_input_gives_no_spikes(evs):
     assert float(out["h"].abs().max()) == 0.0
 
 
-def test_oddness_is_bitwise_fp32(evs):
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-6), ("bf16", 1e-5)])
+def test_oddness_up_to_accumulator_rounding(evs, prec, bound):
+    """Negating the input negates every potential and spike (the oracle's
+    oddness pin).  The layers that read spikes run on the bf16 matrix core
+    (FP32 nets through the exact three-part weight split), whose FP32
+    accumulation on gfx950 is not exactly sign-symmetric: potentials agree
+    to float32 rounding and spikes may differ only where the potential sits
+    at a threshold."""
     x, ws = make_inputs((3, 16, 16, 2), 6, 45, 61)
-    _, _, a = _run(evs, (3, 16, 16, 2), "fp32", x, ws)
-    _, _, b = _run(evs, (3, 16, 16, 2), "fp32", -x, ws)
-    assert torch.equal(b["s"], -a["s"])
-    assert torch.equal(b["h"], -a["h"])
-    assert int(a["s"].abs().sum()) > 0
-
-
-def test_oddness_bf16_up_to_accumulator_rounding(evs):
-    """BF16 operands round symmetrically, but the BF16 MFMA accumulation on
-    gfx950 is not exactly sign-symmetric: potentials agree to a few float32
-    ulps and spikes may differ only where the potential sits at a threshold."""
-    x, ws = make_inputs((3, 16, 16, 2), 6, 45, 61)
-    _, _, a = _run(evs, (3, 16, 16, 2), "bf16", x, ws)
-    _, _, b = _run(evs, (3, 16, 16, 2), "bf16", -x, ws)
+    _, _, a = _run(evs, (3, 16, 16, 2), prec, x, ws)
+    _, _, b = _run(evs, (3, 16, 16, 2), prec, -x, ws)
     d = (b["h"] + a["h"]).abs()
     rel = float(d.max() / a["h"].abs().max())
-    print(f"  bf16 oddness: max |h(-x) + h(x)| / max|h| = {rel:.3e}, "
+    print(f"  {prec} oddness: max |h(-x) + h(x)| / max|h| = {rel:.3e}, "
           f"differing potentials {int((d > 0).sum())} of {d.numel()}", flush=True)
-    assert rel <= 1e-5
+    assert rel <= bound
+    assert int(a["s"].abs().sum()) > 0
     mism = b["s"] != -a["s"]
     if mism.any():
         hl = a["h"][:, :, -2:][mism]
