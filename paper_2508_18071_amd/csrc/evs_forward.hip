@@ -86,8 +86,17 @@ struct Cfg {
   static constexpr int K1 = 9 * CIN;
   static constexpr int KS1 = BF16 ? cdiv(K1, 32) : cdiv(K1, 4);
   static constexpr int XELEM = BF16 ? 2 : 4;
-  // x planes plus one all-zero plane read by the padded K slots of layer 1
-  static constexpr int XS_BYTES = align16((CIN + 1) * NPIXL * XELEM);
+  // x planes plus one all-zero plane read by the padded K slots of layer 1;
+  // FP32 nets with hidden layers fill them by direct global -> LDS loads of
+  // 64-pixel chunks into two buffers (frame t+1 lands while t is read)
+  static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX;
+  static constexpr int XCK = CIN * CHT;              // x chunks: one canvas row of one plane
+  static constexpr int XPW = cdiv(XCK, NW);          // chunk loads per wave and frame
+  // x buffer: front pad, CIN planes and the zero plane back to back (plane
+  // stride NPIX), then room for the neighbourhood of the junk pixel
+  static constexpr int XPL = NPIX;
+  static constexpr int XS1 = align16((PADF + (CIN + 1) * XPL + 2 * CWT + 4) * XELEM);
+  static constexpr int XS_BYTES = XS1 * (XDMA ? 2 : 1);
   static constexpr int SELEM = S16 ? 2 : 4;
   static constexpr int SP1_BYTES = NH >= 1 ? align16(NPIXL * CH * SELEM) : 0;
   // separate layer-2 spike buffer: saves two barriers per frame
@@ -98,6 +107,7 @@ struct Cfg {
   static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
   static_assert(NB1 <= 32 && NB2 <= 32 && NBO <= 32 && NOUT <= 32, "mask words overflow");
   static_assert(PADF + JP + CWT + 1 < NPIXL, "junk pixel neighbourhood outside the planes");
+  static_assert(CWT <= 64, "a canvas row must fit one wave");
 };
 
 __device__ inline f4 mfma_f32(float a, float b, f4 c) {
@@ -107,6 +117,12 @@ __device__ inline f4 mfma_bf16(u4 a, u4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
                                                  __builtin_bit_cast(bf8, b), c, 0, 0, 0);
 }
+
+// s_waitcnt operand that waits until at most N vector memory operations of
+// this wave are outstanding (expcnt and lgkmcnt left at their maxima)
+template <int N>
+constexpr int kVmcntEncoded = (N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14);
+static_assert(kVmcntEncoded<0> == 0x0f70, "s_waitcnt encoding");
 
 __device__ inline unsigned pack_bf16x2(float lo, float hi) {
   // both values are exact in bf16: take the upper halves of the floats
@@ -150,7 +166,7 @@ __device__ __forceinline__ void kslot(int kb, int g, int& tau, int& cib) {
 // LDS layout of one workgroup (byte offsets).
 template <class C>
 struct Layout {
-  static constexpr int XS = 0;                                  // x tile [CIN+1][NPIXL]
+  static constexpr int XS = 0;                                  // x tile(s) [pad | CIN+1 planes | tail]
   static constexpr int SP = XS + C::XS_BYTES;                   // spikes [NPIXL][CH] (x2 if SEP)
   static constexpr int WL = SP + C::SP_BYTES;                   // VALU output weights [9][CI][2] f32
   static constexpr int FR1 = WL + align16(C::WL_FLOATS * 4);    // layer-1 A fragments
@@ -160,7 +176,8 @@ struct Layout {
       C::NH >= 2 ? (C::S16 ? C::KB * C::NSP * C::MB * 64 * 16 : 9 * (C::CH / 16) * C::MB * 64 * 16) : 0;
   static constexpr int FR3 = FR2 + FR2_BYTES;                   // output-layer A fragments
   static constexpr int FR3_BYTES = C::OMF ? C::KB * 64 * 16 : 0;
-  static constexpr int TOTAL = FR3 + FR3_BYTES;
+  static constexpr int XDUMMY = FR3 + FR3_BYTES;                // target of the padding x loads
+  static constexpr int TOTAL = XDUMMY + (C::XDMA ? 256 : 0);
   static_assert(TOTAL <= 160 * 1024, "tile does not fit in LDS");
 };
 
@@ -259,6 +276,11 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
 }
 
 // ------------------------------------------------------------------ tile
+// Workgroup barrier for LDS data: completes this wave's LDS operations and
+// meets the other waves.  Unlike __syncthreads() it leaves outstanding
+// global -> LDS loads alone (the x prefetch is waited for by count).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 struct Tile {
   int n, ty0, tx0;
 };
@@ -394,11 +416,10 @@ __device__ __forceinline__ void read_hidden_state(f4 (&st)[NB][C::MB], unsigned 
 template <class C>
 __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl, char* lds) {
   using Lo = Layout<C>;
-  float* const xsf = reinterpret_cast<float*>(lds + Lo::XS);
   uint16_t* const xsb = reinterpret_cast<uint16_t*>(lds + Lo::XS);
-  const float* const spf = reinterpret_cast<const float*>(lds + Lo::SP);
-  const uint16_t* const spb = reinterpret_cast<const uint16_t*>(lds + Lo::SP);
-  const uint16_t* const spb2 = reinterpret_cast<const uint16_t*>(lds + Lo::SP + C::S2OFF);
+  float* const xsf = reinterpret_cast<float*>(lds + Lo::XS);
+  const char* const sp1 = lds + Lo::SP;              // layer-1 spikes (and layer-2 ones unless SEP)
+  const char* const sp2 = lds + Lo::SP + C::S2OFF;   // layer-2 spikes
   const float* const wl = reinterpret_cast<const float*>(lds + Lo::WL);
 
   const int tid = threadIdx.x;
@@ -430,11 +451,16 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     a2[i] = C::NH >= 2 ? block_pixel<C>(2, wave + C::NW * i, j, gy0, gx0, H, W, ok) : 0;
     vm2 |= (ok ? 1u : 0u) << i;
   }
+  // output neurons (MFMA form): lane group g < 2 holds channel g of pixel j;
+  // oo = its offset inside one frame of s_out (-1: not stored)
+  int oo[C::NBO];
 #pragma unroll
   for (int i = 0; i < C::NBO; ++i) {
     bool ok = false;
     ao[i] = C::OMF ? block_pixel<C>(C::NL, wave + C::NW * i, j, gy0, gx0, H, W, ok) : 0;
     vmo |= (ok ? 1u : 0u) << i;
+    const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
+    oo[i] = (ok && g < cout) ? g * (int)HW + (gy0 + row) * W + (gx0 + col) : -1;
   }
   // ---- output pixels of this lane (VALU output layer)
   int op[C::NOUT];
@@ -453,18 +479,15 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   f4 st1[C::NB1][C::MB];
   f4 st2[C::NB2][C::MB];
   float so[C::NOUT][2];
-  f4 sob[C::NBO];           // output state, MFMA form: lane group g = channel, row 0 = potential
+  float vo[C::NBO];         // output potential (MFMA form)
   const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * ca.vin_nstride : nullptr;
   const float fill = C::RELAX ? 0.f : __builtin_nanf("");
   if constexpr (C::NH >= 1) read_hidden_state<C, C::NB1>(st1, vm1, a1, g, vin, c1, 0, gy0, gx0, W, HW, fill);
   if constexpr (C::NH >= 2) read_hidden_state<C, C::NB2>(st2, vm2, a2, g, vin, c2, choff2, gy0, gx0, W, HW, fill);
 #pragma unroll
   for (int i = 0; i < C::NBO; ++i) {
-    sob[i] = f4{0.f, 0.f, 0.f, 0.f};
-    if (C::OMF && vin && g < cout && ((vmo >> i) & 1u)) {
-      const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
-      sob[i][0] = vin[(size_t)(choffo + g) * HW + (size_t)(gy0 + row) * W + (gx0 + col)];
-    }
+    vo[i] = 0.f;
+    if (C::OMF && vin && oo[i] >= 0) vo[i] = vin[(size_t)choffo * HW + oo[i]];
   }
 #pragma unroll
   for (int k = 0; k < C::NOUT; ++k) {
@@ -478,32 +501,76 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     }
   }
 
-  // ---- x staging (register prefetch of the next frame)
+  // ---- x staging
   const float* xclip = ca.x + (size_t)tl.n * ca.x_nstride;
-  float xpf[C::XPF];
-#define EVS_LOAD_X(tt)                                                                          \
-  do {                                                                                          \
-    const float* xf = xclip + (size_t)(tt) * C::CIN * HW;                                       \
-    _Pragma("unroll") for (int k = 0; k < C::XPF; ++k) {                                        \
-      const int e = tid + C::NT * k;                                                            \
-      const int c = e / C::NPIX, rem = e % C::NPIX;                                             \
-      const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;                               \
-      float v = 0.f;                                                                            \
-      if (e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = xf[(size_t)c * HW + (size_t)gy * W + gx]; \
-      xpf[k] = v;                                                                               \
-    }                                                                                           \
-  } while (0)
-#define EVS_STORE_X()                                                                           \
-  do {                                                                                          \
-    _Pragma("unroll") for (int k = 0; k < C::XPF; ++k) {                                        \
-      const int e = tid + C::NT * k;                                                            \
-      if (e < C::XN) {                                                                          \
-        const int c = e / C::NPIX, rem = e % C::NPIX;                                           \
-        if constexpr (C::BF16) xsb[c * C::NPIXL + C::PADF + rem] = f32_to_bf16_rne(xpf[k]);    \
-        else xsf[c * C::NPIXL + C::PADF + rem] = xpf[k];                                        \
-      }                                                                                         \
-    }                                                                                           \
-  } while (0)
+  // (a) FP32 nets: direct global -> LDS buffer loads into two x buffers.
+  // Chunk wave + NW*k is one canvas row of one x plane, lane = canvas
+  // column.  Every wave issues exactly XPW loads per frame (chunks past the
+  // last and rows outside the image read through an empty buffer, columns
+  // outside the image use an offset past the end: both return zero), so a
+  // frame's loads can be waited for by count while the next frame's are in
+  // flight.  The per-lane offset is the same for every chunk.
+  const unsigned xv = (gx0 + lane >= 0 && gx0 + lane < W) ? (unsigned)(gx0 + lane) * 4u : 0x80000000u;
+  auto issue_x = [&](int tt, int buf) __attribute__((always_inline)) {
+    if constexpr (C::XDMA) {
+      float* const xf = const_cast<float*>(xclip + (size_t)tt * C::CIN * HW);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(xf, (short)0, (int)(C::CIN * HW * 4), 0x00020000);
+      const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(xf, (short)0, 0, 0x00020000);
+      if (lane < C::CWT) {
+#pragma unroll
+        for (int k = 0; k < C::XPW; ++k) {
+          const int id = wave + C::NW * k;
+          const int c = id / C::CHT, r = id % C::CHT;
+          const bool real = id < C::XCK;
+          const bool row_in = real && gy0 + r >= 0 && gy0 + r < H;
+          const int dst = real ? Lo::XS + buf * C::XS1 + (C::PADF + id * C::CWT) * 4 : Lo::XDUMMY;
+          const unsigned so = row_in ? (unsigned)(c * (int)HW + (gy0 + r) * W) * 4u : 0u;
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(row_in ? rs : rz, (__attribute__((address_space(3))) void*)(lds + dst),
+                                                   4, xv, so, 0, 0);
+        }
+      }
+    }
+  };
+  // (b) other nets: register prefetch of the next frame
+  float xpf[C::XDMA ? 1 : C::XPF];
+  auto load_x = [&](int tt) __attribute__((always_inline)) {
+    if constexpr (!C::XDMA) {
+      const float* xf = xclip + (size_t)tt * C::CIN * HW;
+#pragma unroll
+      for (int k = 0; k < C::XPF; ++k) {
+        const int e = tid + C::NT * k;
+        const int c = e / C::NPIX, rem = e % C::NPIX;
+        const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;
+        float v = 0.f;
+        if (e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = xf[(size_t)c * HW + (size_t)gy * W + gx];
+        xpf[k] = v;
+      }
+    }
+  };
+  auto store_x = [&]() __attribute__((always_inline)) {
+    if constexpr (!C::XDMA) {
+#pragma unroll
+      for (int k = 0; k < C::XPF; ++k) {
+        const int e = tid + C::NT * k;
+        if (e < C::XN) {
+          const int c = e / C::NPIX, rem = e % C::NPIX;
+          if constexpr (C::BF16) xsb[c * C::XPL + C::PADF + rem] = f32_to_bf16_rne(xpf[k]);
+          else xsf[c * C::XPL + C::PADF + rem] = xpf[k];
+        }
+      }
+    }
+  };
+
+  // per-lane x-plane offsets of the layer-1 k-steps (FP32: K = 4q + g)
+  int o1[C::BF16 ? 1 : C::KS1];
+  if constexpr (!C::BF16) {
+#pragma unroll
+    for (int q = 0; q < C::KS1; ++q) {
+      const int K = 4 * q + g;
+      const int tap = K / C::CIN, c = K - tap * C::CIN;
+      o1[q] = K < C::K1 ? c * C::XPL + tap_off(tap, C::CWT) : C::CIN * C::XPL;
+    }
+  }
 
   const int nseg = ca.ckpt_every > 0 ? cdiv(T, ca.ckpt_every) : 0;
   const TraceBox tb{ca.tb_y0, ca.tb_x0, ca.tb_h, ca.tb_w};
@@ -521,21 +588,36 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       }
     }
 #pragma unroll
-    for (int i = 0; i < C::NBO; ++i) {
-      if (C::OMF && g < cout && ((vmo >> i) & 1u)) {
-        const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
-        dst[(size_t)(choffo + g) * HW + (size_t)(gy0 + row) * W + (gx0 + col)] = sob[i][0];
-      }
-    }
+    for (int i = 0; i < C::NBO; ++i)
+      if (C::OMF && oo[i] >= 0) dst[(size_t)choffo * HW + oo[i]] = vo[i];
   };
 
-  // ---- prologue: frame 0 into LDS, frame 1 into registers
-  EVS_LOAD_X(0);
-  EVS_STORE_X();
-  if (T > 1) EVS_LOAD_X(1);
-  __syncthreads();
+  // ---- prologue: frame 0 into LDS, frame 1 in flight (DMA) or in registers
+  if constexpr (C::XDMA) {
+    issue_x(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (T > 1) issue_x(1, 1);
+  } else {
+    load_x(0);
+    store_x();
+    if (T > 1) load_x(1);
+    __syncthreads();
+  }
 
   for (int t = 0; t < T; ++t) {
+    // block pixel indices, opaque to the optimiser inside the frame loop:
+    // each (block, k-step) LDS address is then formed when used instead of
+    // being hoisted out of the loop into registers of its own
+#pragma unroll
+    for (int i = 0; i < C::NB1; ++i) asm volatile("" : "+v"(a1[i]));
+#pragma unroll
+    for (int i = 0; i < C::NB2; ++i) asm volatile("" : "+v"(a2[i]));
+#pragma unroll
+    for (int i = 0; i < C::NBO; ++i) asm volatile("" : "+v"(ao[i]));
+    const int (&e1)[C::NB1] = a1;
+    const int (&e2)[C::NB2] = a2;
+    const int (&eo)[C::NBO] = ao;
     float* trace_t = nullptr;
     if constexpr (C::FULL) {
       if (ca.ckpt && (t % ca.ckpt_every) == 0)
@@ -550,24 +632,29 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       for (int i = 0; i < C::NB1; ++i)
 #pragma unroll
         for (int m = 0; m < C::MB; ++m) st1[i][m] *= leak;
-#pragma unroll 1
-      for (int q = 0; q < C::KS1; ++q) {
-        if constexpr (!C::BF16) {
-          const float* fr = reinterpret_cast<const float*>(lds + Lo::FR1) + q * C::MB * 64 + lane;
-          float a[C::MB];
+      if constexpr (!C::BF16) {
+        // f32 MFMA; the operands of k-step q+1 load while those of q multiply
+        const float* xb = reinterpret_cast<const float*>(lds + Lo::XS + (C::XDMA ? (t & 1) * C::XS1 : 0));
+        const float* fr1 = reinterpret_cast<const float*>(lds + Lo::FR1) + lane;
+        float bq[2][C::NB1], aq[2][C::MB];
+        auto ld1 = [&](int q, int s) __attribute__((always_inline)) {
 #pragma unroll
-          for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
-          const int K = 4 * q + g;
-          const int tap = K / C::CIN, c = K - tap * C::CIN;
-          const int o = K < C::K1 ? c * C::NPIXL + tap_off(tap, C::CWT) : C::CIN * C::NPIXL;
-          float bv[C::NB1];
+          for (int m = 0; m < C::MB; ++m) aq[s][m] = fr1[(q * C::MB + m) * 64];
 #pragma unroll
-          for (int i = 0; i < C::NB1; ++i) bv[i] = xsf[a1[i] + o];
+          for (int i = 0; i < C::NB1; ++i) bq[s][i] = xb[e1[i] + o1[q]];
+        };
+        ld1(0, 0);
+#pragma unroll
+        for (int q = 0; q < C::KS1; ++q) {
+          if (q + 1 < C::KS1) ld1(q + 1, (q + 1) & 1);
 #pragma unroll
           for (int m = 0; m < C::MB; ++m)
 #pragma unroll
-            for (int i = 0; i < C::NB1; ++i) st1[i][m] = mfma_f32(a[m], bv[i], st1[i][m]);
-        } else {
+            for (int i = 0; i < C::NB1; ++i) st1[i][m] = mfma_f32(aq[q & 1][m], bq[q & 1][i], st1[i][m]);
+        }
+      } else {
+#pragma unroll 1
+        for (int q = 0; q < C::KS1; ++q) {
           const u4* fr = reinterpret_cast<const u4*>(lds + Lo::FR1) + q * C::MB * 64 + lane;
           u4 a[C::MB];
 #pragma unroll
@@ -577,7 +664,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           for (int e = 0; e < 8; ++e) {
             const int K = 32 * q + 8 * g + e;
             const int tap = K / C::CIN, c = K - tap * C::CIN;
-            o[e] = K < C::K1 ? c * C::NPIXL + tap_off(tap, C::CWT) : C::CIN * C::NPIXL;
+            o[e] = K < C::K1 ? c * C::XPL + tap_off(tap, C::CWT) : C::CIN * C::XPL;
           }
           u4 bv[C::NB1];
 #pragma unroll
@@ -585,7 +672,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             unsigned wd[4];
 #pragma unroll
             for (int e2 = 0; e2 < 4; ++e2) {
-              const unsigned r0 = xsb[a1[i] + o[2 * e2]], r1 = xsb[a1[i] + o[2 * e2 + 1]];
+              const unsigned r0 = xsb[e1[i] + o[2 * e2]], r1 = xsb[e1[i] + o[2 * e2 + 1]];
               wd[e2] = r0 | (r1 << 16);
             }
             bv[i] = u4{wd[0], wd[1], wd[2], wd[3]};
@@ -598,11 +685,18 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       }
 #pragma unroll
       for (int i = 0; i < C::NB1; ++i)
-        hidden_epilogue<C>(st1[i], lds, 0, a1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, c1, 0, gy0,
+        hidden_epilogue<C>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, c1, 0, gy0,
                            gx0, tb);
-      __syncthreads();                                   // B1: s1 visible, xs free
-      if (t + 1 < T) EVS_STORE_X();
-      if (t + 2 < T) EVS_LOAD_X(t + 2);
+      lds_barrier();                                   // B1: s1 visible, x buffer (t & 1) free
+      if constexpr (C::XDMA) {
+        // three-layer nets issue after the layer-2 epilogue: the compiler
+        // orders every LDS store after LDS DMA still in flight, and the
+        // output layer + next layer-1 MFMAs are the longest store-free stretch
+        if (C::NH == 1 && t + 2 < T) issue_x(t + 2, t & 1);
+      } else {
+        if (t + 1 < T) store_x();
+        if (t + 2 < T) load_x(t + 2);
+      }
     }
 
     if constexpr (C::NH >= 2) {
@@ -612,28 +706,34 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
         for (int m = 0; m < C::MB; ++m) st2[i][m] *= leak;
       if constexpr (C::S16) {
-        // spike fragment of k-step kb loaded once, multiplied by the NSP weight parts
-#pragma unroll 1
-        for (int kb = 0; kb < C::KB; ++kb) {
+        // the spike fragment of k-step kb is loaded once and multiplied by
+        // the NSP weight parts; k-step kb+1 loads while kb multiplies
+        const u4* fr2 = reinterpret_cast<const u4*>(lds + Lo::FR2) + lane;
+        u4 bq[2][C::NB2], aq[2][C::NSP][C::MB];
+        auto ld2 = [&](int kb, int s) __attribute__((always_inline)) {
           int tau, cib;
           kslot<C::CH>(kb, g, tau, cib);
-          const int o = tap_off(tau > 8 ? 8 : tau, C::CWT) * C::CH + cib;   // tap 9: zero weights
-          u4 bv[C::NB2];
+          const int o = (tap_off(tau > 8 ? 8 : tau, C::CWT) * C::CH + cib) * 2;   // tap 9: zero weights
 #pragma unroll
-          for (int i = 0; i < C::NB2; ++i) bv[i] = *reinterpret_cast<const u4*>(spb + (size_t)a2[i] * C::CH + o);
+          for (int i = 0; i < C::NB2; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sp1 + e2[i] * C::CH * 2 + o);
 #pragma unroll
-          for (int p = 0; p < C::NSP; ++p) {
-            const u4* fr = reinterpret_cast<const u4*>(lds + Lo::FR2) + (kb * C::NSP + p) * C::MB * 64 + lane;
-            u4 a[C::MB];
+          for (int p = 0; p < C::NSP; ++p)
 #pragma unroll
-            for (int m = 0; m < C::MB; ++m) a[m] = fr[m * 64];
+            for (int m = 0; m < C::MB; ++m) aq[s][p][m] = fr2[((kb * C::NSP + p) * C::MB + m) * 64];
+        };
+        ld2(0, 0);
+#pragma unroll
+        for (int kb = 0; kb < C::KB; ++kb) {
+          if (kb + 1 < C::KB) ld2(kb + 1, (kb + 1) & 1);
+#pragma unroll
+          for (int p = 0; p < C::NSP; ++p)
 #pragma unroll
             for (int m = 0; m < C::MB; ++m)
 #pragma unroll
-              for (int i = 0; i < C::NB2; ++i) st2[i][m] = mfma_bf16(a[m], bv[i], st2[i][m]);
-          }
+              for (int i = 0; i < C::NB2; ++i) st2[i][m] = mfma_bf16(aq[kb & 1][p][m], bq[kb & 1][i], st2[i][m]);
         }
       } else {
+        const float* spf = reinterpret_cast<const float*>(sp1);
 #pragma unroll 1
         for (int tau = 0; tau < 9; ++tau) {
           const int to = tap_off(tau, C::CWT);
@@ -647,7 +747,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             f4 bv[C::NB2];
 #pragma unroll
             for (int i = 0; i < C::NB2; ++i)
-              bv[i] = *reinterpret_cast<const f4*>(spf + (size_t)(a2[i] + to) * C::CH + 16 * hh + 4 * g);
+              bv[i] = *reinterpret_cast<const f4*>(spf + (size_t)(e2[i] + to) * C::CH + 16 * hh + 4 * g);
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4)
 #pragma unroll
@@ -657,48 +757,64 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           }
         }
       }
-      if constexpr (!C::SEP) __syncthreads();            // B2: all reads of s1 done
+      if constexpr (!C::SEP) lds_barrier();            // B2: all reads of s1 done
 #pragma unroll
       for (int i = 0; i < C::NB2; ++i)
-        hidden_epilogue<C>(st2[i], lds, C::S2OFF, a2[i], (vm2 >> i) & 1u, g, theta, alpha, relaxed, trace_t, c2,
+        hidden_epilogue<C>(st2[i], lds, C::S2OFF, e2[i], (vm2 >> i) & 1u, g, theta, alpha, relaxed, trace_t, c2,
                            choff2, gy0, gx0, tb);
-      __syncthreads();                                   // B3: s2 visible
+      if constexpr (C::XDMA) {
+        if (t + 2 < T) issue_x(t + 2, t & 1);
+        // x(t+1) was issued one frame ago: wait for it, not for x(t+2)
+        if (t + 2 < T) __builtin_amdgcn_s_waitcnt(kVmcntEncoded<C::XPW>);
+        else __builtin_amdgcn_s_waitcnt(0);
+      }
+      lds_barrier();                                   // B3: s2 visible
+    } else if constexpr (C::XDMA) {
+      if (t + 2 < T) __builtin_amdgcn_s_waitcnt(kVmcntEncoded<C::XPW>);
+      else __builtin_amdgcn_s_waitcnt(0);
     }
 
     if constexpr (C::OMF) {
       // ================= output layer on MFMA: rows 4co + p, K = tap * CH + ci
-      const uint16_t* const so_b = C::NH == 2 ? spb2 : spb;
+      const char* const sob = C::NH == 2 ? sp2 : sp1;
+      const u4* fr3 = reinterpret_cast<const u4*>(lds + Lo::FR3) + lane;
+      f4 acc[C::NBO];
 #pragma unroll
-      for (int i = 0; i < C::NBO; ++i) sob[i] = f4{leak * sob[i][0], 0.f, 0.f, 0.f};
-#pragma unroll 1
-      for (int kb = 0; kb < C::KB; ++kb) {
-        const u4 a = reinterpret_cast<const u4*>(lds + Lo::FR3)[kb * 64 + lane];
+      for (int i = 0; i < C::NBO; ++i) acc[i] = f4{leak * vo[i], 0.f, 0.f, 0.f};
+      u4 bq[2][C::NBO], aq[2];
+      auto ld3 = [&](int kb, int s) __attribute__((always_inline)) {
         int tau, cib;
         kslot<C::CH>(kb, g, tau, cib);
-        const int o = tap_off(tau > 8 ? 8 : tau, C::CWT) * C::CH + cib;
-        u4 bv[C::NBO];
+        const int o = (tap_off(tau > 8 ? 8 : tau, C::CWT) * C::CH + cib) * 2;
 #pragma unroll
-        for (int i = 0; i < C::NBO; ++i) bv[i] = *reinterpret_cast<const u4*>(so_b + (size_t)ao[i] * C::CH + o);
+        for (int i = 0; i < C::NBO; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sob + eo[i] * C::CH * 2 + o);
+        aq[s] = fr3[kb * 64];
+      };
+      ld3(0, 0);
 #pragma unroll
-        for (int i = 0; i < C::NBO; ++i) sob[i] = mfma_bf16(a, bv[i], sob[i]);
+      for (int kb = 0; kb < C::KB; ++kb) {
+        if (kb + 1 < C::KB) ld3(kb + 1, (kb + 1) & 1);
+#pragma unroll
+        for (int i = 0; i < C::NBO; ++i) acc[i] = mfma_bf16(aq[kb & 1], bq[kb & 1][i], acc[i]);
       }
       if (g < 2) {
         // lanes of group g hold output channel g of pixel j
+        int8_t* const s8 = reinterpret_cast<int8_t*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
+        float* const s32 = reinterpret_cast<float*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
 #pragma unroll
         for (int i = 0; i < C::NBO; ++i) {
-          const bool ok = ((vmo >> i) & 1u) && g < cout;
-          const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
-          const int gy = gy0 + row, gx = gx0 + col;
-          const float h = C::NSP == 3 ? (sob[i][0] + sob[i][1]) + sob[i][2] : sob[i][0];
-          if (C::FULL && ok && trace_t && tb.has(gy, gx))
-            trace_t[(size_t)(choffo + g) * tb.plane() + tb.idx(gy, gx)] = h;
+          const float h = C::NSP == 3 ? (acc[i][0] + acc[i][1]) + acc[i][2] : acc[i][0];
+          if (C::FULL && oo[i] >= 0 && trace_t) {
+            const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
+            const int gy = gy0 + row, gx = gx0 + col;
+            if (tb.has(gy, gx)) trace_t[(size_t)(choffo + g) * tb.plane() + tb.idx(gy, gx)] = h;
+          }
           float v = h;
           const float sp = bilif(v, theta, alpha, false);
-          sob[i][0] = v;
-          if (ok && ca.s_out) {
-            const size_t o = (((size_t)tl.n * T + t) * cout + g) * HW + (size_t)gy * W + gx;
-            if (C::FULL && ca.s_fp32) reinterpret_cast<float*>(ca.s_out)[o] = sp;
-            else reinterpret_cast<int8_t*>(ca.s_out)[o] = (int8_t)sp;
+          vo[i] = v;
+          if (oo[i] >= 0 && ca.s_out) {
+            if (C::FULL && ca.s_fp32) s32[oo[i]] = sp;
+            else s8[oo[i]] = (int8_t)sp;
           }
         }
       }
@@ -716,13 +832,13 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             const float w0 = wl[(tau * C::CIN + c) * 2], w1 = wl[(tau * C::CIN + c) * 2 + 1];
 #pragma unroll
             for (int k = 0; k < C::NOUT; ++k) {
-              const float xv = xsf[c * C::NPIXL + op[k] + to];
+              const float xv = xsf[c * C::XPL + op[k] + to];
               u[k][0] = fmaf(w0, xv, u[k][0]);
               u[k][1] = fmaf(w1, xv, u[k][1]);
             }
           }
         } else {
-          const float* sfin = reinterpret_cast<const float*>(lds + Lo::SP + C::S2OFF);
+          const float* sfin = reinterpret_cast<const float*>(sp2);
 #pragma unroll
           for (int c4 = 0; c4 < C::CH / 4; ++c4) {
             const f4 wa = *reinterpret_cast<const f4*>(wl + (tau * C::CH + 4 * c4) * 2);
@@ -761,17 +877,16 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       }
     }
     if constexpr (C::NH == 0) {
-      __syncthreads();
-      if (t + 1 < T) EVS_STORE_X();
-      if (t + 2 < T) EVS_LOAD_X(t + 2);
+      lds_barrier();
+      if (t + 1 < T) store_x();
+      if (t + 2 < T) load_x(t + 2);
     }
     // B4: spikes / xs consumed before the next frame overwrites them (the
     // separate layer-2 buffer makes B3 of the next frame the guard)
-    if constexpr (!C::SEP) __syncthreads();
+    if constexpr (!C::SEP) lds_barrier();
   }
+  if constexpr (C::XDMA) __builtin_amdgcn_s_waitcnt(0);
   if (ca.v_out) write_state(ca.v_out + (size_t)tl.n * sumc * HW);
-#undef EVS_LOAD_X
-#undef EVS_STORE_X
 }
 
 template <class C>
@@ -891,7 +1006,7 @@ const Variant kVariants[] = {
     EVS_VARIANT(2, 3, 16, 1, 30, 40, 8, "L2 h16 bf16 30x40 w8"),
     // two-layer nets with hidden width <= 32
     EVS_VARIANT_R(2, 3, 32, 22, 32, 8, "L2 h32 f32 22x32 w8"),
-    EVS_VARIANT(2, 3, 32, 0, 30, 40, 8, "L2 h32 f32 30x40 w8"),
+    EVS_VARIANT(2, 3, 32, 0, 24, 32, 8, "L2 h32 f32 24x32 w8"),
     EVS_VARIANT(2, 3, 32, 0, 16, 44, 8, "L2 h32 f32 16x44 w8"),
     EVS_VARIANT_B(2, 3, 32, 1, 24, 32, 8, "L2 h32 bf16 24x32 w8"),
     EVS_VARIANT_B(2, 3, 32, 1, 30, 40, 8, "L2 h32 bf16 30x40 w8"),
