@@ -98,7 +98,10 @@ struct Cfg {
   static constexpr int XS1 = align16((PADF + (CIN + 1) * XPL + 2 * CWT + 4) * XELEM);
   static constexpr int XS_BYTES = XS1 * (XDMA ? 2 : 1);
   static constexpr int SELEM = S16 ? 2 : 4;
-  static constexpr int SP1_BYTES = NH >= 1 ? align16(NPIXL * CH * SELEM) : 0;
+  // bf16 spikes are stored as CH/8 planes of [pixel][8 channels] (16 B per
+  // pixel): the 16 lanes of a lane group then read 256 contiguous bytes
+  static constexpr int SPL = NPIXL * 16;             // bytes of one 8-channel plane
+  static constexpr int SP1_BYTES = NH >= 1 ? (S16 ? SPL * (CH / 8) : align16(NPIXL * CH * SELEM)) : 0;
   // separate layer-2 spike buffer: saves two barriers per frame
   static constexpr bool SEP = NH == 2 && CH == 16 && S16;
   static constexpr int S2OFF = SEP ? SP1_BYTES : 0;
@@ -167,7 +170,7 @@ __device__ __forceinline__ void kslot(int kb, int g, int& tau, int& cib) {
 template <class C>
 struct Layout {
   static constexpr int XS = 0;                                  // x tile(s) [pad | CIN+1 planes | tail]
-  static constexpr int SP = XS + C::XS_BYTES;                   // spikes [NPIXL][CH] (x2 if SEP)
+  static constexpr int SP = XS + C::XS_BYTES;                   // spikes: bf16 [CH/8][NPIXL][8], f32 [NPIXL][CH] (x2 if SEP)
   static constexpr int WL = SP + C::SP_BYTES;                   // VALU output weights [9][CI][2] f32
   static constexpr int FR1 = WL + align16(C::WL_FLOATS * 4);    // layer-1 A fragments
   static constexpr int FR1_BYTES = C::NH >= 1 ? C::KS1 * C::MB * 64 * (C::BF16 ? 16 : 4) : 0;
@@ -344,12 +347,16 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
       s[r] = bilif(v, theta, alpha, C::RELAX && relaxed);
       st[m][r] = v;
     }
+    // materialise the reset potential here: left to the scheduler, the
+    // reset sinks to the next frame and keeps every spike value live
+    asm volatile("" : "+v"(st[m]));
     if constexpr (C::RELAX) {
       if (!valid) s = f4{0.f, 0.f, 0.f, 0.f};
     }
     if constexpr (C::S16) {
       uint2 w2 = {pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
-      *reinterpret_cast<uint2*>(lds + Layout<C>::SP + sp_off + ((size_t)p * C::CH + 16 * m + 4 * g) * 2) = w2;
+      // channels 16m + 4g .. +3: plane 2m + g/2, half (g & 1) of the pixel's 16 bytes
+      *reinterpret_cast<uint2*>(lds + Layout<C>::SP + sp_off + (2 * m + (g >> 1)) * C::SPL + p * 16 + 8 * (g & 1)) = w2;
     } else {
       *reinterpret_cast<f4*>(lds + Layout<C>::SP + sp_off + ((size_t)p * C::CH + 16 * m + 4 * g) * 4) = s;
     }
@@ -713,9 +720,9 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         auto ld2 = [&](int kb, int s) __attribute__((always_inline)) {
           int tau, cib;
           kslot<C::CH>(kb, g, tau, cib);
-          const int o = (tap_off(tau > 8 ? 8 : tau, C::CWT) * C::CH + cib) * 2;   // tap 9: zero weights
+          const int o = (cib >> 3) * C::SPL + tap_off(tau > 8 ? 8 : tau, C::CWT) * 16;   // tap 9: zero weights
 #pragma unroll
-          for (int i = 0; i < C::NB2; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sp1 + e2[i] * C::CH * 2 + o);
+          for (int i = 0; i < C::NB2; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sp1 + e2[i] * 16 + o);
 #pragma unroll
           for (int p = 0; p < C::NSP; ++p)
 #pragma unroll
@@ -785,9 +792,9 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       auto ld3 = [&](int kb, int s) __attribute__((always_inline)) {
         int tau, cib;
         kslot<C::CH>(kb, g, tau, cib);
-        const int o = (tap_off(tau > 8 ? 8 : tau, C::CWT) * C::CH + cib) * 2;
+        const int o = (cib >> 3) * C::SPL + tap_off(tau > 8 ? 8 : tau, C::CWT) * 16;
 #pragma unroll
-        for (int i = 0; i < C::NBO; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sob + eo[i] * C::CH * 2 + o);
+        for (int i = 0; i < C::NBO; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sob + eo[i] * 16 + o);
         aq[s] = fr3[kb * 64];
       };
       ld3(0, 0);
@@ -811,6 +818,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           }
           float v = h;
           const float sp = bilif(v, theta, alpha, false);
+          asm volatile("" : "+v"(v));
           vo[i] = v;
           if (oo[i] >= 0 && ca.s_out) {
             if (C::FULL && ca.s_fp32) s32[oo[i]] = sp;
