@@ -281,7 +281,7 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
   bt.item_start[n_clips] = items;
   bt.n_items = items;
   int32_t* counter = reinterpret_cast<int32_t*>(wsp);
-  if ((st = zero_i32(counter, 1, s))) return st;
+  if ((st = zero_i32(counter, 8, s))) return st;      // one work queue per XCD
   return launch_forward_batched(*net, na, bt, tile, counter, s);
 }
 

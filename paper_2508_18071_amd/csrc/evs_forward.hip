@@ -929,8 +929,27 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void
   run_tile<C>(na, ca, tl, lds);
 }
 
-// Persistent batched kernel: workgroups pop (clip, tile) items from a device
-// counter; items are ordered clip by clip, clips longest-first.
+// Work queues of the persistent kernel: the items are cut into one
+// contiguous range per XCD (the hardware deals workgroups round-robin over
+// the 8 XCDs), so neighbouring tiles, which share halo rows of x, run on
+// the same L2; a workgroup whose range is empty takes items from the others.
+constexpr int kQueues = 8;
+
+// Next item for a workgroup on XCD `x` (thread 0 only), -1 when all are taken.
+__device__ inline int pop_item(int32_t* counter, int n_items, int x) {
+  const int per = (n_items + kQueues - 1) / kQueues;
+  for (int k = 0; k < kQueues; ++k) {
+    const int y = (x + k) % kQueues;
+    const int lo = y * per, hi = lo + per < n_items ? lo + per : n_items;
+    if (lo >= hi) continue;
+    const int i = atomicAdd(counter + y, 1);
+    if (lo + i < hi) return lo + i;
+  }
+  return -1;
+}
+
+// Persistent batched kernel: workgroups pop (clip, tile) items from the
+// per-XCD queues; items are ordered clip by clip, clips longest-first.
 template <class C>
 __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void fwd_batched_kernel(FwdNetArgs na, BatchTable bt, int32_t* counter) {
   __shared__ __attribute__((aligned(16))) char lds[Layout<C>::TOTAL];
@@ -938,13 +957,13 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void
   init_lds<C>(na, lds);
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) item_sh = pop_item(counter, bt.n_items, blockIdx.x % kQueues);
     __syncthreads();
     const int item = item_sh;
-    if (item >= bt.n_items) break;
+    if (item < 0) break;
     int c = 0;
     while (c + 1 < bt.n_clips && bt.item_start[c + 1] <= item) ++c;
-    const FwdClipArgs& ca = bt.clip[c];
+    const FwdClipArgs ca = bt.clip[c];            // by value: scalar registers, loaded once per item
     const int local = item - bt.item_start[c];
     const int per_n = ca.tiles_x * ca.tiles_y;
     Tile tl;
@@ -967,7 +986,7 @@ struct Variant {
   void (*single_fast)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*single_full)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*single_relaxed)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
-  void (*batched)(const FwdNetArgs&, const BatchTable&, int32_t*, int, hipStream_t, hipError_t*);
+  void (*batched)(const FwdNetArgs&, const BatchTable&, int32_t*, int ncu, hipStream_t, hipError_t*);
 };
 
 template <class C>
@@ -976,9 +995,20 @@ void launch_single(const FwdNetArgs& na, const FwdClipArgs& ca, hipStream_t st, 
   hipLaunchKernelGGL(fwd_kernel<C>, grid, dim3(C::NT), 0, st, na, ca);
   *err = hipGetLastError();
 }
+// Persistent launch: as many workgroups as the CUs hold at once (two per CU
+// for the 4-wave tiles), capped by the number of work items.
 template <class C>
-void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter, int n_wg,
+void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter, int ncu,
                     hipStream_t st, hipError_t* err) {
+  static int per_cu = 0;                       // queried once per kernel (host-side only)
+  if (per_cu == 0) {
+    int n = 1;
+    *err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fwd_batched_kernel<C>, C::NT, 0);
+    if (*err != hipSuccess) return;
+    per_cu = n < 1 ? 1 : n;
+  }
+  const int cap = per_cu * ncu;
+  const int n_wg = bt.n_items < cap ? bt.n_items : cap;
   hipLaunchKernelGGL(fwd_batched_kernel<C>, dim3(n_wg), dim3(C::NT), 0, st, na, bt, counter);
   *err = hipGetLastError();
 }
@@ -987,7 +1017,7 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
 #define EVS_FAST_FULL(NL, CIN, CH, BF, TH, TW, NW)                                                   \
   &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 0)>, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 1)>
 // a tile variant: inference kernel + training/debug kernel; _R adds the
-// relaxed-spike kernel (FP32 shapes: their default tile), _B the batched one
+// relaxed-spike kernel (one tile per FP32 shape), _B the batched one
 #define EVS_VARIANT(NL, CIN, CH, BF, TH, TW, NW, NAME) \
   Variant{NL, CIN, CH, BF, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, BF, TH, TW, NW), nullptr, nullptr}
 #define EVS_VARIANT_R(NL, CIN, CH, TH, TW, NW, NAME)                                 \
@@ -1013,21 +1043,21 @@ const Variant kVariants[] = {
     EVS_VARIANT_R(2, 1, 16, 30, 40, 8, "L2 cin1 h16 f32 30x40 w8"),
     EVS_VARIANT(2, 3, 16, 1, 30, 40, 8, "L2 h16 bf16 30x40 w8"),
     // two-layer nets with hidden width <= 32
-    EVS_VARIANT_R(2, 3, 32, 22, 32, 8, "L2 h32 f32 22x32 w8"),
     EVS_VARIANT(2, 3, 32, 0, 24, 32, 8, "L2 h32 f32 24x32 w8"),
+    EVS_VARIANT_R(2, 3, 32, 22, 32, 8, "L2 h32 f32 22x32 w8"),
     EVS_VARIANT(2, 3, 32, 0, 16, 44, 8, "L2 h32 f32 16x44 w8"),
+    EVS_VARIANT_B(2, 3, 32, 1, 12, 32, 4, "L2 h32 bf16 12x32 w4"),
     EVS_VARIANT_B(2, 3, 32, 1, 24, 32, 8, "L2 h32 bf16 24x32 w8"),
-    EVS_VARIANT_B(2, 3, 32, 1, 30, 40, 8, "L2 h32 bf16 30x40 w8"),
-    EVS_VARIANT_B(2, 3, 32, 1, 16, 32, 4, "L2 h32 bf16 16x32 w4"),
-    EVS_VARIANT_B(2, 3, 32, 1, 20, 32, 4, "L2 h32 bf16 20x32 w4"),
-    EVS_VARIANT(2, 3, 32, 1, 12, 32, 4, "L2 h32 bf16 12x32 w4"),
+    EVS_VARIANT(2, 3, 32, 1, 30, 40, 8, "L2 h32 bf16 30x40 w8"),
+    EVS_VARIANT(2, 3, 32, 1, 16, 32, 4, "L2 h32 bf16 16x32 w4"),
+    EVS_VARIANT(2, 3, 32, 1, 20, 32, 4, "L2 h32 bf16 20x32 w4"),
     // three-layer nets
     EVS_VARIANT_RB(3, 3, 16, 24, 32, 8, "L3 h16 f32 24x32 w8"),
     EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
     EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
     EVS_VARIANT(3, 3, 16, 0, 30, 32, 8, "L3 h16 f32 30x32 w8"),
-    EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40 w8"),
     EVS_VARIANT(3, 3, 16, 1, 24, 32, 8, "L3 h16 bf16 24x32 w8"),
+    EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40 w8"),
     EVS_VARIANT(3, 3, 16, 1, 16, 32, 4, "L3 h16 bf16 16x32 w4"),
     EVS_VARIANT(3, 3, 32, 1, 24, 32, 8, "L3 h32 bf16 24x32 w8"),
 };
@@ -1114,9 +1144,8 @@ int launch_forward_batched(const evs_net& net, const FwdNetArgs& na, const Batch
   int dev = 0, ncu = 0;
   EVS_HIP(hipGetDevice(&dev));
   EVS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int n_wg = bt.n_items < ncu ? bt.n_items : ncu;
   hipError_t e = hipSuccess;
-  v->batched(na, bt, counter, n_wg, stream, &e);
+  v->batched(na, bt, counter, ncu, stream, &e);
   if (e != hipSuccess) return hip_check(e, "batched forward kernel launch");
   return EVS_OK;
 }
