@@ -4,94 +4,118 @@
 // The dense int8 array is cut into chunks of one (t, channel) plane each.
 // Pass 1 counts the non-zero spikes of every chunk; pass 2 turns the counts
 // into output offsets (exclusive scan in one workgroup); pass 3 re-reads the
-// chunk and writes each event at its offset.  Inside a chunk, each lane
-// reads 4 consecutive spikes per round; the lane's exclusive offset inside
-// the wave comes from three ballots of the bit planes of its count (0..4)
-// with mbcnt, and wave totals are scanned in LDS, so the output order is
-// the dense order without any sort and the result is deterministic.
+// chunk and writes its events at that offset.  In pass 3 each lane loads 16
+// consecutive spikes per round; its exclusive offset inside the wave comes
+// from five ballots of the bit planes of its count (0..16) with mbcnt, the
+// wave totals are scanned in LDS, the round's events are gathered in LDS in
+// dense order and then written out by all lanes as one contiguous run of
+// 8-byte stores.  No sort is needed and the result is deterministic.
 #include "evs_ops.hpp"
 
 namespace evs {
 namespace {
 
-constexpr int kThreads = 256;            // 4 waves
-constexpr int kRounds = 16;              // rounds of 4 x 256 spikes per chunk
-constexpr int kChunk = kThreads * 4 * kRounds;   // 16384 spikes per workgroup
+constexpr int kThreads = 256;                    // 4 waves
+constexpr int kSpl = 16;                         // spikes per lane and round (one 16-byte load)
+constexpr int kRound = kThreads * kSpl;          // 4096 spikes per round
+constexpr int kRounds = 4;
+constexpr int kChunk = kRound * kRounds;         // 16384 spikes per workgroup
 
 __device__ inline unsigned lane_prefix(unsigned long long mask) {
   // number of lanes below this one whose bit is set in mask
   return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-__device__ inline unsigned nz_bytes(unsigned w) {
-  // one bit per non-zero byte of w (bits 0, 8, 16, 24 -> 0..3)
-  unsigned m = 0;
+// bit 8k+7 set for every non-zero byte k of w
+__device__ inline unsigned nz_hi(unsigned w) { return (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u; }
+
+// spikes p0 .. p0+15 of a plane (zero past its end)
+__device__ inline uint4 load16(const int8_t* base, int p0, int HW, bool vec) {
+  if (vec && p0 + 15 < HW) return *reinterpret_cast<const uint4*>(base + p0);
+  unsigned w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-  for (int b = 0; b < 4; ++b) m |= (((w >> (8 * b)) & 0xffu) ? 1u : 0u) << b;
-  return m;
+  for (int b = 0; b < 16; ++b)
+    if (p0 + b < HW) w[b >> 2] |= ((unsigned)(uint8_t)base[p0 + b]) << (8 * (b & 3));
+  return uint4{w[0], w[1], w[2], w[3]};
 }
 
-template <bool WRITE>
-__global__ __launch_bounds__(kThreads) void k_compact(const int8_t* __restrict__ s, int HW, int W,
-                                                      int chunks_per_plane, int C,
-                                                      int32_t* __restrict__ counts,
-                                                      const long long* __restrict__ offsets,
-                                                      uint64_t* __restrict__ events, long long cap) {
-  const int chunk = blockIdx.x;                 // chunk within the plane
-  const long long plane = blockIdx.y;           // t * C + c
+__device__ inline int count16(uint4 v) {
+  return __builtin_popcount(nz_hi(v.x)) + __builtin_popcount(nz_hi(v.y)) + __builtin_popcount(nz_hi(v.z)) +
+         __builtin_popcount(nz_hi(v.w));
+}
+
+// pass 1: non-zero spikes of every chunk
+__global__ __launch_bounds__(kThreads) void k_count(const int8_t* __restrict__ s, int HW, int chunks_per_plane,
+                                                    int vec, int32_t* __restrict__ counts) {
+  const int chunk = blockIdx.x;
+  const long long plane = blockIdx.y;
+  const int8_t* base = s + plane * HW;
+  int n = 0;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r)
+    n += count16(load16(base, chunk * kChunk + r * kRound + kSpl * threadIdx.x, HW, vec != 0));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) n += __shfl_xor(n, off);
+  __shared__ int wsum[4];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[plane * chunks_per_plane + chunk] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// pass 3: events of every chunk at its offset
+__global__ __launch_bounds__(kThreads) void k_write(const int8_t* __restrict__ s, int HW, int W,
+                                                    int chunks_per_plane, int C, int vec,
+                                                    const long long* __restrict__ offsets,
+                                                    uint64_t* __restrict__ events, long long cap) {
+  const int chunk = blockIdx.x;
+  const long long plane = blockIdx.y;            // t * C + c
   const int t = (int)(plane / C), c = (int)(plane - (long long)t * C);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int8_t* base = s + plane * HW;
-  const long long block_id = plane * chunks_per_plane + chunk;
+  __shared__ uint2 stage[kRound];                // the round's events, dense order
   __shared__ int wave_tot[4];
-  __shared__ int wave_off[4];
-  long long run = WRITE ? offsets[block_id] : 0;
-  int total = 0;
-  const bool vec = (HW & 3) == 0;
+  __shared__ int wave_off[5];
+  long long run = offsets[plane * chunks_per_plane + chunk];
   for (int r = 0; r < kRounds; ++r) {
-    const int p0 = chunk * kChunk + r * (kThreads * 4) + 4 * threadIdx.x;   // first of 4 spikes
-    unsigned w = 0;
-    if (vec && p0 + 3 < HW) {
-      w = *reinterpret_cast<const unsigned*>(base + p0);
-    } else {
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (p0 + b < HW) w |= ((unsigned)(uint8_t)base[p0 + b]) << (8 * b);
-    }
-    const unsigned nzm = nz_bytes(w);
-    const unsigned cnt = __builtin_popcount(nzm);
-    const unsigned long long b0 = __ballot(cnt & 1u), b1 = __ballot(cnt & 2u), b2 = __ballot(cnt & 4u);
-    const unsigned pre = lane_prefix(b0) + 2u * lane_prefix(b1) + 4u * lane_prefix(b2);
-    const int wt = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
-    if (lane == 0) wave_tot[wave] = wt;
+    const int p0 = chunk * kChunk + r * kRound + kSpl * threadIdx.x;
+    const uint4 v = load16(base, p0, HW, vec != 0);
+    const unsigned cnt = (unsigned)count16(v);
+    const unsigned long long b0 = __ballot(cnt & 1u), b1 = __ballot(cnt & 2u), b2 = __ballot(cnt & 4u),
+                             b3 = __ballot(cnt & 8u), b4 = __ballot(cnt & 16u);
+    const unsigned pre = lane_prefix(b0) + 2u * lane_prefix(b1) + 4u * lane_prefix(b2) + 8u * lane_prefix(b3) +
+                         16u * lane_prefix(b4);
+    if (lane == 0)
+      wave_tot[wave] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2) + 8 * __popcll(b3) + 16 * __popcll(b4);
     __syncthreads();
     if (threadIdx.x == 0) {
       int acc = 0;
       for (int k = 0; k < 4; ++k) { wave_off[k] = acc; acc += wave_tot[k]; }
-      wave_tot[0] = acc;      // round total (read after the next barrier)
+      wave_off[4] = acc;                           // round total
     }
     __syncthreads();
-    const int round_total = wave_tot[0];
-    if (WRITE) {
-      long long o = run + wave_off[wave] + pre;
+    const int total = wave_off[4];
+    if (cnt) {
+      int slot = wave_off[wave] + (int)pre;
+      int y = p0 / W, x = p0 - y * W;
+      const unsigned ww[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if ((nzm >> b) & 1u) {
-          const int p = p0 + b;
-          const int y = p / W, x = p - y * W;
-          const int8_t v = (int8_t)((w >> (8 * b)) & 0xffu);
-          const uint64_t ev = (uint64_t)(uint32_t)t | ((uint64_t)x << 32) | ((uint64_t)y << 44) |
-                              ((uint64_t)c << 56) | ((uint64_t)(v < 0 ? 1u : 0u) << 63);
-          if (o < cap) events[o] = ev;
-          ++o;
+      for (int b = 0; b < kSpl; ++b) {
+        const unsigned byte = (ww[b >> 2] >> (8 * (b & 3))) & 0xffu;
+        if (byte) {
+          const unsigned neg = byte >> 7;          // -1 is 0xff
+          stage[slot++] = uint2{(unsigned)t, (unsigned)x | ((unsigned)y << 12) | ((unsigned)c << 24) | (neg << 31)};
         }
+        if (++x == W) { x = 0; ++y; }
       }
     }
-    run += round_total;
-    total += round_total;
-    __syncthreads();          // wave_tot/wave_off reused next round
+    __syncthreads();
+    for (int i = threadIdx.x; i < total; i += kThreads) {
+      const long long o = run + i;
+      if (o < cap) reinterpret_cast<uint2*>(events)[o] = stage[i];
+    }
+    run += total;
+    __syncthreads();                               // stage and wave_off reused next round
   }
-  if (!WRITE && threadIdx.x == 0) counts[block_id] = total;
 }
 
 // Exclusive scan of the chunk counts in one workgroup (fixed order); the
@@ -140,13 +164,14 @@ int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events
   // grid.y holds the (t, c) planes; split across z only if the y limit is exceeded
   if (planes > 65535) return fail(EVS_EUNSUPPORTED, "compact_events: more than 65535 (t, c) planes per call");
   dim3 grid((unsigned)cpp, (unsigned)planes);
-  hipLaunchKernelGGL(k_compact<false>, grid, dim3(kThreads), 0, st, s, (int)HW, W, (int)cpp, C, counts,
-                     (const long long*)nullptr, (uint64_t*)nullptr, 0LL);
+  // 16-byte loads when every plane starts 16-byte aligned
+  const int vec = ((reinterpret_cast<uintptr_t>(s) & 15) == 0 && (HW & 15) == 0) ? 1 : 0;
+  hipLaunchKernelGGL(k_count, grid, dim3(kThreads), 0, st, s, (int)HW, (int)cpp, vec, counts);
   EVS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, counts, cpp * planes, offsets, count);
   EVS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_compact<true>, grid, dim3(kThreads), 0, st, s, (int)HW, W, (int)cpp, C, counts,
-                     offsets, events, (long long)cap);
+  hipLaunchKernelGGL(k_write, grid, dim3(kThreads), 0, st, s, (int)HW, W, (int)cpp, C, vec, offsets, events,
+                     (long long)cap);
   EVS_HIP(hipGetLastError());
   return EVS_OK;
 }
