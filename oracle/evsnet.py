@@ -18,10 +18,16 @@ saturation effect of Sec. 3.1); the membrane starts at zero unless an
 initial state is given (the internal-state bias of Sec. 3.1).
 
 Backward: the Heaviside in the fire step is replaced by the surrogate of
-Eq. (4), read as the total derivative of sigma(h - theta) - sigma(-h - theta)
-with the sigmoid sigma(z) = 1 / (1 + exp(-alpha z)):
+Eq. (4), read as the total derivative of sigma(h - theta) - sigma(-h - theta):
 
-    psi(h) = sigma'(h - theta) + sigma'(-h - theta),  sigma' = alpha s (1 - s)
+    psi(h) = sigma'(h - theta) + sigma'(-h - theta)
+
+with one of two smooth steps sigma (argument ``surr``):
+    "sigmoid"  sigma(z) = 1 / (1 + exp(-alpha z)),   sigma' = alpha s (1 - s)
+    "atan"     the arctangent surrogate the paper trains with (Sec. 3.3, the
+               formula itself is not printed; read as the usual arctangent
+               step) sigma(z) = 1/2 + arctan(pi/2 alpha z) / pi,
+               sigma'(z) = (alpha / 2) / (1 + (pi/2 alpha z)^2)
 """
 
 from __future__ import annotations
@@ -83,16 +89,38 @@ def sigmoid(z: np.ndarray, alpha: float) -> np.ndarray:
     return 0.5 * (1.0 + np.tanh(0.5 * alpha * z))
 
 
-def relaxed_fire(h: np.ndarray, theta: float, alpha: float) -> np.ndarray:
+def atan_step(z: np.ndarray, alpha: float) -> np.ndarray:
+    """Arctangent step 1/2 + arctan(pi/2 alpha z) / pi."""
+    return 0.5 + np.arctan(0.5 * np.pi * alpha * z) / np.pi
+
+
+def step(z: np.ndarray, alpha: float, surr: str = "sigmoid") -> np.ndarray:
+    if surr == "sigmoid":
+        return sigmoid(z, alpha)
+    if surr == "atan":
+        return atan_step(z, alpha)
+    raise ValueError(surr)
+
+
+def step_slope(z: np.ndarray, alpha: float, surr: str = "sigmoid") -> np.ndarray:
+    """Derivative of step(z)."""
+    if surr == "sigmoid":
+        a = sigmoid(z, alpha)
+        return alpha * a * (1.0 - a)
+    if surr == "atan":
+        q = 0.5 * np.pi * alpha * z
+        return 0.5 * alpha / (1.0 + q * q)
+    raise ValueError(surr)
+
+
+def relaxed_fire(h: np.ndarray, theta: float, alpha: float, surr: str = "sigmoid") -> np.ndarray:
     """Smooth spike sigma(h - theta) - sigma(-h - theta) whose derivative is psi."""
-    return sigmoid(h - theta, alpha) - sigmoid(-h - theta, alpha)
+    return step(h - theta, alpha, surr) - step(-h - theta, alpha, surr)
 
 
-def surrogate(h: np.ndarray, theta: float, alpha: float) -> np.ndarray:
-    """psi(h): surrogate dS/dh of Eq. (4), sigmoid form with slope alpha."""
-    a = sigmoid(h - theta, alpha)
-    b = sigmoid(-h - theta, alpha)
-    return alpha * a * (1.0 - a) + alpha * b * (1.0 - b)
+def surrogate(h: np.ndarray, theta: float, alpha: float, surr: str = "sigmoid") -> np.ndarray:
+    """psi(h): surrogate dS/dh of Eq. (4) with slope alpha."""
+    return step_slope(h - theta, alpha, surr) + step_slope(-h - theta, alpha, surr)
 
 
 # ----------------------------------------------------------------------------
@@ -119,7 +147,7 @@ def bf16_round(a) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 def forward(x, weights, theta, leak, v_init=None, mode="hard", alpha=4.0,
-            reset_unit=None, keep_traces=True):
+            reset_unit=None, keep_traces=True, surr="sigmoid"):
     """Run the network over a clip.
 
     x        [T, C0, H, W]
@@ -154,10 +182,10 @@ def forward(x, weights, theta, leak, v_init=None, mode="hard", alpha=4.0,
                 s = fire(h, theta)
                 rs = s
             elif mode == "relaxed":
-                s = relaxed_fire(h, theta, alpha)
+                s = relaxed_fire(h, theta, alpha, surr)
                 rs = s
             elif mode == "hybrid":
-                s = relaxed_fire(h, theta, alpha)
+                s = relaxed_fire(h, theta, alpha, surr)
                 rs = fire(h, theta)
             else:
                 raise ValueError(mode)
@@ -175,7 +203,7 @@ def forward(x, weights, theta, leak, v_init=None, mode="hard", alpha=4.0,
 # ----------------------------------------------------------------------------
 
 def backward(x, weights, theta, leak, grad_s, v_init=None, mode="hard", alpha=4.0,
-             detach_reset=False, ckpt_every=None):
+             detach_reset=False, ckpt_every=None, surr="sigmoid"):
     """Surrogate-gradient BPTT through the whole clip.
 
     grad_s  [T, C_L, H, W] = dLoss/ds_L[t]
@@ -203,7 +231,7 @@ def backward(x, weights, theta, leak, grad_s, v_init=None, mode="hard", alpha=4.
     for t0 in starts:
         ckpts.append([vl.copy() for vl in v])
         seg = forward(x[t0:t0 + k], ws, theta, leak, v_init=v, mode=mode, alpha=alpha,
-                      keep_traces=False)
+                      keep_traces=False, surr=surr)
         v = seg["v"]
     dW = [np.zeros_like(w) for w in ws]
     dx = np.zeros_like(x)
@@ -211,13 +239,13 @@ def backward(x, weights, theta, leak, grad_s, v_init=None, mode="hard", alpha=4.
     for si in reversed(range(len(starts))):
         t0 = starts[si]
         t1 = min(T, t0 + k)
-        seg = forward(x[t0:t1], ws, theta, leak, v_init=ckpts[si], mode=mode, alpha=alpha)
+        seg = forward(x[t0:t1], ws, theta, leak, v_init=ckpts[si], mode=mode, alpha=alpha, surr=surr)
         for tt in reversed(range(t1 - t0)):
             t = t0 + tt
             G = np.asarray(grad_s[t], dtype=np.float64)
             for l in reversed(range(L)):
                 h = seg["h"][l][tt]
-                psi = surrogate(h, theta, alpha)
+                psi = surrogate(h, theta, alpha, surr)
                 if detach_reset:
                     g_h = G * psi + g_v[l]
                 else:

@@ -220,7 +220,7 @@ def test_surrogate_is_derivative_of_relaxed_spike():
 
 # ---------------------------------------------------------------- BPTT
 
-def _fd_check(mode, detach, chs=(2, 3, 2), T=4, H=5, W=5, seed=7):
+def _fd_check(mode, detach, chs=(2, 3, 2), T=4, H=5, W=5, seed=7, surr="sigmoid", alpha=4.0):
     rng = np.random.default_rng(seed)
     x = rng.normal(size=(T, chs[0], H, W))
     ws = rand_net(chs, seed, scale=1.5)
@@ -229,9 +229,11 @@ def _fd_check(mode, detach, chs=(2, 3, 2), T=4, H=5, W=5, seed=7):
     theta, beta = 0.5, 0.9
 
     def loss(ws_, x_, v_):
-        return float((evsnet.forward(x_, ws_, theta, beta, v_init=v_, mode=mode)["s"] * G).sum())
+        return float((evsnet.forward(x_, ws_, theta, beta, v_init=v_, mode=mode, alpha=alpha,
+                                     surr=surr)["s"] * G).sum())
 
-    g = evsnet.backward(x, ws, theta, beta, G, v_init=v0, mode=mode, detach_reset=detach)
+    g = evsnet.backward(x, ws, theta, beta, G, v_init=v0, mode=mode, detach_reset=detach, alpha=alpha,
+                        surr=surr)
     eps = 1e-6
     errs = []
     for l in range(len(ws)):
@@ -263,6 +265,38 @@ def _fd_check(mode, detach, chs=(2, 3, 2), T=4, H=5, W=5, seed=7):
 
 def test_p11_bptt_matches_fd_of_relaxed_forward():
     assert _fd_check("relaxed", False) < 1e-6
+
+
+# ---------------------------------------------------------------- arctangent surrogate (Sec. 3.3)
+
+def test_atan_step_closed_forms():
+    """sigma(0) = 1/2, sigma'(0) = alpha/2, sigma(z) + sigma(-z) = 1, limits 0 and 1,
+    and sigma(z) = 3/4 where pi/2 alpha z = 1 (arctan 1 = pi/4)."""
+    for alpha in (0.5, 2.0, 4.0):
+        assert evsnet.step(np.array(0.0), alpha, "atan") == 0.5
+        assert evsnet.step_slope(np.array(0.0), alpha, "atan") == pytest.approx(alpha / 2, rel=1e-15)
+        z = np.linspace(-5, 5, 101)
+        np.testing.assert_allclose(evsnet.step(z, alpha, "atan") + evsnet.step(-z, alpha, "atan"), 1.0,
+                                   rtol=0, atol=1e-15)
+        assert evsnet.step(np.array(2.0 / (np.pi * alpha)), alpha, "atan") == pytest.approx(0.75, rel=1e-14)
+        assert evsnet.step(np.array(1e9), alpha, "atan") == pytest.approx(1.0, abs=1e-8)
+        assert evsnet.step(np.array(-1e9), alpha, "atan") == pytest.approx(0.0, abs=1e-8)
+
+
+def test_atan_surrogate_is_derivative_of_relaxed_spike():
+    h = np.linspace(-3, 3, 601)
+    eps = 1e-6
+    for alpha in (2.0, 4.0):
+        fd = (evsnet.relaxed_fire(h + eps, 0.5, alpha, "atan") - evsnet.relaxed_fire(h - eps, 0.5, alpha, "atan")) / (2 * eps)
+        np.testing.assert_allclose(evsnet.surrogate(h, 0.5, alpha, "atan"), fd, rtol=1e-7, atol=1e-9)
+    # psi is even in h and peaks at the two thresholds
+    np.testing.assert_allclose(evsnet.surrogate(h, 0.5, 2.0, "atan"), evsnet.surrogate(-h, 0.5, 2.0, "atan"), rtol=1e-15)
+    psi = evsnet.surrogate(h, 0.5, 2.0, "atan")
+    assert abs(abs(h[np.argmax(psi)]) - 0.5) < 0.011
+
+
+def test_atan_bptt_matches_fd_of_relaxed_forward():
+    assert _fd_check("relaxed", False, surr="atan", alpha=2.0) < 1e-6
 
 
 def test_p12_detached_reset_bptt_matches_fd_of_hybrid_forward():
