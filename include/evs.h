@@ -67,7 +67,7 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
  *              that may itself fire with either sign.
  *   theta      firing threshold V_th > 0 (Eq. 2-3)
  *   leak       beta = 1 - 1/tau in [0, 1]
- *   surr_alpha slope of the sigmoid surrogate sigma(z) = 1/(1+exp(-alpha z))
+ *   surr_alpha slope alpha of the surrogate step sigma (see `surrogate`)
  *              used by evs_backward and by relaxed forwards (Eq. 4)
  *   precision  EVS_FP32: convolutions in FP32 (MFMA f32);
  *              EVS_BF16: x and W rounded to bfloat16 (round-to-nearest-even)
@@ -78,7 +78,13 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
  *              whose exact derivative is the surrogate (FP32 only; used to
  *              check gradients against finite differences).
  *   detach_reset  evs_backward only: 1 stops the gradient through the
- *              reset term theta * s.                                        */
+ *              reset term theta * s.
+ *   surrogate  smooth step sigma of the surrogate and of relaxed spikes:
+ *              EVS_SURR_SIGMOID (0) sigma(z) = 1/(1+exp(-alpha z)), or
+ *              EVS_SURR_ATAN (1) sigma(z) = 1/2 + arctan(pi/2 alpha z)/pi,
+ *              the arctangent surrogate the paper trains with (Sec. 3.3).  */
+#define EVS_SURR_SIGMOID 0
+#define EVS_SURR_ATAN 1
 typedef struct evs_net {
   int32_t n_layers;
   int32_t ch[4];
@@ -88,6 +94,7 @@ typedef struct evs_net {
   int32_t precision;
   int32_t relaxed;
   int32_t detach_reset;
+  int32_t surrogate;
 } evs_net;
 
 /* One clip, or a batch of N clips of equal shape (host struct).

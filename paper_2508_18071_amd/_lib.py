@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libevs.so")
 
 EVS_OK, EVS_EINVAL, EVS_EUNSUPPORTED, EVS_EWORKSPACE, EVS_EHIP, EVS_EOVERFLOW = range(6)
 EVS_FP32, EVS_BF16 = 0, 1
+EVS_SURR_SIGMOID, EVS_SURR_ATAN = 0, 1
 EVS_OP_FORWARD, EVS_OP_BACKWARD, EVS_OP_EMD, EVS_OP_COMPACT = range(4)
 
 
@@ -27,6 +28,7 @@ class EvsNet(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("relaxed", ctypes.c_int32),
         ("detach_reset", ctypes.c_int32),
+        ("surrogate", ctypes.c_int32),
     ]
 
 

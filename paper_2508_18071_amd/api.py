@@ -25,6 +25,7 @@ class Net:
     precision: str = "fp32"        # "fp32" | "bf16"
     relaxed: bool = False
     detach_reset: bool = False
+    surrogate: str = "sigmoid"      # "sigmoid" or "atan" (the paper's arctangent surrogate)
 
     def c(self) -> EvsNet:
         n = EvsNet()
@@ -38,6 +39,7 @@ class Net:
         n.precision = _lib.EVS_BF16 if self.precision == "bf16" else _lib.EVS_FP32
         n.relaxed = int(self.relaxed)
         n.detach_reset = int(self.detach_reset)
+        n.surrogate = {"sigmoid": 0, "atan": 1}[self.surrogate]
         return n
 
     @property

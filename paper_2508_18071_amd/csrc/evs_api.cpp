@@ -42,6 +42,8 @@ int validate_net(const evs_net* net) {
   if (!(net->surr_alpha > 0.f)) return fail(EVS_EINVAL, "surr_alpha must be positive");
   if (net->precision != EVS_FP32 && net->precision != EVS_BF16) return fail(EVS_EINVAL, "bad precision");
   if (net->relaxed && net->precision != EVS_FP32) return fail(EVS_EUNSUPPORTED, "relaxed spikes need FP32");
+  if (net->surrogate != EVS_SURR_SIGMOID && net->surrogate != EVS_SURR_ATAN)
+    return fail(EVS_EINVAL, "surrogate must be EVS_SURR_SIGMOID or EVS_SURR_ATAN");
   return EVS_OK;
 }
 
@@ -113,7 +115,7 @@ FwdNetArgs make_net_args(const evs_net& net, const void* packed) {
   na.theta = net.theta;
   na.leak = net.leak;
   na.alpha = net.surr_alpha;
-  na.relaxed = net.relaxed;
+  na.relaxed = net.relaxed ? 1 + net.surrogate : 0;     // 0 hard, 1 sigmoid, 2 arctangent
   return na;
 }
 

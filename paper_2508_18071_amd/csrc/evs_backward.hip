@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ hseg,
                                                  int len, int N, int HW, const float* __restrict__ G,
                                                  long long G_nstride, long long G_tstride,
                                                  float* __restrict__ gh, float* __restrict__ gv, float theta,
-                                                 float leak, float alpha, int detach) {
+                                                 float leak, float alpha, int surr, int detach) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long total = (long long)N * C * HW;
   if (idx >= total) return;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ hseg,
   for (int t = len - 1; t >= 0; --t) {
     const float h = hseg[(((size_t)n * len + t) * sumc + choff + c) * HW + p];
     const float Gv = G[(size_t)n * G_nstride + (size_t)t * G_tstride + (size_t)c * HW + p];
-    const float psi = surrogate(h, theta, alpha);
+    const float psi = surrogate(h, theta, alpha, surr);
     const float g_h = detach ? fmaf(Gv, psi, g_v) : fmaf(fmaf(-theta, g_v, Gv), psi, g_v);
     gh[(((size_t)n * len + t) * C + c) * HW + p] = g_h;
     g_v = leak * g_h;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
       if (ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W) {
         if (hseg) {
           const float h = hseg[(((size_t)n * len + t) * sumc + choff_in + ci) * HW + (size_t)y * W + xx];
-          v = spike_of(h, theta, alpha, relaxed != 0);
+          v = spike_of(h, theta, alpha, relaxed);
         } else {
           v = x[(size_t)n * x_nstride + ((size_t)t * Cin + ci) * HW + (size_t)y * W + xx];
           if (bf_x) v = round_bf16(v);
@@ -342,7 +342,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
       const long long tot = (long long)N * C * HW;
       hipLaunchKernelGGL(k_adjoint, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, hseg, sumc,
                          choff[l - 1], C, len, N, (int)HW, G, G_ns, G_ts, gh, gv, net.theta, net.leak,
-                         net.surr_alpha, net.detach_reset);
+                         net.surr_alpha, net.surrogate, net.detach_reset);
       EVS_HIP(hipGetLastError());
       // weight gradient partials for this segment, then fixed-order reduction
       const int CI = pad_in(Cin), CO = pad_out(C);
@@ -352,7 +352,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
 #define EVS_CALL_DW(A, B)                                                                              \
   launch_dw<A, B>(gdw, st, gh, C, Cin, len, H, W, Lo.tiles_x, clip.x + (size_t)t0 * cin0 * HW,          \
                   (long long)T * cin0 * HW, bf ? 1 : 0, hin, sumc, choff_in, net.theta, net.surr_alpha, \
-                  net.relaxed, partial)
+                  net.relaxed ? 1 + net.surrogate : 0, partial)
       EVS_DISPATCH_PAD(CI, CO, EVS_CALL_DW);
 #undef EVS_CALL_DW
       EVS_HIP(hipGetLastError());

@@ -8,14 +8,31 @@ namespace evs {
 
 __device__ inline float sigm_fast(float z) { return __frcp_rn(1.0f + __expf(-z)); }
 
+// Smooth step of the surrogate (Sec. 3.3, Eq. 4) and its slope.
+//   kind 0: logistic sigmoid 1 / (1 + exp(-alpha z))
+//   kind 1: arctangent 1/2 + arctan(pi/2 alpha z) / pi
+__device__ inline float surr_step(float z, float alpha, int kind) {
+  if (kind == 1) return 0.5f + atanf(1.57079633f * alpha * z) * 0.318309886f;
+  return sigm_fast(alpha * z);
+}
+__device__ inline float surr_slope(float z, float alpha, int kind) {
+  if (kind == 1) {
+    const float q = 1.57079633f * alpha * z;
+    return 0.5f * alpha / fmaf(q, q, 1.0f);
+  }
+  const float a = sigm_fast(alpha * z);
+  return alpha * a * (1.0f - a);
+}
+
 // BiLIF fire + reset (Eq. 2-3): returns the spike and updates v in place (v
-// holds the charged potential h on entry).  relaxed: the smooth spike
-// sigma(alpha(h - theta)) - sigma(alpha(-h - theta)).
-__device__ inline float bilif(float& v, float theta, float alpha, bool relaxed) {
+// holds the charged potential h on entry).  relaxed: 0 hard spikes; 1 or 2
+// the smooth spike step(h - theta) - step(-h - theta) of the sigmoid (1) or
+// arctangent (2) step.
+__device__ inline float bilif(float& v, float theta, float alpha, int relaxed) {
   const float h = v;
   float s;
   if (relaxed) {
-    s = sigm_fast(alpha * (h - theta)) - sigm_fast(alpha * (-h - theta));
+    s = surr_step(h - theta, alpha, relaxed - 1) - surr_step(-h - theta, alpha, relaxed - 1);
   } else {
     // h >= theta -> +1, h <= -theta -> -1, else 0 (theta > 0; a NaN h gives 0):
     // one compare of |h| and the sign of h copied onto 1.0
@@ -27,14 +44,15 @@ __device__ inline float bilif(float& v, float theta, float alpha, bool relaxed) 
 }
 
 // The spike the forward emitted for the charged potential h.
-__device__ inline float spike_of(float h, float theta, float alpha, bool relaxed) {
+__device__ inline float spike_of(float h, float theta, float alpha, int relaxed) {
   float v = h;
   return bilif(v, theta, alpha, relaxed);
 }
 
-// Surrogate derivative of the spike (Eq. 4, sigmoid of slope alpha):
-// psi(h) = sigma'(h - theta) + sigma'(-h - theta), sigma' = alpha s (1 - s).
-__device__ inline float surrogate(float h, float theta, float alpha) {
+// Surrogate derivative of the spike (Eq. 4):
+// psi(h) = step'(h - theta) + step'(-h - theta), kind 0 sigmoid, 1 arctangent.
+__device__ inline float surrogate(float h, float theta, float alpha, int kind) {
+  if (kind == 1) return surr_slope(h - theta, alpha, 1) + surr_slope(-h - theta, alpha, 1);
   const float a = sigm_fast(alpha * (h - theta));
   const float b = sigm_fast(alpha * (-h - theta));
   return alpha * (a * (1.0f - a) + b * (1.0f - b));

@@ -327,7 +327,7 @@ __device__ __forceinline__ int block_pixel(int l, int b, int j, int gy0, int gx0
 // write spikes to LDS and, optionally, h to the trace.
 template <class C>
 __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int sp_off, int p, bool valid, int g,
-                                                float theta, float alpha, bool relaxed, float* trace_t,
+                                                float theta, float alpha, int relaxed, float* trace_t,
                                                 int cl, int choff, int gy0, int gx0, const TraceBox& tb) {
   if (C::FULL && trace_t && valid) {
     const int row = (p - C::PADF) / C::CWT, col = (p - C::PADF) % C::CWT;
@@ -349,7 +349,7 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       float v = st[m][r];
-      s[r] = bilif(v, theta, alpha, C::RELAX && relaxed);
+      s[r] = bilif(v, theta, alpha, C::RELAX ? relaxed : 0);
       st[m][r] = v;
     }
     // materialise the reset potential here: left to the scheduler, the
@@ -754,7 +754,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   const size_t HW = (size_t)H * W;
   const int sumc = na.sum_c;
   const float theta = na.theta, leak = na.leak, alpha = na.alpha;
-  const bool relaxed = na.relaxed != 0;
+  const int relaxed = na.relaxed;                   // 0 hard, 1 sigmoid, 2 arctangent step
   const int c1 = na.ch[1], c2 = na.ch[2];
   const int cout = na.ch[na.n_layers];
   const int choff2 = c1, choffo = (C::NH == 0) ? 0 : (C::NH == 1 ? c1 : c1 + c2);
@@ -1191,7 +1191,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             if (tb.has(gy, gx)) trace_t[(size_t)(choffo + co) * tb.plane() + tb.idx(gy, gx)] = u[k][co];
           }
           float v = u[k][co];
-          const float s = bilif(v, theta, alpha, C::RELAX && relaxed);
+          const float s = bilif(v, theta, alpha, C::RELAX ? relaxed : 0);
           so[k][co] = v;
           if (ok && co < cout && ca.s_out) {
             const size_t o = (((size_t)tl.n * T + t) * cout + co) * HW + pix;

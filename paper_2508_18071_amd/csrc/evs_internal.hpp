@@ -76,7 +76,7 @@ struct FwdNetArgs {
   int32_t wofs[3];       // float offsets of each layer in w
   int32_t sum_c;
   float theta, leak, alpha;
-  int32_t relaxed;
+  int32_t relaxed;       // 0 hard spikes, 1 relaxed (sigmoid step), 2 relaxed (arctangent step)
 };
 
 // Batched (persistent) launch: a clip table passed by value.

@@ -72,6 +72,38 @@ def test_forward_rejects_bad_networks_before_launch(evs, kw, code):
     assert evs.lib().evs_last_error()
 
 
+def test_forward_rejects_unknown_surrogate(evs):
+    net = _net(evs, channels=(3, 16, 2))
+    net.surrogate = 2
+    c = evs._lib.EvsClip()
+    c.N, c.T, c.H, c.W = 1, 4, 8, 8
+    c.x = 16
+    st = evs.lib().evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0,
+                               None, 0, None)
+    assert st == 1
+    assert b"surrogate" in evs.lib().evs_last_error()
+
+
+def _header_struct_fields(name):
+    import re
+    src = open(os.path.join(ROOT, "include", "evs.h")).read()
+    body = re.search(r"typedef struct " + name + r" \{(.*?)\} " + name + ";", src, re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(",") if "," in decl and "[" not in decl else [decl]:
+            tok = part.strip().split()[-1].lstrip("*")
+            fields.append(tok.split("[")[0])
+    return fields
+
+
+def test_ctypes_structs_mirror_the_header(evs):
+    assert _header_struct_fields("evs_net") == [f for f, _ in evs._lib.EvsNet._fields_]
+    assert _header_struct_fields("evs_clip") == [f for f, _ in evs._lib.EvsClip._fields_]
+
+
 def test_forward_rejects_bad_clips_and_workspace(evs):
     L = evs.lib()
     net = _net(evs, channels=(3, 16, 16, 2))

@@ -35,22 +35,30 @@ def _rel(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-12))
 
 
-def _setup(evs, channels, prec, T, H, W, N=1, seed=0, scale=1.0, relaxed=False, detach=False):
+SURR_ALPHA = {"sigmoid": 4.0, "atan": 2.0}
+
+
+def _setup(evs, channels, prec, T, H, W, N=1, seed=0, scale=1.0, relaxed=False, detach=False, surr="sigmoid"):
     x, ws = make_inputs(channels, T, H, W, N=N, seed=seed, scale=scale)
-    net = evs.Net(channels, theta=THETA, leak=LEAK, precision=prec, relaxed=relaxed, detach_reset=detach)
+    net = evs.Net(channels, theta=THETA, leak=LEAK, precision=prec, relaxed=relaxed, detach_reset=detach,
+                  surrogate=surr, surr_alpha=SURR_ALPHA[surr])
     wt = [torch.from_numpy(w).cuda() for w in ws]
     packed = evs.pack_weights(net, wt)
     return x, ws, net, packed
 
 
-@pytest.mark.parametrize("channels,prec,detach", [((3, 8, 2), "fp32", False), ((3, 16, 16, 2), "fp32", False),
-                                                  ((3, 16, 16, 2), "fp32", True), ((3, 32, 2), "bf16", False),
-                                                  ((3, 16, 16, 2), "bf16", False), ((1, 1), "fp32", False)])
+@pytest.mark.parametrize("channels,prec,detach,surr", [((3, 8, 2), "fp32", False, "sigmoid"),
+                                                       ((3, 16, 16, 2), "fp32", False, "sigmoid"),
+                                                       ((3, 16, 16, 2), "fp32", True, "sigmoid"),
+                                                       ((3, 16, 16, 2), "fp32", False, "atan"),
+                                                       ((3, 32, 2), "bf16", False, "sigmoid"),
+                                                       ((3, 16, 16, 2), "bf16", False, "sigmoid"),
+                                                       ((1, 1), "fp32", False, "sigmoid")])
 @pytest.mark.parametrize("k", [4, 100])
-def test_backward_matches_oracle(evs, channels, prec, detach, k):
+def test_backward_matches_oracle(evs, channels, prec, detach, surr, k):
     T, H, W, N = 9, 21, 27, 2
-    print(f"case {channels} {prec} detach={detach} k={k}", flush=True)
-    x, ws, net, packed = _setup(evs, channels, prec, T, H, W, N=N, seed=3, detach=detach)
+    print(f"case {channels} {prec} detach={detach} surrogate={surr} k={k}", flush=True)
+    x, ws, net, packed = _setup(evs, channels, prec, T, H, W, N=N, seed=3, detach=detach, surr=surr)
     xg = x.cuda()
     out = evs.forward(net, packed, xg, trace=True, ckpt_every=k)
     rng = np.random.default_rng(1)
@@ -71,7 +79,7 @@ def test_backward_matches_oracle(evs, channels, prec, detach, k):
         # same trajectory: every layer's spikes agree with the oracle's
         for hl, sr in zip(split_layers(h[n], channels), ref["spk"]):
             assert np.array_equal(evsnet.fire(hl, THETA), sr), "trajectory diverged; reseed"
-        g = evsnet.backward(xo[n], ows, THETA, LEAK, G[n], detach_reset=detach)
+        g = evsnet.backward(xo[n], ows, THETA, LEAK, G[n], detach_reset=detach, alpha=SURR_ALPHA[surr], surr=surr)
         for l in range(len(ws)):
             dW_ref[l] += g["dW"][l]
         assert _rel(dx[n].cpu().numpy(), g["dx"]) < 1e-4
@@ -105,19 +113,20 @@ def test_checkpoint_interval_and_determinism(evs):
         assert _rel(res[k][1].cpu().numpy(), res[4][1].cpu().numpy()) < 1e-5
 
 
-def test_relaxed_backward_matches_oracle_and_finite_differences(evs):
+@pytest.mark.parametrize("surr", ["sigmoid", "atan"])
+def test_relaxed_backward_matches_oracle_and_finite_differences(evs, surr):
     """8x8x4 crop (8x8 pixels, 4 frames): GPU BPTT of the smooth forward
     against the oracle and against central differences of the GPU forward."""
     channels = (3, 16, 16, 2)
     T, H, W = 4, 8, 8
-    x, ws, net, packed = _setup(evs, channels, "fp32", T, H, W, seed=9, relaxed=True)
+    x, ws, net, packed = _setup(evs, channels, "fp32", T, H, W, seed=9, relaxed=True, surr=surr)
     xg = x.cuda()
     G = np.random.default_rng(4).normal(size=(1, T, 2, H, W)).astype(np.float32)
     Gt = torch.from_numpy(G).cuda()
     out = evs.forward(net, packed, xg, s_fp32=True, ckpt_every=2)
     gws, dx, _ = evs.backward(net, packed, xg, out["ckpt"], 2, Gt, want_dx=True)
     torch.cuda.synchronize()
-    ref = evsnet.backward(x[0].numpy(), ws, THETA, LEAK, G[0], mode="relaxed")
+    ref = evsnet.backward(x[0].numpy(), ws, THETA, LEAK, G[0], mode="relaxed", alpha=SURR_ALPHA[surr], surr=surr)
     for l in range(3):
         assert _rel(gws[l].cpu().numpy(), ref["dW"][l]) < 1e-4
     assert _rel(dx[0].cpu().numpy(), ref["dx"]) < 1e-4

@@ -199,15 +199,16 @@ def test_initial_state_and_checkpoints(evs):
     np.testing.assert_array_equal(v[0].cpu().numpy(), hv - np.float32(THETA) * fire32(hv, THETA).astype(np.float32))
 
 
-def test_relaxed_forward_matches_oracle(evs):
+@pytest.mark.parametrize("surr,alpha", [("sigmoid", 4.0), ("atan", 2.0)])
+def test_relaxed_forward_matches_oracle(evs, surr, alpha):
     channels = (3, 16, 16, 2)
     x, ws = make_inputs(channels, 6, 30, 44)
-    net = evs.Net(channels, theta=THETA, leak=LEAK, relaxed=True)
+    net = evs.Net(channels, theta=THETA, leak=LEAK, relaxed=True, surrogate=surr, surr_alpha=alpha)
     wt = [torch.from_numpy(w).cuda() for w in ws]
     packed = evs.pack_weights(net, wt)
     out = evs.forward(net, packed, x.cuda(), s_fp32=True, trace=True)
     torch.cuda.synchronize()
-    ref = evsnet.forward(x[0].numpy(), ws, THETA, LEAK, mode="relaxed")
+    ref = evsnet.forward(x[0].numpy(), ws, THETA, LEAK, mode="relaxed", alpha=alpha, surr=surr)
     s = out["s"][0].cpu().numpy()
     np.testing.assert_allclose(s, ref["s"], atol=2e-4)
     h = split_layers(out["h"][0].cpu().numpy(), channels)

@@ -490,3 +490,82 @@ def test_bf16_round_matches_torch():
                            np.array([1.0, -1.0, 0.0, 1.00390625, 1.01171875, 3.0e38, 1e-40], np.float32)])
     ref = torch.from_numpy(vals).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(evsnet.bf16_round(vals), ref)
+
+
+# ---------------------------------------------------------------- Eq. (1) input and contrast-crossing targets
+
+from oracle import prologue  # noqa: E402
+
+
+def test_luminance_weights_and_gray():
+    """Rec. 709 luma weights (Eq. 1) sum to 1: a gray pixel keeps its value;
+    each primary alone gives its own weight."""
+    img = np.broadcast_to(np.linspace(0, 2, 7)[:, None], (7, 3))
+    rgb = np.stack([img] * 3)                                                    # [3, 7, 3]
+    np.testing.assert_allclose(prologue.luminance(rgb, 1.0), img, rtol=1e-15)
+    for c, w in enumerate(prologue.LUMA):
+        e = np.zeros((3, 1, 1))
+        e[c] = 1.0
+        assert prologue.luminance(e, 255.0)[0, 0] == pytest.approx(255.0 * w, rel=1e-15)
+
+
+def test_linlog_branches_meet_at_the_knee_and_increase():
+    for knee in (5.0, 20.0, 100.0):
+        assert prologue.linlog(np.array(knee), knee) == pytest.approx(np.log(knee), rel=1e-15)
+        assert prologue.linlog(np.array(knee * (1 - 1e-12)), knee) == pytest.approx(np.log(knee), rel=1e-10)
+        L = np.linspace(0, 5 * knee, 2001)
+        assert np.all(np.diff(prologue.linlog(L, knee)) > 0)
+        assert prologue.linlog(np.array(0.0), knee) == 0.0
+    assert prologue.linlog(np.array(np.e ** 4), 20.0) == pytest.approx(4.0, rel=1e-15)
+    assert prologue.linlog(np.array(10.0), 20.0) == pytest.approx(np.log(20.0) / 2, rel=1e-15)
+
+
+def test_logdiff_constant_and_step():
+    rng = np.random.default_rng(0)
+    frame = rng.uniform(0.01, 1.0, size=(3, 6, 7))
+    X = prologue.logdiff(np.stack([frame] * 5))
+    assert X.shape == (4, 1, 6, 7) and np.all(X == 0)
+    # gray frames above the knee: X = ln(b / a)
+    a, b = 0.3, 0.7
+    fr = np.stack([np.full((3, 2, 2), a), np.full((3, 2, 2), b)])
+    np.testing.assert_allclose(prologue.logdiff(fr), np.log(b / a), rtol=1e-14)
+    # below the knee the step is linear: (ln 20 / 20) * 255 * (b - a)
+    a, b = 0.01, 0.02
+    fr = np.stack([np.full((3, 2, 2), a), np.full((3, 2, 2), b)])
+    np.testing.assert_allclose(prologue.logdiff(fr), np.log(20.0) / 20.0 * 255.0 * (b - a), rtol=1e-13)
+
+
+def _gray_from_log(l):
+    """Gray frames whose lin-log luminance (scale 255, knee 20) is l (> ln 20)."""
+    v = np.exp(l) / 255.0
+    return np.broadcast_to(v[:, None, ...], (v.shape[0], 3) + v.shape[1:]).copy()
+
+
+def test_contrast_events_log_ramp_closed_form():
+    """A log ramp of delta per frame emits floor(t delta / C) ON events up to frame t."""
+    T, delta, C = 60, 0.0713, 0.2
+    l = 8.0 + delta * np.arange(T)                   # stays above ln(knee) both ways
+    E = prologue.contrast_events(_gray_from_log(l[:, None, None] * np.ones((1, 2, 3))), C)
+    cum = np.cumsum(E[:, 0, 0, 0].astype(int))
+    np.testing.assert_array_equal(cum, np.floor(np.arange(T) * delta / C + 1e-12).astype(int))
+    assert np.all(E[:, 1] == 0)
+    # the mirrored ramp emits the same counts as OFF events
+    E2 = prologue.contrast_events(_gray_from_log((2 * l[0] - l)[:, None, None] * np.ones((1, 2, 3))), C)
+    np.testing.assert_array_equal(E2[:, 1], E[:, 0])
+    assert np.all(E2[:, 0] == 0)
+
+
+def test_contrast_events_step_constant_and_balance():
+    C = 0.2
+    l = np.full(8, np.log(40.0))
+    l[3:] += 3.3 * C
+    E = prologue.contrast_events(_gray_from_log(l[:, None, None] * np.ones((1, 1, 1))), C)
+    np.testing.assert_array_equal(E[:, 0, 0, 0], [0, 0, 0, 3, 0, 0, 0, 0])
+    # constant frames: nothing; random clips: the events account for the log change within C
+    rng = np.random.default_rng(5)
+    fr = rng.uniform(0.05, 1.0, size=(12, 3, 5, 4))
+    E = prologue.contrast_events(fr, C).astype(np.float64)
+    lg = prologue.linlog(prologue.luminance(fr))
+    resid = lg[-1] - lg[0] - C * (E[:, 0] - E[:, 1]).sum(axis=0)
+    assert np.all(np.abs(resid) < C + 1e-12)
+    assert np.all(prologue.contrast_events(np.stack([fr[0]] * 6), C) == 0)
