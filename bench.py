@@ -257,6 +257,43 @@ def batched_form(torch, synth, evs, dev, args):
             "single_clip_loop_value": round(px / PX720 / (t_single / 1e3), 1)}
 
 
+def prologue_form(torch, evs, x, args):
+    """Eq. (1) network input (RGB frames -> log-difference X) and the
+    contrast-crossing target generator over the same 720p clip."""
+    T = x.shape[1]
+    X = torch.empty(1, T - 1, 1, x.shape[3], x.shape[4], dtype=torch.float32, device=x.device)
+    E = None
+    res = {}
+    for name in ("logdiff", "contrast_events"):
+        def run():
+            nonlocal E
+            if name == "logdiff":
+                evs.logdiff(x, out=X)
+            else:
+                E = evs.contrast_events(x)
+        for _ in range(max(1, args.warmup)):
+            run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(3, args.steps // 2)):
+            tm = Timer(torch)
+            with tm:
+                run()
+            ts.append(tm)
+        torch.cuda.synchronize()
+        ms = float(np.mean([t.ms() for t in ts]))
+        px = x.shape[3] * x.shape[4]
+        by = (T * 12 + (T - 1) * 4) * px if name == "logdiff" else T * (12 + 2) * px
+        gbs = by / (ms / 1e3) / 1e9
+        res[name] = {"ms": round(ms, 3), "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "bytes": by}
+        log(f"{name}: {ms:.2f} ms, {gbs:.0f} GB/s")
+    del X, E
+    res["workload"] = ("same 1000-frame 720p clip: Eq. (1) log-difference input (lum_scale 255, knee 20) and "
+                       "contrast-crossing events (C = 0.2) of its frames")
+    return res
+
+
 def cpu_baseline(x_host, ws, channels, theta, leak, frames):
     from oracle import evsnet
     try:
@@ -279,7 +316,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1000, help="clip length of the headline workload")
-    ap.add_argument("--forms", default="fp32,compact,w32,train,batched")
+    ap.add_argument("--forms", default="fp32,compact,w32,prologue,train,batched")
     ap.add_argument("--cpu-frames", type=int, default=16)
     ap.add_argument("--batch-window", type=int, default=200, help="frames per window of the batched form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -423,6 +460,8 @@ def main():
             log(f"w32 {prec}: {ms:.2f} ms, {px_frames / PX720 / (ms / 1e3):.0f} fps")
         del o3
 
+    if "prologue" in forms:
+        rec["forms"]["prologue"] = prologue_form(torch, evs, x, args)
     if events is not None:
         del events, cws
     if "train" in forms:

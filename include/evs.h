@@ -11,6 +11,8 @@
  *   evs_backward        the surrogate-gradient BPTT backward (Eq. 4)
  *   evs_emd_loss        the bidirectional polarity-split EMD loss (Eq. 7-11)
  *   evs_compact_events  dense spike frames -> (t, x, y, c, polarity) events
+ *   evs_logdiff         the network input of Eq. 1 from RGB frames
+ *   evs_contrast_events contrast-crossing target events of clean frames
  *
  * Network definition, per frame t and layer l = 1..L (s_0[t] = x[t]):
  *   u_l[t] = conv3x3(s_{l-1}[t], W_l)       zero "same" padding, stride 1,
@@ -210,6 +212,30 @@ int evs_emd_loss(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t 
 int evs_compact_events(const int8_t* s, int32_t T, int32_t C, int32_t H, int32_t W,
                        uint64_t* events, int64_t capacity, int64_t* count,
                        void* ws, size_t ws_bytes, void* stream);
+
+/* Network input of Eq. (1) (Sec. 3.2): per pixel the Rec. 709 luminance
+ * L = lum_scale * (0.2126 R + 0.7152 G + 0.0722 B) of linear RGB frames,
+ * mapped to ln L at and above the knee and to (ln knee / knee) * L below it,
+ * and differenced in time: X_k = L_log[k] - L_log[k-1] for k = 1..T.  The
+ * result is the input of a one-channel net (ch[0] = 1).
+ *   rgb    [N][T+1][3][H][W] float32 frames 0..T
+ *   x_out  [N][T][1][H][W] float32
+ *   lum_scale, knee  > 0 (the paper's rho; e.g. 255 and 20)
+ * No workspace; graph-capturable.                                        */
+int evs_logdiff(const float* rgb, int32_t N, int32_t T, int32_t H, int32_t W,
+                float lum_scale, float knee, float* x_out, void* stream);
+
+/* Contrast-crossing events of clean frames (training targets standing in
+ * for the event simulator the paper trains against): per pixel, with L_log
+ * as in evs_logdiff, the reference level starts at frame 0; at frame t >= 1
+ * d = L_log[t] - ref emits n = sgn(d) floor(|d| / C) events, ref += n C.
+ *   rgb    [N][T][3][H][W] float32 clean frames
+ *   e_out  [N][T][2][H][W] int8: channel 0 ON = max(n, 0), channel 1
+ *          OFF = max(-n, 0), clamped to 127; frame 0 is all zero
+ *   C      contrast threshold > 0
+ * FP32 arithmetic; no workspace; graph-capturable.                       */
+int evs_contrast_events(const float* rgb, int32_t N, int32_t T, int32_t H, int32_t W,
+                        float lum_scale, float knee, float C, int8_t* e_out, void* stream);
 
 /* Time the compiled tile shapes for this network and frame size on
  * `stream` (allocates its own scratch; not capture-safe) and remember the

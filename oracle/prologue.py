@@ -65,15 +65,16 @@ def contrast_events(rgb: np.ndarray, C: float = 0.2, lum_scale: float = 255.0, k
 
 
 def contrast_margin(rgb: np.ndarray, C: float = 0.2, lum_scale: float = 255.0, knee: float = 20.0) -> np.ndarray:
-    """Per pixel, the smallest distance of |d| / C to an integer over all
-    frames (along the oracle's own trajectory): where it is tiny, a rounding
-    of a different precision may decide the event count differently."""
+    """Per pixel, the smallest distance of q = |d| / C to a boundary of
+    floor(q), i.e. to an integer >= 1, over all frames (along the oracle's own
+    trajectory): where it is tiny, a rounding of a different precision may
+    decide the event count differently."""
     l = linlog(luminance(rgb, lum_scale), knee)
     ref = l[0].copy()
     m = np.full(l.shape[1:], np.inf)
     for t in range(1, l.shape[0]):
         d = l[t] - ref
         q = np.abs(d) / C
-        m = np.minimum(m, np.abs(q - np.round(q)))
+        m = np.minimum(m, np.abs(q - np.maximum(np.round(q), 1.0)))
         ref = ref + np.sign(d) * np.floor(q) * C
     return m

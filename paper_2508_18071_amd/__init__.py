@@ -5,9 +5,9 @@ include/evs.h); this package only marshals torch tensors into it.
 """
 
 from .api import (Net, Graph, pack_weights, forward, forward_batched, backward, emd_loss,
-                  compact_events, autotune, set_tile, tile_count, tile_name)
+                  compact_events, logdiff, contrast_events, autotune, set_tile, tile_count, tile_name)
 from ._lib import lib, EvsError, LIB_PATH, EXPORTED
 
 __all__ = ["Net", "Graph", "pack_weights", "forward", "forward_batched", "backward", "emd_loss",
-           "compact_events", "autotune", "set_tile", "tile_count", "tile_name", "lib",
+           "compact_events", "logdiff", "contrast_events", "autotune", "set_tile", "tile_count", "tile_name", "lib",
            "EvsError", "LIB_PATH", "EXPORTED"]

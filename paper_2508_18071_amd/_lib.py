@@ -63,6 +63,11 @@ _SIGS = [
     ("evs_compact_events", ctypes.c_int,
      [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P,
       _P, ctypes.c_size_t, _P]),
+    ("evs_logdiff", ctypes.c_int,
+     [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _P, _P]),
+    ("evs_contrast_events", ctypes.c_int,
+     [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+      ctypes.c_float, _P, _P]),
     ("evs_autotune", ctypes.c_int,
      [ctypes.POINTER(EvsNet), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
       ctypes.POINTER(ctypes.c_int32), _P]),

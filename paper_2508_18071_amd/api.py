@@ -235,6 +235,37 @@ def compact_events(s: torch.Tensor, capacity: int | None = None, stream=None):
     return ev, cnt
 
 
+def logdiff(rgb: torch.Tensor, lum_scale: float = 255.0, knee: float = 20.0, out=None, stream=None):
+    """Network input of Eq. (1): RGB frames [N, T+1, 3, H, W] (or [T+1, 3, H, W])
+    -> X [N, T, 1, H, W], the temporal difference of the lin-log luminance."""
+    _check_dev(rgb)
+    if rgb.dim() == 4:
+        rgb = rgb.unsqueeze(0)
+    N, T1, C, H, W = rgb.shape
+    if C != 3 or T1 < 2:
+        raise ValueError("logdiff needs [N, T+1, 3, H, W] frames with T >= 1")
+    x = out if out is not None else torch.empty(N, T1 - 1, 1, H, W, dtype=torch.float32, device=rgb.device)
+    check(lib().evs_logdiff(rgb.data_ptr(), N, T1 - 1, H, W, float(lum_scale), float(knee), x.data_ptr(),
+                            _stream(stream)), "logdiff")
+    return x
+
+
+def contrast_events(rgb: torch.Tensor, C: float = 0.2, lum_scale: float = 255.0, knee: float = 20.0, stream=None):
+    """Target events of clean frames [N, T, 3, H, W] (or [T, 3, H, W]) -> int8
+    [N, T, 2, H, W] ON/OFF counts of an ideal contrast-threshold camera."""
+    _check_dev(rgb)
+    squeeze = rgb.dim() == 4
+    if squeeze:
+        rgb = rgb.unsqueeze(0)
+    N, T, ch, H, W = rgb.shape
+    if ch != 3:
+        raise ValueError("contrast_events needs RGB frames")
+    e = torch.empty(N, T, 2, H, W, dtype=torch.int8, device=rgb.device)
+    check(lib().evs_contrast_events(rgb.data_ptr(), N, T, H, W, float(lum_scale), float(knee), float(C),
+                                    e.data_ptr(), _stream(stream)), "contrast_events")
+    return e[0] if squeeze else e
+
+
 def backward(net: Net, packed, x, ckpt, ckpt_every, grad_s, want_dx=False, want_dv=False, stream=None):
     """BPTT backward; returns (list of dW, dx or None, dv or None)."""
     if x.dim() == 4:

@@ -16,4 +16,12 @@ int evs_compact_events(const int8_t* s, int32_t T, int32_t C, int32_t H, int32_t
                        int64_t capacity, int64_t* count, void* ws, size_t wsb, void* stream) {
   return evs::compact_events(s, T, C, H, W, events, capacity, count, ws, wsb, (hipStream_t)stream);
 }
+int evs_logdiff(const float* rgb, int32_t N, int32_t T, int32_t H, int32_t W, float lum_scale, float knee,
+                float* x_out, void* stream) {
+  return evs::logdiff(rgb, N, T, H, W, lum_scale, knee, x_out, (hipStream_t)stream);
+}
+int evs_contrast_events(const float* rgb, int32_t N, int32_t T, int32_t H, int32_t W, float lum_scale, float knee,
+                        float C, int8_t* e_out, void* stream) {
+  return evs::contrast_events(rgb, N, T, H, W, lum_scale, knee, C, e_out, (hipStream_t)stream);
+}
 }
