@@ -84,9 +84,22 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
  *   surrogate  smooth step sigma of the surrogate and of relaxed spikes:
  *              EVS_SURR_SIGMOID (0) sigma(z) = 1/(1+exp(-alpha z)), or
  *              EVS_SURR_ATAN (1) sigma(z) = 1/2 + arctan(pi/2 alpha z)/pi,
- *              the arctangent surrogate the paper trains with (Sec. 3.3).  */
+ *              the arctangent surrogate the paper trains with (Sec. 3.3).
+ *   input      what evs_forward reads from clip x:
+ *              EVS_INPUT_DIRECT (0): the network input itself,
+ *              [N][T][ch[0]][H][W].
+ *              EVS_INPUT_RGB_LOGDIFF (1): T+1 linear RGB frames
+ *              [N][T+1][3][H][W]; the forward forms the one-channel input of
+ *              Eq. 1 (Sec. 3.2) as it stages each frame, bit-identical to
+ *              evs_logdiff with the same lum_scale and knee.  Needs ch[0] = 1
+ *              and FP32; forward only (one clip per call): evs_backward
+ *              rejects it, training passes the output of evs_logdiff.
+ *   lum_scale, knee  used with EVS_INPUT_RGB_LOGDIFF only, as in
+ *              evs_logdiff (255 and 20 in the paper's reading).           */
 #define EVS_SURR_SIGMOID 0
 #define EVS_SURR_ATAN 1
+#define EVS_INPUT_DIRECT 0
+#define EVS_INPUT_RGB_LOGDIFF 1
 typedef struct evs_net {
   int32_t n_layers;
   int32_t ch[4];
@@ -97,10 +110,15 @@ typedef struct evs_net {
   int32_t relaxed;
   int32_t detach_reset;
   int32_t surrogate;
+  int32_t input;
+  float lum_scale;
+  float knee;
 } evs_net;
 
 /* One clip, or a batch of N clips of equal shape (host struct).
- *   x        [N][T][Cin][H][W] float32, the noisy linear RGB frames
+ *   x        [N][T][Cin][H][W] float32, the network input (noisy linear
+ *            RGB frames for Cin = 3); [N][T+1][3][H][W] RGB frames for
+ *            nets with input = EVS_INPUT_RGB_LOGDIFF
  *   s_out    [N][T][Cout][H][W] spikes: int8 in {-1,0,1} (s_fp32 = 0) or
  *            float32 (s_fp32 = 1; required for relaxed nets); may be NULL
  *   v_state  NULL, or [N][sum_l C_l][H][W] float32 membrane potentials of

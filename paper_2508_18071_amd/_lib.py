@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libevs.so")
 EVS_OK, EVS_EINVAL, EVS_EUNSUPPORTED, EVS_EWORKSPACE, EVS_EHIP, EVS_EOVERFLOW = range(6)
 EVS_FP32, EVS_BF16 = 0, 1
 EVS_SURR_SIGMOID, EVS_SURR_ATAN = 0, 1
+EVS_INPUT_DIRECT, EVS_INPUT_RGB_LOGDIFF = 0, 1
 EVS_OP_FORWARD, EVS_OP_BACKWARD, EVS_OP_EMD, EVS_OP_COMPACT = range(4)
 
 
@@ -29,6 +30,9 @@ class EvsNet(ctypes.Structure):
         ("relaxed", ctypes.c_int32),
         ("detach_reset", ctypes.c_int32),
         ("surrogate", ctypes.c_int32),
+        ("input", ctypes.c_int32),
+        ("lum_scale", ctypes.c_float),
+        ("knee", ctypes.c_float),
     ]
 
 

@@ -26,6 +26,11 @@ class Net:
     relaxed: bool = False
     detach_reset: bool = False
     surrogate: str = "sigmoid"      # "sigmoid" or "atan" (the paper's arctangent surrogate)
+    # "direct": x is the network input; "rgb_logdiff": x holds T+1 RGB frames
+    # and the forward forms the one-channel Eq. (1) input itself
+    input: str = "direct"
+    lum_scale: float = 255.0
+    knee: float = 20.0
 
     def c(self) -> EvsNet:
         n = EvsNet()
@@ -40,6 +45,9 @@ class Net:
         n.relaxed = int(self.relaxed)
         n.detach_reset = int(self.detach_reset)
         n.surrogate = {"sigmoid": 0, "atan": 1}[self.surrogate]
+        n.input = {"direct": 0, "rgb_logdiff": 1}[self.input]
+        n.lum_scale = self.lum_scale
+        n.knee = self.knee
         return n
 
     @property
@@ -134,7 +142,11 @@ def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = F
     if x.dtype != torch.float32:
         raise ValueError("x must be float32")
     N, T, C, H, W = x.shape
-    if C != net.channels[0]:
+    if net.input == "rgb_logdiff":
+        if C != 3 or T < 2:
+            raise ValueError("rgb_logdiff input needs [N, T+1, 3, H, W] frames with T >= 1")
+        T -= 1
+    elif C != net.channels[0]:
         raise ValueError("x channels do not match the network")
     dev = x.device
     cout = net.channels[-1]
@@ -147,6 +159,7 @@ def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = F
         nseg = (T + ckpt_every - 1) // ckpt_every
         ck = torch.empty(N, nseg, net.sum_c, H, W, dtype=torch.float32, device=dev)
     c = _clip(x, out, s_fp32, v_state, h, trace_box)
+    c.T = T
     if ws is None:
         ws, nb = workspace(net, [c], device=dev)
     else:

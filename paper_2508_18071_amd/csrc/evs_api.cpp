@@ -1,5 +1,6 @@
 // C ABI of libevs: argument validation, workspace sizing, tile selection and
 // dispatch to the HIP kernels.  Declared in include/evs.h.
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -44,13 +45,21 @@ int validate_net(const evs_net* net) {
   if (net->relaxed && net->precision != EVS_FP32) return fail(EVS_EUNSUPPORTED, "relaxed spikes need FP32");
   if (net->surrogate != EVS_SURR_SIGMOID && net->surrogate != EVS_SURR_ATAN)
     return fail(EVS_EINVAL, "surrogate must be EVS_SURR_SIGMOID or EVS_SURR_ATAN");
+  if (net->input != EVS_INPUT_DIRECT && net->input != EVS_INPUT_RGB_LOGDIFF)
+    return fail(EVS_EINVAL, "input must be EVS_INPUT_DIRECT or EVS_INPUT_RGB_LOGDIFF");
+  if (net->input == EVS_INPUT_RGB_LOGDIFF) {
+    if (net->ch[0] != 1) return fail(EVS_EINVAL, "RGB log-difference input feeds a one-channel net (ch[0] = 1)");
+    if (net->precision != EVS_FP32) return fail(EVS_EUNSUPPORTED, "RGB log-difference input needs FP32");
+    if (!(net->lum_scale > 0.f) || !(net->knee > 0.f) || !(net->lum_scale < 3.0e38f) || !(net->knee < 3.0e38f))
+      return fail(EVS_EINVAL, "lum_scale and knee must be positive and finite");
+  }
   return EVS_OK;
 }
 
 int validate_clip(const evs_net& net, const evs_clip& c, bool need_x) {
   if (c.N < 1 || c.T < 1 || c.H < 1 || c.W < 1) return fail(EVS_EINVAL, "clip N, T, H, W must be >= 1");
   if (c.H > 4096 || c.W > 4096) return fail(EVS_EUNSUPPORTED, "frame size above 4096");
-  if ((double)c.N * c.T * net.ch[0] * c.H * c.W > 9.0e18) return fail(EVS_EOVERFLOW, "clip too large");
+  if ((double)c.N * (c.T + 1) * 3 * c.H * c.W > 9.0e18) return fail(EVS_EOVERFLOW, "clip too large");
   if (need_x && !c.x) return fail(EVS_EINVAL, "clip x is NULL");
   if (net.relaxed && c.s_out && !c.s_fp32) return fail(EVS_EINVAL, "relaxed spikes need s_fp32 = 1");
   if (c.trace_box[2] > 0 || c.trace_box[3] > 0) {
@@ -116,6 +125,10 @@ FwdNetArgs make_net_args(const evs_net& net, const void* packed) {
   na.leak = net.leak;
   na.alpha = net.surr_alpha;
   na.relaxed = net.relaxed ? 1 + net.surrogate : 0;     // 0 hard, 1 sigmoid, 2 arctangent
+  na.x_rgb = net.input == EVS_INPUT_RGB_LOGDIFF ? 1 : 0;
+  na.lum_scale = net.lum_scale;
+  na.knee = net.knee;
+  na.toe = na.x_rgb ? (float)(std::log((double)net.knee) / (double)net.knee) : 0.f;
   return na;
 }
 
@@ -224,7 +237,7 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
     ca.tiles_x = (c.W + tw - 1) / tw;
     ca.tiles_y = (c.H + th - 1) / th;
     const int64_t HW = (int64_t)c.H * c.W;
-    ca.x_nstride = (int64_t)c.T * net->ch[0] * HW;
+    ca.x_nstride = net->input == EVS_INPUT_RGB_LOGDIFF ? (int64_t)(c.T + 1) * 3 * HW : (int64_t)c.T * net->ch[0] * HW;
     ca.vin_nstride = (int64_t)sumc * HW;
     if (c.trace_box[2] > 0) {
       ca.tb_y0 = c.trace_box[0]; ca.tb_x0 = c.trace_box[1]; ca.tb_h = c.trace_box[2]; ca.tb_w = c.trace_box[3];
@@ -261,6 +274,7 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
   const int tile = forward_batched_tile(*net, choose_tile(*net, clips[big].H, clips[big].W));
   if (tile < 0) return fail(EVS_EUNSUPPORTED, "no batched kernel compiled for this network");
   if (net->relaxed) return fail(EVS_EUNSUPPORTED, "batched forward: relaxed spikes not supported");
+  if (net->input != EVS_INPUT_DIRECT) return fail(EVS_EUNSUPPORTED, "batched forward: direct input only");
   for (int i = 0; i < n_clips; ++i)
     if (clips[i].s_fp32 || clips[i].h_trace)
       return fail(EVS_EUNSUPPORTED, "batched forward: int8 spikes only, no traces");

@@ -100,14 +100,16 @@ int evs_autotune(const evs_net* net, int32_t H, int32_t W, int32_t T, int32_t* c
   float *x = nullptr, *w = nullptr;
   int8_t* out = nullptr;
   hipEvent_t e0, e1;
-  EVS_HIP(hipMalloc(&x, (size_t)T * cin * HW * 4));
+  // RGB log-difference nets read T+1 RGB frames
+  const size_t xfl = net->input == EVS_INPUT_RGB_LOGDIFF ? (size_t)(T + 1) * 3 * HW : (size_t)T * cin * HW;
+  EVS_HIP(hipMalloc(&x, xfl * 4));
   EVS_HIP(hipMalloc(&w, wfl * 4));
   EVS_HIP(hipMalloc(&out, (size_t)T * cout * HW));
   EVS_HIP(hipEventCreate(&e0));
   EVS_HIP(hipEventCreate(&e1));
   int best = 0;
   float best_ms = 1e30f;
-  if ((st = fill_uniform(x, (size_t)T * cin * HW, 1u, 0.f, 2.f, s)) ||
+  if ((st = fill_uniform(x, xfl, 1u, 0.f, 2.f, s)) ||
       (st = fill_uniform(w, wfl, 2u, -0.5f, 0.5f, s))) goto done;
   {
     const FwdNetArgs na = make_net_args(*net, w);
@@ -115,7 +117,7 @@ int evs_autotune(const evs_net* net, int32_t H, int32_t W, int32_t T, int32_t* c
     ca.x = x;
     ca.s_out = out;
     ca.N = 1; ca.T = T; ca.H = H; ca.W = W;
-    ca.x_nstride = (int64_t)T * cin * HW;
+    ca.x_nstride = (int64_t)xfl;
     for (int tile = 0; tile < n; ++tile) {
       int th, tw;
       forward_tile_dims(*net, tile, &th, &tw);

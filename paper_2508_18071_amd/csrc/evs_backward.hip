@@ -268,7 +268,7 @@ BwdLayout layout(const evs_net& net, const evs_clip& c, int k) {
 }  // namespace
 
 size_t backward_workspace_bytes(const evs_net& net, const evs_clip& clip, int ckpt_every) {
-  if (validate_clip(net, clip, false) != EVS_OK || ckpt_every < 1) return (size_t)-1;
+  if (net.input != EVS_INPUT_DIRECT || validate_clip(net, clip, false) != EVS_OK || ckpt_every < 1) return (size_t)-1;
   return layout(net, clip, ckpt_every < clip.T ? ckpt_every : clip.T).total;
 }
 
@@ -277,6 +277,8 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
              hipStream_t st) {
   int rc = validate_net(&net);
   if (rc) return rc;
+  if (net.input != EVS_INPUT_DIRECT)
+    return fail(EVS_EUNSUPPORTED, "backward: direct input only (pass the output of evs_logdiff)");
   if ((rc = validate_clip(net, clip, true))) return rc;
   if (!packed || !ckpt || !grad_s || !grad_w) return fail(EVS_EINVAL, "backward: NULL argument");
   if (ckpt_every < 1) return fail(EVS_EINVAL, "backward: ckpt_every must be >= 1");

@@ -1,5 +1,6 @@
-// Device-side helpers shared by the forward and backward kernels, so that a
-// recomputed spike is bit-identical to the one the forward emitted.
+// Device-side helpers shared by the forward, backward and input kernels, so
+// that a recomputed spike (or input) is bit-identical to the one the forward
+// used.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,6 +8,16 @@
 namespace evs {
 
 __device__ inline float sigm_fast(float z) { return __frcp_rn(1.0f + __expf(-z)); }
+
+// Lin-log luminance of Eq. (1) (Sec. 3.2) of one linear RGB pixel:
+// L = scale (0.2126 R + 0.7152 G + 0.0722 B), then ln L at and above the knee
+// and toe * L below it (toe = ln(knee) / knee, so the branches meet).  Every
+// operation is spelled out (no contraction), so the stand-alone input kernel
+// and the forward's fused input staging compute identical bits.
+__device__ inline float linlog_lum(float r, float g, float b, float scale, float knee, float toe) {
+  const float L = __fmul_rn(scale, __fmaf_rn(0.0722f, b, __fmaf_rn(0.7152f, g, __fmul_rn(0.2126f, r))));
+  return L >= knee ? logf(L) : __fmul_rn(toe, L);
+}
 
 // Smooth step of the surrogate (Sec. 3.3, Eq. 4) and its slope.
 //   kind 0: logistic sigmoid 1 / (1 + exp(-alpha z))

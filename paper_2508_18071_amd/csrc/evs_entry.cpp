@@ -6,6 +6,7 @@ extern "C" {
 int evs_backward(const evs_net* net, const void* packed, const evs_clip* clip, const float* ckpt, int32_t k,
                  const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v, void* ws, size_t wsb,
                  void* stream) {
+  if (!net || !clip) return evs::fail(EVS_EINVAL, "backward: net or clip is NULL");
   return evs::backward(*net, packed, *clip, ckpt, k, grad_s, grad_w, grad_x, grad_v, ws, wsb, (hipStream_t)stream);
 }
 int evs_emd_loss(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t C, int32_t H, int32_t W,

@@ -51,12 +51,19 @@ constexpr int align16(int b) { return (b + 15) & ~15; }
 
 // MODE_: 0 = inference; 1 = training/debug features (h traces, membrane
 // checkpoints, FP32 spike output); 2 = relaxed (smooth) spikes with the
-// features of mode 1.  Only mode 0 leaves the feature code out of the loop.
+// features of mode 1; 3 = inference with the wave-specialised schedule
+// (FP32 three-layer 16-channel nets only).  Modes 0 and 3 leave the feature
+// code out of the loop.  MODE_ + 4 (modes 0-2 of one-channel FP32 nets):
+// x holds RGB frames and the input of Eq. (1) is formed while staging.
 template <int NL_, int CIN_, int CH_, bool BF16_, int TH_, int TW_, int NW_, int MODE_>
 struct Cfg {
   static constexpr int NL = NL_, CIN = CIN_, CH = CH_, TH = TH_, TW = TW_, NW = NW_, MODE = MODE_;
-  static constexpr bool BF16 = BF16_, FULL = MODE_ >= 1, RELAX = MODE_ == 2;
+  static constexpr int BMODE = MODE_ & 3;
+  static constexpr bool LOGX = MODE_ >= 4;
+  static constexpr bool BF16 = BF16_, FULL = BMODE == 1 || BMODE == 2, RELAX = BMODE == 2;
+  static_assert(!LOGX || (CIN_ == 1 && !BF16_ && BMODE != 3), "RGB input: one-channel FP32 nets, modes 0-2");
   static_assert(!(BF16_ && MODE_ == 2), "relaxed spikes are FP32 only");
+  static_assert(MODE_ != 3 || (!BF16_ && NL_ == 3 && CH_ == 16 && NW_ == 8), "mode 3: FP32 3-layer h16 w8 only");
   static constexpr int CO = 2;                       // output channels (max)
   static constexpr int NH = NL - 1;                  // hidden layers
   static constexpr int CHT = TH + 2 * NL, CWT = TW + 2 * NL;
@@ -89,7 +96,7 @@ struct Cfg {
   // x planes plus one all-zero plane read by the padded K slots of layer 1;
   // FP32 nets with hidden layers fill them by direct global -> LDS loads of
   // 64-pixel chunks into two buffers (frame t+1 lands while t is read)
-  static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX;
+  static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX && !LOGX;
   static constexpr int XCK = CIN * CHT;              // x chunks: one canvas row of one plane
   static constexpr int XPW = cdiv(XCK, NW);          // chunk loads per wave and frame
   // x buffer: front pad, CIN planes and the zero plane back to back (plane
@@ -107,10 +114,9 @@ struct Cfg {
   static constexpr int S2OFF = SEP ? SP1_BYTES : 0;
   static constexpr int SP_BYTES = SP1_BYTES * (SEP ? 2 : 1);
   static constexpr int WL_FLOATS = OMF ? 0 : 9 * (NH >= 1 ? CH : CIN) * CO;
-  // wave-specialised schedule (FP32 three-layer 16-channel inference
-  // kernel): layer-2 blocks over waves 0-3, layer-1 and output blocks over
-  // waves 4-7
-  static constexpr bool PIPE = !BF16 && NH == 2 && CH == 16 && NW == 8 && MODE == 0;
+  // wave-specialised schedule (mode 3): layer-2 blocks over waves 0-3,
+  // layer-1 and output blocks over waves 4-7
+  static constexpr bool PIPE = MODE == 3;
   static constexpr int NB1V = cdiv(nblk(1), 4), NB2M = cdiv(nblk(2), 4), NBOV = cdiv(nblk(NL), 4);
   static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
   static_assert(NB1 <= 32 && NB2 <= 32 && NBO <= 32 && NOUT <= 32, "mask words overflow");
@@ -855,22 +861,30 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       }
     }
   };
-  // (b) other nets: register prefetch of the next frame
-  float xpf[C::XDMA ? 1 : C::XPF];
-  auto load_x = [&](int tt) __attribute__((always_inline)) {
+  // (b) other nets: register prefetch of the next frame.  With RGB input
+  // (LOGX) a lane prefetches the three colours of its canvas pixels of RGB
+  // frame tt + 1 and keeps the lin-log luminance of frame tt of the same
+  // pixels (xl_prev), so input frame tt is X = L_log[tt + 1] - L_log[tt];
+  // pixels outside the image load zeros and give X = 0 (the zero padding).
+  constexpr int XPR = C::LOGX ? 3 : 1;
+  float xpf[C::XDMA ? 1 : C::XPF * XPR];
+  float xl_prev[C::LOGX ? C::XPF : 1];
+  auto fetch_x = [&](int frame) __attribute__((always_inline)) {
     if constexpr (!C::XDMA) {
-      const float* xf = xclip + (size_t)tt * C::CIN * HW;
+      const float* xf = xclip + (size_t)frame * (C::LOGX ? 3 : C::CIN) * HW;
 #pragma unroll
       for (int k = 0; k < C::XPF; ++k) {
         const int e = tid + C::NT * k;
         const int c = e / C::NPIX, rem = e % C::NPIX;
         const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;
-        float v = 0.f;
-        if (e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = xf[(size_t)c * HW + (size_t)gy * W + gx];
-        xpf[k] = v;
+        const bool in = e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W;
+        const size_t o = (size_t)c * HW + (size_t)gy * W + gx;
+#pragma unroll
+        for (int r = 0; r < XPR; ++r) xpf[k * XPR + r] = in ? xf[o + (size_t)r * HW] : 0.f;
       }
     }
   };
+  auto load_x = [&](int tt) __attribute__((always_inline)) { fetch_x(C::LOGX ? tt + 1 : tt); };
   auto store_x = [&]() __attribute__((always_inline)) {
     if constexpr (!C::XDMA) {
 #pragma unroll
@@ -878,8 +892,14 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         const int e = tid + C::NT * k;
         if (e < C::XN) {
           const int c = e / C::NPIX, rem = e % C::NPIX;
-          if constexpr (C::BF16) xsb[c * C::XPL + C::PADF + rem] = f32_to_bf16_rne(xpf[k]);
-          else xsf[c * C::XPL + C::PADF + rem] = xpf[k];
+          float v = xpf[k * XPR];
+          if constexpr (C::LOGX) {
+            const float l = linlog_lum(xpf[3 * k], xpf[3 * k + 1], xpf[3 * k + 2], na.lum_scale, na.knee, na.toe);
+            v = __fsub_rn(l, xl_prev[k]);
+            xl_prev[k] = l;
+          }
+          if constexpr (C::BF16) xsb[c * C::XPL + C::PADF + rem] = f32_to_bf16_rne(v);
+          else xsf[c * C::XPL + C::PADF + rem] = v;
         }
       }
     }
@@ -923,6 +943,12 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     __syncthreads();
     if (T > 1) issue_x(1, 1);
   } else {
+    if constexpr (C::LOGX) {
+      fetch_x(0);
+#pragma unroll
+      for (int k = 0; k < C::XPF; ++k)
+        xl_prev[k] = linlog_lum(xpf[3 * k], xpf[3 * k + 1], xpf[3 * k + 2], na.lum_scale, na.knee, na.toe);
+    }
     load_x(0);
     store_x();
     if (T > 1) load_x(1);
@@ -1304,6 +1330,8 @@ struct Variant {
   void (*single_full)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*single_relaxed)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*batched)(const FwdNetArgs&, const BatchTable&, int32_t*, int ncu, hipStream_t, hipError_t*);
+  // RGB-input kernels of one-channel nets: inference, training/debug, relaxed
+  void (*logx[3])(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
 };
 
 template <class C>
@@ -1343,6 +1371,17 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
 #define EVS_VARIANT_B(NL, CIN, CH, BF, TH, TW, NW, NAME)                             \
   Variant{NL, CIN, CH, BF, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, BF, TH, TW, NW), \
           nullptr, &launch_batched<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 0)>}
+// one-channel FP32 nets: _R plus the RGB-input (Eq. 1) kernels
+#define EVS_VARIANT_RX(NL, CH, TH, TW, NW, NAME)                                              \
+  Variant{NL, 1, CH, 0, TH, TW, NAME, EVS_FAST_FULL(NL, 1, CH, 0, TH, TW, NW),                  \
+          &launch_single<EVS_CFG(NL, 1, CH, 0, TH, TW, NW, 2)>, nullptr,                        \
+          {&launch_single<EVS_CFG(NL, 1, CH, 0, TH, TW, NW, 4)>,                                \
+           &launch_single<EVS_CFG(NL, 1, CH, 0, TH, TW, NW, 5)>,                                \
+           &launch_single<EVS_CFG(NL, 1, CH, 0, TH, TW, NW, 6)>}}
+// the wave-specialised schedule as the inference kernel of a tile
+#define EVS_VARIANT_P(TH, TW, NAME)                                                              \
+  Variant{3, 3, 16, 0, TH, TW, NAME, &launch_single<EVS_CFG(3, 3, 16, 0, TH, TW, 8, 3)>,          \
+          &launch_single<EVS_CFG(3, 3, 16, 0, TH, TW, 8, 1)>, nullptr, nullptr}
 #define EVS_VARIANT_RB(NL, CIN, CH, TH, TW, NW, NAME)                                \
   Variant{NL, CIN, CH, 0, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, 0, TH, TW, NW),   \
           &launch_single<EVS_CFG(NL, CIN, CH, 0, TH, TW, NW, 2)>,                    \
@@ -1351,13 +1390,13 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
 // Tile variants per network shape; the first one of a shape is its default.
 const Variant kVariants[] = {
     // single-layer nets (input -> output), f32
-    EVS_VARIANT_R(1, 1, 16, 32, 32, 8, "L1 cin1 f32 32x32 w8"),
+    EVS_VARIANT_RX(1, 16, 32, 32, 8, "L1 cin1 f32 32x32 w8"),
     EVS_VARIANT_R(1, 3, 16, 32, 32, 8, "L1 cin3 f32 32x32 w8"),
     // two-layer nets cin -> hidden(<=16) -> out
     EVS_VARIANT_RB(2, 3, 16, 16, 32, 8, "L2 h16 f32 16x32 w8"),
     EVS_VARIANT(2, 3, 16, 0, 30, 40, 8, "L2 h16 f32 30x40 w8"),
     EVS_VARIANT(2, 3, 16, 0, 20, 32, 4, "L2 h16 f32 20x32 w4"),
-    EVS_VARIANT_R(2, 1, 16, 30, 40, 8, "L2 cin1 h16 f32 30x40 w8"),
+    EVS_VARIANT_RX(2, 16, 30, 40, 8, "L2 cin1 h16 f32 30x40 w8"),
     EVS_VARIANT(2, 3, 16, 1, 30, 40, 8, "L2 h16 bf16 30x40 w8"),
     // two-layer nets with hidden width <= 32
     EVS_VARIANT(2, 3, 32, 0, 24, 32, 8, "L2 h32 f32 24x32 w8"),
@@ -1373,6 +1412,7 @@ const Variant kVariants[] = {
     EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
     EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
     EVS_VARIANT(3, 3, 16, 0, 30, 32, 8, "L3 h16 f32 30x32 w8"),
+    EVS_VARIANT_P(24, 32, "L3 h16 f32 24x32 w8 pipe"),
     EVS_VARIANT(3, 3, 16, 1, 24, 32, 8, "L3 h16 bf16 24x32 w8"),
     EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40 w8"),
     EVS_VARIANT(3, 3, 16, 1, 16, 32, 4, "L3 h16 bf16 16x32 w4"),
@@ -1439,14 +1479,20 @@ int launch_forward(const evs_net& net, const FwdNetArgs& na, const FwdClipArgs& 
   const Variant* v = find_variant(net, tile_id);
   if (!v) return fail(EVS_EUNSUPPORTED, "no compiled forward kernel for this network shape");
   hipError_t e = hipSuccess;
-  if (na.relaxed) {
+  const bool full = ca.h_trace || ca.ckpt || ca.s_fp32;
+  if (na.x_rgb) {
+    // results do not depend on the tile: take the first variant of the shape that has the kernels
+    const int n = forward_tile_count(net);
+    for (int t = 0; t < n && !v->logx[0]; ++t) v = find_variant(net, t);
+    if (!v->logx[0]) return fail(EVS_EUNSUPPORTED, "no RGB-input kernel compiled for this network shape");
+    v->logx[na.relaxed ? 2 : (full ? 1 : 0)](na, ca, stream, &e);
+  } else if (na.relaxed) {
     // results do not depend on the tile: take the first variant of the shape that has the kernel
     const int n = forward_tile_count(net);
     for (int t = 0; t < n && !v->single_relaxed; ++t) v = find_variant(net, t);
     if (!v->single_relaxed) return fail(EVS_EUNSUPPORTED, "no relaxed-spike kernel compiled for this network shape");
     v->single_relaxed(na, ca, stream, &e);
   } else {
-    const bool full = ca.h_trace || ca.ckpt || ca.s_fp32;
     (full ? v->single_full : v->single_fast)(na, ca, stream, &e);
   }
   if (e != hipSuccess) return hip_check(e, "forward kernel launch");
@@ -1458,6 +1504,7 @@ int launch_forward_batched(const evs_net& net, const FwdNetArgs& na, const Batch
   const Variant* v = find_variant(net, tile_id);
   if (!v) return fail(EVS_EUNSUPPORTED, "no compiled forward kernel for this network shape");
   if (!v->batched) return fail(EVS_EUNSUPPORTED, "no batched kernel compiled for this tile variant");
+  if (na.x_rgb) return fail(EVS_EUNSUPPORTED, "batched forward: direct input only");
   int dev = 0, ncu = 0;
   EVS_HIP(hipGetDevice(&dev));
   EVS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));

@@ -53,7 +53,7 @@ __host__ __device__ inline float round_bf16(float f) { return bf16_to_f32(f32_to
 // ---------------------------------------------------------------- forward
 // Per-launch arguments of the forward kernels (one clip batch).
 struct FwdClipArgs {
-  const float* x;        // [N][T][Cin][H][W]
+  const float* x;        // [N][T][Cin][H][W], or [N][T+1][3][H][W] RGB (FwdNetArgs::x_rgb)
   void* s_out;           // [N][T][Cout][H][W] int8 or float, may be null
   float* v_out;          // [N][sumC][H][W] final state, may be null
   const float* v_in;     // [N][sumC][H][W] initial state, may be null
@@ -77,6 +77,10 @@ struct FwdNetArgs {
   int32_t sum_c;
   float theta, leak, alpha;
   int32_t relaxed;       // 0 hard spikes, 1 relaxed (sigmoid step), 2 relaxed (arctangent step)
+  // x holds T+1 RGB frames and the input is their lin-log luminance
+  // difference (Eq. 1): scale, knee and toe slope ln(knee) / knee
+  int32_t x_rgb;
+  float lum_scale, knee, toe;
 };
 
 // Batched (persistent) launch: a clip table passed by value.

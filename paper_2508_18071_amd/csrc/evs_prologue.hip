@@ -7,6 +7,7 @@
 // in a register.  HBM-bound.
 #include <cmath>
 
+#include "evs_device.hpp"
 #include "evs_ops.hpp"
 
 namespace evs {
@@ -14,11 +15,9 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// lin-log luminance of Eq. (1): L = s (0.2126 R + 0.7152 G + 0.0722 B), then
-// ln L at and above the knee, toe * L below it (toe = ln(knee) / knee)
-__device__ inline float linlog_lum(const float* f, size_t HW, float scale, float knee, float toe) {
-  const float L = scale * (0.2126f * f[0] + 0.7152f * f[HW] + 0.0722f * f[2 * HW]);
-  return L >= knee ? logf(L) : toe * L;
+// lin-log luminance of Eq. (1) of the pixel at f (planes HW apart)
+__device__ inline float linlog_at(const float* f, size_t HW, float scale, float knee, float toe) {
+  return linlog_lum(f[0], f[HW], f[2 * HW], scale, knee, toe);
 }
 
 // x_out[n][k-1][0][p] = L_log[k] - L_log[k-1], k = 1..T, from frames 0..T
@@ -30,10 +29,10 @@ __global__ __launch_bounds__(kThreads) void k_logdiff(const float* __restrict__ 
   const long long n = idx / HW, p = idx - n * HW;
   const float* f = rgb + (size_t)n * (T + 1) * 3 * HW + p;
   float* o = x_out + (size_t)n * T * HW + p;
-  float prev = linlog_lum(f, HW, scale, knee, toe);
+  float prev = linlog_at(f, HW, scale, knee, toe);
   for (int k = 1; k <= T; ++k) {
-    const float l = linlog_lum(f + (size_t)k * 3 * HW, HW, scale, knee, toe);
-    o[(size_t)(k - 1) * HW] = l - prev;
+    const float l = linlog_at(f + (size_t)k * 3 * HW, HW, scale, knee, toe);
+    o[(size_t)(k - 1) * HW] = __fsub_rn(l, prev);
     prev = l;
   }
 }
@@ -48,11 +47,11 @@ __global__ __launch_bounds__(kThreads) void k_contrast(const float* __restrict__
   const long long n = idx / HW, p = idx - n * HW;
   const float* f = rgb + (size_t)n * T * 3 * HW + p;
   int8_t* e = e_out + (size_t)n * T * 2 * HW + p;
-  float ref = linlog_lum(f, HW, scale, knee, toe);
+  float ref = linlog_at(f, HW, scale, knee, toe);
   e[0] = 0;
   e[HW] = 0;
   for (int t = 1; t < T; ++t) {
-    const float d = linlog_lum(f + (size_t)t * 3 * HW, HW, scale, knee, toe) - ref;
+    const float d = linlog_at(f + (size_t)t * 3 * HW, HW, scale, knee, toe) - ref;
     const float q = floorf(fabsf(d) / C);
     const float nev = d > 0.f ? q : (d < 0.f ? -q : 0.f);
     ref = fmaf(nev, C, ref);

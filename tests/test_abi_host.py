@@ -145,3 +145,40 @@ def test_tile_registry(evs):
         assert all(evs.tile_name(net, t) for t in range(n))
         with pytest.raises(evs.EvsError):
             evs.set_tile(net, n)
+
+
+@pytest.mark.parametrize("kw,field,code", [
+    (dict(channels=(3, 16, 2), input="rgb_logdiff"), None, 1),            # needs a one-channel net
+    (dict(channels=(1, 16, 2), input="rgb_logdiff", precision="bf16"), None, 2),
+    (dict(channels=(1, 16, 2), input="rgb_logdiff", knee=0.0), None, 1),
+    (dict(channels=(1, 16, 2), input="rgb_logdiff", lum_scale=float("nan")), None, 1),
+    (dict(channels=(1, 16, 2)), ("input", 2), 1),
+])
+def test_forward_rejects_bad_rgb_input(evs, kw, field, code):
+    net = _net(evs, **kw)
+    if field:
+        setattr(net, field[0], field[1])
+    c = evs._lib.EvsClip()
+    c.N, c.T, c.H, c.W = 1, 4, 8, 8
+    c.x = 16
+    st = evs.lib().evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0,
+                               None, 0, None)
+    assert st == code
+    assert evs.lib().evs_last_error()
+
+
+def test_backward_rejects_rgb_input(evs):
+    """Training takes the output of evs_logdiff: backward refuses RGB-input nets
+    before touching any pointer."""
+    net = _net(evs, channels=(1, 16, 2), input="rgb_logdiff")
+    c = evs._lib.EvsClip()
+    c.N, c.T, c.H, c.W = 1, 4, 8, 8
+    c.x = 16
+    L = evs.lib()
+    assert L.evs_workspace_bytes(ctypes.byref(net), ctypes.byref(c), 1, 2, evs._lib.EVS_OP_BACKWARD) == \
+        ctypes.c_size_t(-1).value
+    arr = (ctypes.c_void_p * 2)(16, 16)
+    st = L.evs_backward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), ctypes.c_void_p(16), 2,
+                        ctypes.c_void_p(16), arr, None, None, ctypes.c_void_p(16), 1 << 20, None)
+    assert st == 2
+    assert b"evs_logdiff" in L.evs_last_error()

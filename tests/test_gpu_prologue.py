@@ -115,3 +115,43 @@ def test_one_channel_net_on_gpu_logdiff(evs):
         assert r["outside"] == 0
     ref = evsnet.forward(x64, ws, THETA, LEAK)
     assert int(np.abs(ref["s"]).sum()) > 0
+
+
+@pytest.mark.parametrize("channels,N,T,H,W", [((1, 2), 2, 7, 45, 61), ((1, 16, 2), 2, 9, 45, 61),
+                                              ((1, 16, 2), 1, 5, 64, 83)])
+def test_fused_rgb_input_matches_two_pass(evs, channels, N, T, H, W):
+    """A net with input="rgb_logdiff" forms X of Eq. (1) while staging the RGB
+    frames; spikes, traces and final state are bit-identical to running the
+    direct-input net on evs_logdiff's X (inference, debug and relaxed
+    kernels), and a clip split in two windows with the state carried gives
+    the same spikes (each window re-reads its first RGB frame)."""
+    rgb = _frames(T + 1, H, W, N=N, seed=11)
+    ws = [w * 6.0 for w in synth.he_weights(channels, 1)]
+    rg = torch.from_numpy(rgb).cuda()
+    X = evs.logdiff(rg)
+    sum_c = sum(channels[1:])
+    for relaxed in (False, True):
+        nx = evs.Net(channels, theta=THETA, leak=LEAK, relaxed=relaxed)
+        nr = evs.Net(channels, theta=THETA, leak=LEAK, relaxed=relaxed, input="rgb_logdiff")
+        packed = evs.pack_weights(nx, [torch.from_numpy(w).cuda() for w in ws])
+        for debug in ((False, True) if not relaxed else (True,)):
+            v1 = torch.zeros(N, sum_c, H, W, device="cuda")
+            v2 = torch.zeros(N, sum_c, H, W, device="cuda")
+            a = evs.forward(nx, packed, X, v_state=v1, trace=debug, s_fp32=debug)
+            b = evs.forward(nr, packed, rg, v_state=v2, trace=debug, s_fp32=debug)
+            torch.cuda.synchronize()
+            print(f"  fused RGB input {channels} relaxed={relaxed} debug={debug}", flush=True)
+            assert torch.equal(a["s"], b["s"])
+            assert torch.equal(v1, v2)
+            if debug:
+                assert torch.equal(a["h"], b["h"])
+            assert int((a["s"] != 0).sum()) > 0
+        if not relaxed:
+            T1 = T // 2
+            v = torch.zeros(N, sum_c, H, W, device="cuda")
+            s1 = evs.forward(nr, packed, rg[:, : T1 + 1].contiguous(), v_state=v)["s"]
+            s2 = evs.forward(nr, packed, rg[:, T1:].contiguous(), v_state=v)["s"]
+            torch.cuda.synchronize()
+            full = evs.forward(nx, packed, X)["s"]
+            torch.cuda.synchronize()
+            assert torch.equal(torch.cat([s1, s2], dim=1), full)
