@@ -96,14 +96,21 @@ struct Cfg {
   // x planes plus one all-zero plane read by the padded K slots of layer 1;
   // FP32 nets with hidden layers fill them by direct global -> LDS loads of
   // 64-pixel chunks into two buffers (frame t+1 lands while t is read)
-  static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX && !LOGX;
+  // FP32 nets with three input channels and 16 hidden channels run layer 1
+  // on the bf16 pipe as well: each staged x value is split into three bf16
+  // parts (x = xh + xm + xl exactly) stored as per-pixel records of the three
+  // channels, one record plane per part (register staging, no raw x in LDS)
+  static constexpr bool XSPLIT = !BF16 && CIN == 3 && CH == 16 && NH >= 1 && !RELAX && !LOGX && MODE != 3;
+  static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX && !LOGX && !XSPLIT;
+  static constexpr int XPP = cdiv(NPIX, NT);         // canvas pixels staged per thread (XSPLIT)
+  static constexpr int NFR1 = 9;                     // XSPLIT A fragments: part h 4 k-steps, m 3, l 2
   static constexpr int XCK = CIN * CHT;              // x chunks: one canvas row of one plane
   static constexpr int XPW = cdiv(XCK, NW);          // chunk loads per wave and frame
   // x buffer: front pad, CIN planes and the zero plane back to back (plane
   // stride NPIX), then room for the neighbourhood of the junk pixel
   static constexpr int XPL = NPIX;
   static constexpr int XS1 = align16((PADF + (CIN + 1) * XPL + 2 * CWT + 4) * XELEM);
-  static constexpr int XS_BYTES = XS1 * (XDMA ? 2 : 1);
+  static constexpr int XS_BYTES = XSPLIT ? 3 * NPIXL * 8 : XS1 * (XDMA ? 2 : 1);
   static constexpr int SELEM = S16 ? 2 : 4;
   // bf16 spikes are stored as CH/8 planes of [pixel][8 channels] (16 B per
   // pixel): the 16 lanes of a lane group then read 256 contiguous bytes
@@ -143,6 +150,26 @@ __device__ inline unsigned pack_bf16x2(float lo, float hi) {
   return (__builtin_bit_cast(unsigned, lo) >> 16) | (__builtin_bit_cast(unsigned, hi) & 0xffff0000u);
 }
 
+// Split three FP32 values into bf16 parts x = h + m + l (round to nearest:
+// h = bf16(x), m = bf16(x - h), l = x - h - m, each exact) and pack them as
+// the records [x0 x1 x2 0] of parts h, m and l.
+__device__ inline void split3_records(float x0, float x1, float x2, uint2 (&rec)[3]) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  float r0 = x0, r1 = x1, r2 = x2;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const bf2 p01 = {(__bf16)r0, (__bf16)r1};
+    const bf2 p2z = {(__bf16)r2, (__bf16)0.f};
+    const unsigned u01 = __builtin_bit_cast(unsigned, p01), u2 = __builtin_bit_cast(unsigned, p2z);
+    rec[b] = uint2{u01, u2};
+    if (b < 2) {
+      r0 -= __builtin_bit_cast(float, u01 << 16);
+      r1 -= __builtin_bit_cast(float, u01 & 0xffff0000u);
+      r2 -= __builtin_bit_cast(float, u2 << 16);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ weights
 __device__ inline float wget(const FwdNetArgs& na, int layer, int co, int ci, int tap) {
   // layer 0-based; real channel bounds checked by the caller
@@ -158,6 +185,28 @@ __device__ inline float wpart(float w, int p) {
   const float r1 = w - hi;
   const float mid = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, r1) & 0xffff0000u);
   return p == 0 ? hi : (p == 1 ? mid : r1 - mid);
+}
+
+// Part p of the round-to-nearest split w = hi + mid + lo into bf16 values
+// (hi = bf16(w), mid = bf16(w - hi), lo = w - hi - mid, all exact): the split
+// of the layer-1 weights, whose x operand is split the same way.
+__device__ inline float wpart_rn(float w, int p) {
+  const float hi = round_bf16(w);
+  const float r1 = w - hi;
+  const float mid = round_bf16(r1);
+  return p == 0 ? hi : (p == 1 ? mid : r1 - mid);
+}
+
+// Layer-1 operand order of the split FP32 nets.  A k-step gives each lane
+// group two 4-entry x records; record R = 8q + 2g + r of k-step q is part
+// b = R / 9 (h, m, l) of the three channels at tap R % 9 (entry 3 is empty;
+// R >= 27 is padding).  Fragment f multiplies weight part p over k-step q:
+// f = 0..3 part h, q = 0..3; f = 4..6 part m, q = 0..2; f = 7..8 part l,
+// q = 0..1.  Part pairs (weight, x) kept: (h, any), (m, h), (m, m), (l, h);
+// the dropped (m, l), (l, m), (l, l) are below 2^-23 |w x| together.
+__device__ __forceinline__ void split_frag(int f, int& p, int& q) {
+  p = f < 4 ? 0 : (f < 7 ? 1 : 2);
+  q = f < 4 ? f : (f < 7 ? f - 4 : f - 7);
 }
 
 // The bf16 value a spike-operand MFMA multiplies: part p of the FP32 weight,
@@ -184,7 +233,8 @@ struct Layout {
   static constexpr int SP = XS + C::XS_BYTES;                   // spikes: bf16 [CH/8][NPIXL][8], f32 [NPIXL][CH] (x2 if SEP)
   static constexpr int WL = SP + C::SP_BYTES;                   // VALU output weights [9][CI][2] f32
   static constexpr int FR1 = WL + align16(C::WL_FLOATS * 4);    // layer-1 A fragments
-  static constexpr int FR1_BYTES = C::NH >= 1 ? C::KS1 * C::MB * 64 * (C::BF16 ? 16 : 4) : 0;
+  static constexpr int FR1_BYTES =
+      C::NH >= 1 ? (C::XSPLIT ? C::NFR1 * 64 * 16 : C::KS1 * C::MB * 64 * (C::BF16 ? 16 : 4)) : 0;
   static constexpr int FR2 = FR1 + FR1_BYTES;                   // layer-2 A fragments
   static constexpr int FR2_BYTES =
       C::NH >= 2 ? (C::S16 ? C::KB * C::NSP * C::MB * 64 * 16 : 9 * (C::CH / 16) * C::MB * 64 * 16) : 0;
@@ -210,7 +260,29 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
       wl[e] = (co < cout && ci < cin) ? wget(na, L, co, ci, tap) : 0.f;
     }
   }
-  if constexpr (C::NH >= 1) {
+  if constexpr (C::XSPLIT) {
+    const int c1 = na.ch[1];
+    // entry (f, lane): row co = lane%16, lane group g = lane/16
+    for (int e = threadIdx.x; e < C::NFR1 * 64; e += C::NT) {
+      const int lane = e % 64, f = e / 64;
+      const int co = lane & 15, g = lane >> 4;
+      int p, q;
+      split_frag(f, p, q);
+      unsigned wd[4];
+      for (int e2 = 0; e2 < 4; ++e2) {
+        float ww[2];
+        for (int h = 0; h < 2; ++h) {
+          const int slot = 2 * e2 + h;
+          const int R = 8 * q + 2 * g + (slot >> 2), c = slot & 3;
+          const int b = R / 9, tap = R % 9;
+          const bool keep = R < 27 && c < 3 && co < c1 && (b == 0 || (b == 1 && p <= 1) || (b == 2 && p == 0));
+          ww[h] = keep ? wpart_rn(wget(na, 0, co, c, tap), p) : 0.f;
+        }
+        wd[e2] = pack_bf16x2(ww[0], ww[1]);
+      }
+      reinterpret_cast<u4*>(lds + Lo::FR1)[e] = u4{wd[0], wd[1], wd[2], wd[3]};
+    }
+  } else if constexpr (C::NH >= 1) {
     const int c1 = na.ch[1];
     // entry (q, m, lane): row co = 16m + lane%16, lane group g = lane/16
     for (int e = threadIdx.x; e < C::KS1 * C::MB * 64; e += C::NT) {
@@ -866,11 +938,36 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   // frame tt + 1 and keeps the lin-log luminance of frame tt of the same
   // pixels (xl_prev), so input frame tt is X = L_log[tt + 1] - L_log[tt];
   // pixels outside the image load zeros and give X = 0 (the zero padding).
+  // Split FP32 nets (XSPLIT) prefetch the three channels of canvas pixels
+  // tid + NT k and store them as records [ch0 ch1 ch2 0] of bf16 parts, one
+  // 8-byte record per pixel in each of the part planes h, m, l.
+  int xo[C::XSPLIT ? C::XPP : 1];
+  if constexpr (C::XSPLIT) {
+#pragma unroll
+    for (int k = 0; k < C::XPP; ++k) {
+      const int q = tid + C::NT * k;
+      const int gy = gy0 + q / C::CWT, gx = gx0 + q % C::CWT;
+      const bool in = q < C::NPIX && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      xo[k] = in ? (gy * W + gx) * 4 : (int)0x80000000u;
+    }
+  }
   constexpr int XPR = C::LOGX ? 3 : 1;
-  float xpf[C::XDMA ? 1 : C::XPF * XPR];
+  constexpr int NXPF = C::XDMA ? 1 : (C::XSPLIT ? 3 * C::XPP : C::XPF * XPR);
+  float xpf[NXPF];
   float xl_prev[C::LOGX ? C::XPF : 1];
   auto fetch_x = [&](int frame) __attribute__((always_inline)) {
-    if constexpr (!C::XDMA) {
+    if constexpr (C::XSPLIT) {
+      // buffer loads: 32-bit pixel offsets, the channel offset in soffset;
+      // pixels outside the canvas or the image use an offset past the end,
+      // which reads zero
+      float* const xf = const_cast<float*>(xclip + (size_t)frame * 3 * HW);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(xf, (short)0, (int)(3 * HW * 4), 0x00020000);
+#pragma unroll
+      for (int k = 0; k < C::XPP; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          xpf[3 * k + c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, xo[k], c * (int)HW * 4, 0));
+    } else if constexpr (!C::XDMA) {
       const float* xf = xclip + (size_t)frame * (C::LOGX ? 3 : C::CIN) * HW;
 #pragma unroll
       for (int k = 0; k < C::XPF; ++k) {
@@ -886,7 +983,19 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   };
   auto load_x = [&](int tt) __attribute__((always_inline)) { fetch_x(C::LOGX ? tt + 1 : tt); };
   auto store_x = [&]() __attribute__((always_inline)) {
-    if constexpr (!C::XDMA) {
+    if constexpr (C::XSPLIT) {
+#pragma unroll
+      for (int k = 0; k < C::XPP; ++k) {
+        const int q = tid + C::NT * k;
+        if (q < C::NPIX) {
+          uint2 rec[3];
+          split3_records(xpf[3 * k], xpf[3 * k + 1], xpf[3 * k + 2], rec);
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            *reinterpret_cast<uint2*>(lds + Lo::XS + (b * C::NPIXL + C::PADF + q) * 8) = rec[b];
+        }
+      }
+    } else if constexpr (!C::XDMA) {
 #pragma unroll
       for (int k = 0; k < C::XPF; ++k) {
         const int e = tid + C::NT * k;
@@ -905,9 +1014,20 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     }
   };
 
+  // split nets: byte offset (from a block pixel's record) of record r of
+  // k-step q for this lane's group; padding records re-read the centre tap
+  // (their weights are zero)
+  int ro[C::XSPLIT ? 8 : 1];
+  if constexpr (C::XSPLIT) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int R = 8 * (k >> 1) + 2 * g + (k & 1);
+      ro[k] = R < 27 ? ((R / 9) * C::NPIXL + tap_off(R % 9, C::CWT)) * 8 : 0;
+    }
+  }
   // per-lane x-plane offsets of the layer-1 k-steps (FP32: K = 4q + g)
-  int o1[C::BF16 ? 1 : C::KS1];
-  if constexpr (!C::BF16) {
+  int o1[C::BF16 || C::XSPLIT ? 1 : C::KS1];
+  if constexpr (!C::BF16 && !C::XSPLIT) {
 #pragma unroll
     for (int q = 0; q < C::KS1; ++q) {
       const int K = 4 * q + g;
@@ -982,7 +1102,55 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       for (int i = 0; i < C::NB1; ++i)
 #pragma unroll
         for (int m = 0; m < C::MB; ++m) st1[i][m] *= leak;
-      if constexpr (!C::BF16) {
+      if constexpr (C::XSPLIT) {
+        // bf16 MFMA over the split records: per block, 4 part-h k-steps
+        // accumulate onto leak * v, 3 part-m and 2 part-l k-steps into
+        // temporaries added at the end; the records of block i+1 load and
+        // the epilogue of block i-1 runs while block i multiplies
+        const char* const xr = lds + Lo::XS;
+        const u4* const fr = reinterpret_cast<const u4*>(lds + Lo::FR1) + lane;
+        u4 af[C::NFR1];
+#pragma unroll
+        for (int f = 0; f < C::NFR1; ++f) af[f] = fr[f * 64];
+        u4 bq[2][4];
+        f4 tm[2], tl2[2];
+        auto ldb = [&](int i, int sl) __attribute__((always_inline)) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint2 lo = *reinterpret_cast<const uint2*>(xr + e1[i] * 8 + ro[2 * q]);
+            const uint2 hi = *reinterpret_cast<const uint2*>(xr + e1[i] * 8 + ro[2 * q + 1]);
+            bq[sl][q] = u4{lo.x, lo.y, hi.x, hi.y};
+          }
+        };
+        ldb(0, 0);
+#pragma unroll
+        for (int i = 0; i <= C::NB1; ++i) {
+          if (i < C::NB1) {
+            if (i + 1 < C::NB1) ldb(i + 1, (i + 1) & 1);
+            const u4 (&b)[4] = bq[i & 1];
+            f4& h = st1[i][0];
+            f4& am = tm[i & 1];
+            f4& al = tl2[i & 1];
+            am = f4{0.f, 0.f, 0.f, 0.f};
+            al = f4{0.f, 0.f, 0.f, 0.f};
+            h = mfma_bf16(af[0], b[0], h);
+            am = mfma_bf16(af[4], b[0], am);
+            al = mfma_bf16(af[7], b[0], al);
+            h = mfma_bf16(af[1], b[1], h);
+            am = mfma_bf16(af[5], b[1], am);
+            al = mfma_bf16(af[8], b[1], al);
+            h = mfma_bf16(af[2], b[2], h);
+            am = mfma_bf16(af[6], b[2], am);
+            h = mfma_bf16(af[3], b[3], h);
+          }
+          if (i > 0) {
+            const int k = i - 1;
+            st1[k][0] += tm[k & 1] + tl2[k & 1];
+            hidden_epilogue<C>(st1[k], lds, 0, e1[k], (vm1 >> k) & 1u, g, theta, alpha, relaxed, trace_t, c1, 0,
+                               gy0, gx0, tb);
+          }
+        }
+      } else if constexpr (!C::BF16) {
         // f32 MFMA; the operands of k-step q+1 load while those of q multiply
         const float* xb = reinterpret_cast<const float*>(lds + Lo::XS + (C::XDMA ? (t & 1) * C::XS1 : 0));
         const float* fr1 = reinterpret_cast<const float*>(lds + Lo::FR1) + lane;
@@ -1033,10 +1201,12 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             for (int i = 0; i < C::NB1; ++i) st1[i][m] = mfma_bf16(a[m], bv[i], st1[i][m]);
         }
       }
+      if constexpr (!C::XSPLIT) {
 #pragma unroll
-      for (int i = 0; i < C::NB1; ++i)
-        hidden_epilogue<C>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, c1, 0, gy0,
-                           gx0, tb);
+        for (int i = 0; i < C::NB1; ++i)
+          hidden_epilogue<C>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, c1, 0, gy0,
+                             gx0, tb);
+      }
       lds_barrier();                                   // B1: s1 visible, x buffer (t & 1) free
       if constexpr (C::XDMA) {
         // three-layer nets issue after the layer-2 epilogue: the compiler
@@ -1412,7 +1582,6 @@ const Variant kVariants[] = {
     EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
     EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
     EVS_VARIANT(3, 3, 16, 0, 30, 32, 8, "L3 h16 f32 30x32 w8"),
-    EVS_VARIANT_P(24, 32, "L3 h16 f32 24x32 w8 pipe"),
     EVS_VARIANT(3, 3, 16, 1, 24, 32, 8, "L3 h16 bf16 24x32 w8"),
     EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40 w8"),
     EVS_VARIANT(3, 3, 16, 1, 16, 32, 4, "L3 h16 bf16 16x32 w4"),

@@ -58,8 +58,9 @@ def test_logdiff_matches_oracle(evs, N, T, H, W):
         ref = prologue.logdiff(rgb[n].astype(np.float64))
         err = np.abs(Xd[n] - ref)
         assert np.all(err <= 4e-6 + 1e-6 * np.abs(ref)), float((err - 1e-6 * np.abs(ref)).max())
-    lum = prologue.luminance(rgb.astype(np.float64))
-    assert (lum < 20).any() and (lum >= 20).any()
+    if H * W > 1:
+        lum = prologue.luminance(rgb.astype(np.float64))
+        assert (lum < 20).any() and (lum >= 20).any()
 
 
 def test_logdiff_constant_frames_are_zero(evs):
