@@ -37,10 +37,12 @@ def conv_flops_per_px(channels):
 
 def mfma_peak(channels, prec):
     """Dense matrix-core peak (TFLOP/s) for the conv mix the forward runs:
-    BF16 nets run every conv on the bf16 pipe; FP32 nets run the first conv
-    (FP32 input) on the f32 pipe and every conv that reads spikes on the
-    bf16 pipe with each weight split exactly into three bf16 parts, i.e. at
-    a third of the bf16 rate.  Harmonic mean over the layers' flops."""
+    BF16 nets run every conv on the bf16 pipe.  FP32 nets run every conv
+    that reads spikes on the bf16 pipe with each weight split exactly into
+    three bf16 parts (a third of the bf16 rate); their first conv runs on
+    the bf16 pipe with x and W both split into three parts, six part
+    products kept (a sixth of the bf16 rate) for 3 -> 16 nets, and on the
+    f32 pipe otherwise.  Harmonic mean over the layers' flops."""
     layers = list(zip(channels[:-1], channels[1:]))
     t = fl = 0.0
     for l, (ci, co) in enumerate(layers):
@@ -48,7 +50,8 @@ def mfma_peak(channels, prec):
         if prec == "bf16":
             peak = BF16_MFMA_PEAK
         elif l == 0:
-            peak = FP32_MFMA_PEAK
+            split_l1 = ci == 3 and len(layers) >= 2 and co == 16
+            peak = BF16_MFMA_PEAK / 6 if split_l1 else FP32_MFMA_PEAK
         else:
             peak = BF16_MFMA_PEAK / 3
         t += f / peak
@@ -108,7 +111,7 @@ def traffic_from_profile(kernel_key, launches_px):
         return None
     d = json.load(open(p))
     ent = d.get(kernel_key)
-    if not ent or ent.get("src_hash") != src_hash("evs_forward.hip"):
+    if not ent or ent.get("src_hash") != src_hash("evs_forward.hip", "evs_device.hpp", "evs_internal.hpp"):
         return None
     return ent.get("bytes_per_launch")
 
@@ -409,8 +412,9 @@ def main():
                    "step": "fused forward" + (" + event compaction" if "compact" in forms else "")},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "peak_note": "f32 MFMA for conv 1, bf16 MFMA at 1/3 rate (exact 3-part weight split) "
-                                  "for the spike convs; vs the FP32 dense peak 157.3: "
+                     "peak_note": "all convs on the bf16 pipe with exact FP32 emulation: conv 1 at 1/6 of "
+                                  "the bf16 rate (x and W split into 3 bf16 parts, 6 part products), the spike "
+                                  "convs at 1/3 (3-part weight split); vs the FP32 dense peak 157.3: "
                                   f"{achieved / FP32_MFMA_PEAK:.3f}",
                      "traffic": traffic_from_profile("fwd_L3_h16_f32", px_frames),
                      "kernel": "fwd_kernel<L3 h16 f32>", "kernel_ms": round(fwd_avg, 3),
