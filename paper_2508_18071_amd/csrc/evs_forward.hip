@@ -51,19 +51,17 @@ constexpr int align16(int b) { return (b + 15) & ~15; }
 
 // MODE_: 0 = inference; 1 = training/debug features (h traces, membrane
 // checkpoints, FP32 spike output); 2 = relaxed (smooth) spikes with the
-// features of mode 1; 3 = inference with the wave-specialised schedule
-// (FP32 three-layer 16-channel nets only).  Modes 0 and 3 leave the feature
-// code out of the loop.  MODE_ + 4 (modes 0-2 of one-channel FP32 nets):
-// x holds RGB frames and the input of Eq. (1) is formed while staging.
+// features of mode 1.  Only mode 0 leaves the feature code out of the loop.
+// MODE_ + 4 (one-channel FP32 nets): x holds RGB frames and the input of
+// Eq. (1) is formed while staging.
 template <int NL_, int CIN_, int CH_, bool BF16_, int TH_, int TW_, int NW_, int MODE_>
 struct Cfg {
   static constexpr int NL = NL_, CIN = CIN_, CH = CH_, TH = TH_, TW = TW_, NW = NW_, MODE = MODE_;
   static constexpr int BMODE = MODE_ & 3;
   static constexpr bool LOGX = MODE_ >= 4;
   static constexpr bool BF16 = BF16_, FULL = BMODE == 1 || BMODE == 2, RELAX = BMODE == 2;
-  static_assert(!LOGX || (CIN_ == 1 && !BF16_ && BMODE != 3), "RGB input: one-channel FP32 nets, modes 0-2");
+  static_assert(!LOGX || (CIN_ == 1 && !BF16_), "RGB input: one-channel FP32 nets");
   static_assert(!(BF16_ && MODE_ == 2), "relaxed spikes are FP32 only");
-  static_assert(MODE_ != 3 || (!BF16_ && NL_ == 3 && CH_ == 16 && NW_ == 8), "mode 3: FP32 3-layer h16 w8 only");
   static constexpr int CO = 2;                       // output channels (max)
   static constexpr int NH = NL - 1;                  // hidden layers
   static constexpr int CHT = TH + 2 * NL, CWT = TW + 2 * NL;
@@ -100,7 +98,7 @@ struct Cfg {
   // on the bf16 pipe as well: each staged x value is split into three bf16
   // parts (x = xh + xm + xl exactly) stored as per-pixel records of the three
   // channels, one record plane per part (register staging, no raw x in LDS)
-  static constexpr bool XSPLIT = !BF16 && CIN == 3 && CH == 16 && NH >= 1 && !RELAX && !LOGX && MODE != 3;
+  static constexpr bool XSPLIT = !BF16 && CIN == 3 && CH == 16 && NH >= 1 && !RELAX && !LOGX;
   static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX && !LOGX && !XSPLIT;
   static constexpr int XPP = cdiv(NPIX, NT);         // canvas pixels staged per thread (XSPLIT)
   static constexpr int NFR1 = 9;                     // XSPLIT A fragments: part h 4 k-steps, m 3, l 2
@@ -121,10 +119,6 @@ struct Cfg {
   static constexpr int S2OFF = SEP ? SP1_BYTES : 0;
   static constexpr int SP_BYTES = SP1_BYTES * (SEP ? 2 : 1);
   static constexpr int WL_FLOATS = OMF ? 0 : 9 * (NH >= 1 ? CH : CIN) * CO;
-  // wave-specialised schedule (mode 3): layer-2 blocks over waves 0-3,
-  // layer-1 and output blocks over waves 4-7
-  static constexpr bool PIPE = MODE == 3;
-  static constexpr int NB1V = cdiv(nblk(1), 4), NB2M = cdiv(nblk(2), 4), NBOV = cdiv(nblk(NL), 4);
   static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
   static_assert(NB1 <= 32 && NB2 <= 32 && NBO <= 32 && NOUT <= 32, "mask words overflow");
   static_assert(PADF + JP + CWT + 1 < NPIXL, "junk pixel neighbourhood outside the planes");
@@ -502,321 +496,9 @@ __device__ __forceinline__ void read_hidden_state(f4 (&st)[NB][C::MB], unsigned 
     }
 }
 
-// ---------------------------------------------------------------------------
-// Layer computations shared by the schedules.  Block i of a layer has its
-// pixel at LDS plane index a[i] (front pad included).
-
-// x tile loader of the FP32 nets: direct buffer -> LDS loads, one canvas row
-// of one x plane per load, lane = canvas column.  Every wave issues exactly
-// XPW loads per frame (chunks past the last and rows outside the image read
-// through an empty buffer, columns outside the image use an offset past the
-// end: both return zero), so a frame's loads can be waited for by count
-// while the next frame's are in flight.
-template <class C>
-struct XLoader {
-  const float* xclip;
-  size_t HW;
-  int H, W, gy0, wave;
-  unsigned xv;                                       // byte offset of this lane's column
-  __device__ XLoader(const float* x, size_t hw, int h, int w, int gy, int gx, int wv, int lane)
-      : xclip(x), HW(hw), H(h), W(w), gy0(gy), wave(wv) {
-    xv = (gx + lane >= 0 && gx + lane < w) ? (unsigned)(gx + lane) * 4u : 0x80000000u;
-  }
-  __device__ __forceinline__ void issue(char* lds, int tt, int buf) const {
-    using Lo = Layout<C>;
-    float* const xf = const_cast<float*>(xclip + (size_t)tt * C::CIN * HW);
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(xf, (short)0, (int)(C::CIN * HW * 4), 0x00020000);
-    const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(xf, (short)0, 0, 0x00020000);
-    if ((int)(threadIdx.x & 63) < C::CWT) {
-#pragma unroll
-      for (int k = 0; k < C::XPW; ++k) {
-        const int id = wave + C::NW * k;
-        const int c = id / C::CHT, r = id % C::CHT;
-        const bool real = id < C::XCK;
-        const bool row_in = real && gy0 + r >= 0 && gy0 + r < H;
-        const int dst = real ? Lo::XS + buf * C::XS1 + (C::PADF + id * C::CWT) * 4 : Lo::XDUMMY;
-        const unsigned so = row_in ? (unsigned)(c * (int)HW + (gy0 + r) * W) * 4u : 0u;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(row_in ? rs : rz, (__attribute__((address_space(3))) void*)(lds + dst),
-                                                 4, xv, so, 0, 0);
-      }
-    }
-  }
-  // wait for the loads issued before the most recent XPW (or for all)
-  __device__ __forceinline__ static void wait(bool newer_in_flight) {
-    if (newer_in_flight) __builtin_amdgcn_s_waitcnt(kVmcntEncoded<C::XPW>);
-    else __builtin_amdgcn_s_waitcnt(0);
-  }
-};
-
-// Layer 1 of FP32 nets (f32 MFMA, K = 4q + g over (tap, c)); the operands of
-// k-step q+1 load while those of q multiply.  st holds leak * v on entry.
-template <class C, int NB>
-__device__ __forceinline__ void layer1_f32(f4 (&st)[NB][C::MB], const int (&a)[NB], const int (&o1)[C::KS1],
-                                           const float* xb, const char* lds, int lane) {
-  const float* fr1 = reinterpret_cast<const float*>(lds + Layout<C>::FR1) + lane;
-  float bq[2][NB], aq[2][C::MB];
-  auto ld = [&](int q, int s) __attribute__((always_inline)) {
-#pragma unroll
-    for (int m = 0; m < C::MB; ++m) aq[s][m] = fr1[(q * C::MB + m) * 64];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) bq[s][i] = xb[a[i] + o1[q]];
-  };
-  ld(0, 0);
-#pragma unroll
-  for (int q = 0; q < C::KS1; ++q) {
-    if (q + 1 < C::KS1) ld(q + 1, (q + 1) & 1);
-#pragma unroll
-    for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-      for (int i = 0; i < NB; ++i) st[i][m] = mfma_f32(aq[q & 1][m], bq[q & 1][i], st[i][m]);
-  }
-}
-
-// A hidden -> hidden layer on the bf16 pipe (spikes in bf16 planes, NSP
-// weight parts): the spike fragment of k-step kb is loaded once and
-// multiplied by the parts; k-step kb+1 loads while kb multiplies.
-template <class C, int NB>
-__device__ __forceinline__ void layer2_s16(f4 (&st)[NB][C::MB], const int (&a)[NB], const char* sp, const char* lds,
-                                           int lane, int g) {
-  const u4* fr2 = reinterpret_cast<const u4*>(lds + Layout<C>::FR2) + lane;
-  u4 bq[2][NB], aq[2][C::NSP][C::MB];
-  auto ld = [&](int kb, int s) __attribute__((always_inline)) {
-    int tau, cib;
-    kslot<C::CH>(kb, g, tau, cib);
-    const int o = (cib >> 3) * C::SPL + tap_off(tau > 8 ? 8 : tau, C::CWT) * 16;   // tap 9: zero weights
-#pragma unroll
-    for (int i = 0; i < NB; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sp + a[i] * 16 + o);
-#pragma unroll
-    for (int p = 0; p < C::NSP; ++p)
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m) aq[s][p][m] = fr2[((kb * C::NSP + p) * C::MB + m) * 64];
-  };
-  ld(0, 0);
-#pragma unroll
-  for (int kb = 0; kb < C::KB; ++kb) {
-    if (kb + 1 < C::KB) ld(kb + 1, (kb + 1) & 1);
-#pragma unroll
-    for (int p = 0; p < C::NSP; ++p)
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-        for (int i = 0; i < NB; ++i) st[i][m] = mfma_bf16(aq[kb & 1][p][m], bq[kb & 1][i], st[i][m]);
-  }
-}
-
-// Output layer on the bf16 pipe: rows 4co + p of the accumulator.
-template <class C, int NB>
-__device__ __forceinline__ void outlayer_s16(f4 (&acc)[NB], const int (&a)[NB], const char* sp, const char* lds,
-                                             int lane, int g) {
-  const u4* fr3 = reinterpret_cast<const u4*>(lds + Layout<C>::FR3) + lane;
-  u4 bq[2][NB], aq[2];
-  auto ld = [&](int kb, int s) __attribute__((always_inline)) {
-    int tau, cib;
-    kslot<C::CH>(kb, g, tau, cib);
-    const int o = (cib >> 3) * C::SPL + tap_off(tau > 8 ? 8 : tau, C::CWT) * 16;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sp + a[i] * 16 + o);
-    aq[s] = fr3[kb * 64];
-  };
-  ld(0, 0);
-#pragma unroll
-  for (int kb = 0; kb < C::KB; ++kb) {
-    if (kb + 1 < C::KB) ld(kb + 1, (kb + 1) & 1);
-#pragma unroll
-    for (int i = 0; i < NB; ++i) acc[i] = mfma_bf16(aq[kb & 1], bq[kb & 1][i], acc[i]);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Wave-specialised schedule of the FP32 three-layer inference kernel.
-//
-// Waves 0-3 (one per SIMD) own layer 2 (its state and MFMAs); waves 4-7
-// own layer 1 and the output layer, which runs one frame behind.  Per frame
-// t, with two barriers:
-//   phase A   waves 4-7: layer 1 of frame t (f32 MFMA, fire/reset -> S1)
-//             waves 0-3: fire/reset of layer 2 for frame t-1 (-> S2)
-//   barrier;  next x frame into LDS
-//   phase B   waves 0-3: layer-2 MFMA of frame t (reads S1)
-//             waves 4-7: output layer of frame t-1 (reads S2)
-//   barrier
-// In phase B every SIMD runs one wave's bf16 MFMAs beside the other wave's
-// output-layer MFMAs, LDS reads and VALU work.  Each neuron sees the same
-// arithmetic as in the plain schedule, so the results are bit-identical.
-// ---------------------------------------------------------------------------
-template <class C>
-__device__ __forceinline__ void pipe_layer2_waves(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl,
-                                                  char* lds, int rw, const XLoader<C>& xl) {
-  constexpr int NB = C::NB2M;
-  const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
-  const int H = ca.H, W = ca.W, T = ca.T;
-  const size_t HW = (size_t)H * W;
-  const float theta = na.theta, leak = na.leak, alpha = na.alpha;
-  const int c1 = na.ch[1], c2 = na.ch[2];
-  const int gy0 = tl.ty0 - C::NL, gx0 = tl.tx0 - C::NL;
-  const TraceBox tb{0, 0, 0, 0};
-  int a2[NB];
-  unsigned vm2 = 0;
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    bool ok = false;
-    a2[i] = block_pixel<C>(2, rw + 4 * i, j, gy0, gx0, H, W, ok);
-    vm2 |= (ok ? 1u : 0u) << i;
-  }
-  f4 st[NB][C::MB];
-  const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * ca.vin_nstride : nullptr;
-  read_hidden_state<C, NB>(st, vm2, a2, g, vin, c2, c1, gy0, gx0, W, HW, __builtin_nanf(""));
-  const char* const sp1 = lds + Layout<C>::SP;
-  for (int t = 0; t <= T; ++t) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) asm volatile("" : "+v"(a2[i]));
-    // phase A: fire/reset of frame t-1
-    if (t > 0) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        hidden_epilogue<C>(st[i], lds, C::S2OFF, a2[i], (vm2 >> i) & 1u, g, theta, alpha, false, nullptr, c2, c1,
-                           gy0, gx0, tb);
-    }
-    lds_barrier();
-    if (t + 2 < T) xl.issue(lds, t + 2, t & 1);
-    XLoader<C>::wait(t + 2 < T);
-    // phase B: layer-2 MFMA of frame t
-    if (t < T) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int m = 0; m < C::MB; ++m) st[i][m] *= leak;
-      layer2_s16<C, NB>(st, a2, sp1, lds, lane, g);
-    }
-    lds_barrier();
-  }
-  if (ca.v_out)
-    write_hidden_state<C, NB>(st, vm2, a2, g, ca.v_out + (size_t)tl.n * na.sum_c * HW, c2, c1, gy0, gx0, W, HW);
-}
-
-template <class C>
-__device__ __forceinline__ void pipe_layer13_waves(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl,
-                                                   char* lds, int rw, const XLoader<C>& xl) {
-  constexpr int NB1 = C::NB1V, NBO = C::NBOV, NBH = (NBO + 1) / 2;
-  const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
-  const int H = ca.H, W = ca.W, T = ca.T;
-  const size_t HW = (size_t)H * W;
-  const float theta = na.theta, leak = na.leak, alpha = na.alpha;
-  const int c1 = na.ch[1], c2 = na.ch[2], cout = na.ch[3];
-  const int choffo = c1 + c2;
-  const int gy0 = tl.ty0 - C::NL, gx0 = tl.tx0 - C::NL;
-  const TraceBox tb{0, 0, 0, 0};
-  int a1[NB1], ao[NBO], oo[NBO];
-  unsigned vm1 = 0;
-#pragma unroll
-  for (int i = 0; i < NB1; ++i) {
-    bool ok = false;
-    a1[i] = block_pixel<C>(1, rw + 4 * i, j, gy0, gx0, H, W, ok);
-    vm1 |= (ok ? 1u : 0u) << i;
-  }
-#pragma unroll
-  for (int i = 0; i < NBO; ++i) {
-    bool ok = false;
-    ao[i] = block_pixel<C>(C::NL, rw + 4 * i, j, gy0, gx0, H, W, ok);
-    const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
-    oo[i] = (ok && g < cout) ? g * (int)HW + (gy0 + row) * W + (gx0 + col) : -1;
-  }
-  int o1[C::KS1];
-#pragma unroll
-  for (int q = 0; q < C::KS1; ++q) {
-    const int K = 4 * q + g;
-    const int tap = K / C::CIN, c = K - tap * C::CIN;
-    o1[q] = K < C::K1 ? c * C::XPL + tap_off(tap, C::CWT) : C::CIN * C::XPL;
-  }
-  f4 st[NB1][C::MB];
-  float vo[NBO];
-  const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * ca.vin_nstride : nullptr;
-  read_hidden_state<C, NB1>(st, vm1, a1, g, vin, c1, 0, gy0, gx0, W, HW, __builtin_nanf(""));
-#pragma unroll
-  for (int i = 0; i < NBO; ++i) vo[i] = (vin && oo[i] >= 0) ? vin[(size_t)choffo * HW + oo[i]] : 0.f;
-  const char* const sp2 = lds + Layout<C>::SP + C::S2OFF;
-  for (int t = 0; t <= T; ++t) {
-#pragma unroll
-    for (int i = 0; i < NB1; ++i) asm volatile("" : "+v"(a1[i]));
-#pragma unroll
-    for (int i = 0; i < NBO; ++i) asm volatile("" : "+v"(ao[i]));
-    // phase A: layer 1 of frame t
-    if (t < T) {
-#pragma unroll
-      for (int i = 0; i < NB1; ++i)
-#pragma unroll
-        for (int m = 0; m < C::MB; ++m) st[i][m] *= leak;
-      layer1_f32<C, NB1>(st, a1, o1, reinterpret_cast<const float*>(lds + Layout<C>::XS + (t & 1) * C::XS1), lds,
-                         lane);
-#pragma unroll
-      for (int i = 0; i < NB1; ++i)
-        hidden_epilogue<C>(st[i], lds, 0, a1[i], (vm1 >> i) & 1u, g, theta, alpha, false, nullptr, c1, 0, gy0, gx0,
-                           tb);
-    }
-    lds_barrier();
-    if (t + 2 < T) xl.issue(lds, t + 2, t & 1);
-    XLoader<C>::wait(t + 2 < T);
-    // phase B: output layer of frame t-1, in two halves of the blocks
-    if (t > 0) {
-      int8_t* const s8 = reinterpret_cast<int8_t*>(ca.s_out) + ((size_t)tl.n * T + (t - 1)) * cout * HW;
-#pragma unroll
-      for (int hf = 0; hf < 2; ++hf) {
-        int ah[NBH];
-        f4 acc[NBH];
-#pragma unroll
-        for (int k = 0; k < NBH; ++k) {
-          const int i = hf * NBH + k < NBO ? hf * NBH + k : NBO - 1;
-          ah[k] = ao[i];
-          acc[k] = f4{leak * vo[i], 0.f, 0.f, 0.f};
-        }
-        outlayer_s16<C, NBH>(acc, ah, sp2, lds, lane, g);
-        if (g < 2) {
-#pragma unroll
-          for (int k = 0; k < NBH; ++k) {
-            const int i = hf * NBH + k;
-            if (i < NBO) {
-              float v = (acc[k][0] + acc[k][1]) + acc[k][2];
-              const float sp = bilif(v, theta, alpha, false);
-              asm volatile("" : "+v"(v));
-              vo[i] = v;
-              if (oo[i] >= 0 && ca.s_out) s8[oo[i]] = (int8_t)sp;
-            }
-          }
-        }
-      }
-    }
-    lds_barrier();
-  }
-  if (ca.v_out) {
-    float* dst = ca.v_out + (size_t)tl.n * na.sum_c * HW;
-    write_hidden_state<C, NB1>(st, vm1, a1, g, dst, c1, 0, gy0, gx0, W, HW);
-#pragma unroll
-    for (int i = 0; i < NBO; ++i)
-      if (oo[i] >= 0) dst[(size_t)choffo * HW + oo[i]] = vo[i];
-  }
-}
-
-template <class C>
-__device__ __forceinline__ void run_tile_pipe(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl, char* lds) {
-  static_assert(C::PIPE, "specialised schedule: FP32 3-layer 16-channel inference kernel");
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const XLoader<C> xl(ca.x + (size_t)tl.n * ca.x_nstride, (size_t)ca.H * ca.W, ca.H, ca.W, tl.ty0 - C::NL,
-                      tl.tx0 - C::NL, wave, threadIdx.x & 63);
-  xl.issue(lds, 0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (ca.T > 1) xl.issue(lds, 1, 1);
-  if (wave < 4) pipe_layer2_waves<C>(na, ca, tl, lds, wave, xl);
-  else pipe_layer13_waves<C>(na, ca, tl, lds, wave - 4, xl);
-  __builtin_amdgcn_s_waitcnt(0);
-}
-
 // Process one tile over frames [0, T) of one clip.
 template <class C>
 __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs& ca, const Tile tl, char* lds) {
-  if constexpr (C::PIPE) {
-    run_tile_pipe<C>(na, ca, tl, lds);
-    return;
-  }
   using Lo = Layout<C>;
   uint16_t* const xsb = reinterpret_cast<uint16_t*>(lds + Lo::XS);
   float* const xsf = reinterpret_cast<float*>(lds + Lo::XS);
@@ -1548,10 +1230,6 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
           {&launch_single<EVS_CFG(NL, 1, CH, 0, TH, TW, NW, 4)>,                                \
            &launch_single<EVS_CFG(NL, 1, CH, 0, TH, TW, NW, 5)>,                                \
            &launch_single<EVS_CFG(NL, 1, CH, 0, TH, TW, NW, 6)>}}
-// the wave-specialised schedule as the inference kernel of a tile
-#define EVS_VARIANT_P(TH, TW, NAME)                                                              \
-  Variant{3, 3, 16, 0, TH, TW, NAME, &launch_single<EVS_CFG(3, 3, 16, 0, TH, TW, 8, 3)>,          \
-          &launch_single<EVS_CFG(3, 3, 16, 0, TH, TW, 8, 1)>, nullptr, nullptr}
 #define EVS_VARIANT_RB(NL, CIN, CH, TH, TW, NW, NAME)                                \
   Variant{NL, CIN, CH, 0, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, 0, TH, TW, NW),   \
           &launch_single<EVS_CFG(NL, CIN, CH, 0, TH, TW, NW, 2)>,                    \
