@@ -71,7 +71,10 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
  *   leak       beta = 1 - 1/tau in [0, 1]
  *   surr_alpha slope alpha of the surrogate step sigma (see `surrogate`)
  *              used by evs_backward and by relaxed forwards (Eq. 4)
- *   precision  EVS_FP32: convolutions in FP32 (MFMA f32);
+ *   precision  EVS_FP32: FP32 convolutions: sums accumulate in FP32 and
+ *              every product is carried to within 2^-22 of its value
+ *              (operands split into bf16 or fp16 parts on the matrix cores,
+ *              or f32 MFMA), i.e. below the rounding of the FP32 sum;
  *              EVS_BF16: x and W rounded to bfloat16 (round-to-nearest-even)
  *              and multiplied on BF16 MFMA with FP32 accumulation.
  *              Membrane state, threshold compare and reset are FP32 in both.

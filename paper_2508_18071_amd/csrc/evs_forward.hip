@@ -77,7 +77,10 @@ struct Cfg {
   static constexpr int NB1 = NH >= 1 ? cdiv(nblk(1), NW) : 1;
   static constexpr int NB2 = NH >= 2 ? cdiv(nblk(2), NW) : 1;
   static constexpr bool S16 = !RELAX;                // hidden spikes stored as bf16
-  static constexpr int NSP = BF16 ? 1 : 3;           // bf16 parts of a weight
+  // FP32 nets: spikes and the weights of the convs that read them in fp16,
+  // each weight (scaled by a power of two per layer) as two fp16 parts
+  static constexpr bool SF16 = !BF16 && !RELAX;
+  static constexpr int NSP = BF16 ? 1 : 2;           // parts of a spike-conv weight
   static constexpr bool OMF = S16 && NH >= 1;        // output layer on MFMA
   static constexpr int KB = CH == 32 ? 9 : 5;        // spike-operand k-steps (32 of K = 9*CH each)
   static constexpr int NBO = OMF ? cdiv(nblk(NL), NW) : 1;
@@ -101,6 +104,9 @@ struct Cfg {
   static constexpr bool XSPLIT = !BF16 && CIN == 3 && CH == 16 && NH >= 1 && !RELAX && !LOGX;
   static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX && !LOGX && !XSPLIT;
   static constexpr int XPP = cdiv(NPIX, NT);         // canvas pixels staged per thread (XSPLIT)
+  // 16-channel spike convs run block by block with all weight fragments in
+  // registers, so that block i-1's epilogue overlaps block i's MFMAs
+  static constexpr bool BO = CH == 16 && S16;
   static constexpr int NFR1 = 9;                     // XSPLIT A fragments: part h 4 k-steps, m 3, l 2
   static constexpr int XCK = CIN * CHT;              // x chunks: one canvas row of one plane
   static constexpr int XPW = cdiv(XCK, NW);          // chunk loads per wave and frame
@@ -128,9 +134,26 @@ struct Cfg {
 __device__ inline f4 mfma_f32(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+__device__ inline f4 mfma_f16(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+}
 __device__ inline f4 mfma_bf16(u4 a, u4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
                                                  __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+// MFMA of a conv that reads spikes: fp16 operands for FP32 nets, bf16 for
+// BF16 nets
+template <class C>
+__device__ inline f4 mfma_sp(u4 a, u4 b, f4 c) {
+  if constexpr (C::SF16) return mfma_f16(a, b, c);
+  else return mfma_bf16(a, b, c);
+}
+
+// Two fp16 values (exact in fp16) packed low, high.
+__device__ inline unsigned pack_f16x2(float lo, float hi) {
+  return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(lo, hi));
 }
 
 // s_waitcnt operand that waits until at most N vector memory operations of
@@ -203,6 +226,23 @@ __device__ __forceinline__ void split_frag(int f, int& p, int& q) {
   q = f < 4 ? f : (f < 7 ? f - 4 : f - 7);
 }
 
+// Power-of-two exponent s that brings the largest weight magnitude of a
+// layer (bits of |w|max) into [2^14, 2^15): the scaled weights use the fp16
+// range without overflow and their low parts stay normal.
+__device__ inline int scale_exp(unsigned maxbits) {
+  if (maxbits == 0u) return 0;
+  const int s = 141 - (int)((maxbits >> 23) & 0xffu);
+  return s < -100 ? -100 : (s > 100 ? 100 : s);
+}
+
+// Part p of the split w sc = h + l into fp16 values (h = fp16(w sc),
+// l = fp16(w sc - h), round to nearest; |w sc - h - l| <= 2^-22 |w sc|).
+__device__ inline float wpart16(float w, float sc, int p) {
+  const float ws = w * sc;
+  const float h = (float)(_Float16)ws;
+  return p == 0 ? h : (float)(_Float16)(ws - h);
+}
+
 // The bf16 value a spike-operand MFMA multiplies: part p of the FP32 weight,
 // or the bf16-rounded weight of a BF16 net (p = 0).
 __device__ inline float wbf(const FwdNetArgs& na, int layer, int co, int ci, int tap, bool bf, int p) {
@@ -235,16 +275,42 @@ struct Layout {
   static constexpr int FR3 = FR2 + FR2_BYTES;                   // output-layer A fragments
   static constexpr int FR3_BYTES = C::OMF ? C::KB * 64 * 16 : 0;
   static constexpr int XDUMMY = FR3 + FR3_BYTES;                // target of the padding x loads
-  static constexpr int TOTAL = XDUMMY + (C::XDMA ? 256 : 0);
+  static constexpr int SCL = XDUMMY + (C::XDMA ? 256 : 0);      // |w|max bits of the spike convs (u32 x 2)
+  static constexpr int TOTAL = SCL + 16;
   static_assert(TOTAL <= 160 * 1024, "tile does not fit in LDS");
 };
 
 // Fill the weight areas of LDS with the MFMA A-operand fragments in the
 // per-lane order the k-step loops read them (and the VALU output weights).
+// Scale 2^s of the spike-conv weights of FP32 nets: slot 0 the hidden ->
+// hidden conv, slot 1 the output conv (1 for other nets).
+template <class C>
+__device__ __forceinline__ float spike_scale(const char* lds, int slot) {
+  if constexpr (C::SF16) return __builtin_ldexpf(1.f, scale_exp(reinterpret_cast<const unsigned*>(lds + Layout<C>::SCL)[slot]));
+  else return 1.f;
+}
+
 template <class C>
 __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
   using Lo = Layout<C>;
   const int L = na.n_layers - 1;
+  if constexpr (C::SF16) {
+    // largest |w| of each conv that reads spikes (|w| bits order like |w|)
+    unsigned* scl = reinterpret_cast<unsigned*>(lds + Lo::SCL);
+    if (threadIdx.x < 4) scl[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int l = 1; l <= L; ++l) {
+      if (l < L && C::NH < 2) continue;
+      const int n = na.ch[l + 1] * na.ch[l] * 9;
+      unsigned m = 0u;
+      for (int e = threadIdx.x; e < n; e += C::NT) {
+        const unsigned b = __builtin_bit_cast(unsigned, na.w[na.wofs[l] + e]) & 0x7fffffffu;
+        m = b > m ? b : m;
+      }
+      atomicMax(scl + (l == L ? 1 : 0), m);
+    }
+    __syncthreads();
+  }
   if constexpr (!C::OMF) {
     float* wl = reinterpret_cast<float*>(lds + Lo::WL);
     const int cin = na.ch[L], cout = na.ch[L + 1];
@@ -302,6 +368,7 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
   }
   if constexpr (C::NH >= 2) {
     const int c1 = na.ch[1], c2 = na.ch[2];
+    const float sc = spike_scale<C>(lds, 0);
     if constexpr (C::S16) {
       // entry ((kb, p, m), lane): part p of the k-step kb fragment, rows co = 16m + lane%16
       for (int e = threadIdx.x; e < C::KB * C::NSP * C::MB * 64; e += C::NT) {
@@ -315,9 +382,11 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
           float ww[2];
           for (int h = 0; h < 2; ++h) {
             const int ci = cib + 2 * e2 + h;
-            ww[h] = (tau < 9 && co < c2 && ci < c1) ? wbf(na, 1, co, ci, tau, C::BF16, p) : 0.f;
+            const bool real = tau < 9 && co < c2 && ci < c1;
+            if constexpr (C::SF16) ww[h] = real ? wpart16(wget(na, 1, co, ci, tau), sc, p) : 0.f;
+            else ww[h] = real ? wbf(na, 1, co, ci, tau, C::BF16, p) : 0.f;
           }
-          wd[e2] = pack_bf16x2(ww[0], ww[1]);
+          wd[e2] = C::SF16 ? pack_f16x2(ww[0], ww[1]) : pack_bf16x2(ww[0], ww[1]);
         }
         reinterpret_cast<u4*>(lds + Lo::FR2)[e] = u4{wd[0], wd[1], wd[2], wd[3]};
       }
@@ -335,6 +404,7 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
   if constexpr (C::OMF) {
     // output layer: row i = 4 co + p holds part p of output channel co
     const int cin = na.ch[L], cout = na.ch[L + 1];
+    const float sc = spike_scale<C>(lds, 1);
     for (int e = threadIdx.x; e < C::KB * 64; e += C::NT) {
       const int lane = e % 64, kb = e / 64;
       const int i = lane & 15, g = lane >> 4;
@@ -346,9 +416,11 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
         float ww[2];
         for (int h = 0; h < 2; ++h) {
           const int ci = cib + 2 * e2 + h;
-          ww[h] = (tau < 9 && co < cout && p < C::NSP && ci < cin) ? wbf(na, L, co, ci, tau, C::BF16, p) : 0.f;
+          const bool real = tau < 9 && co < cout && p < C::NSP && ci < cin;
+          if constexpr (C::SF16) ww[h] = real ? wpart16(wget(na, L, co, ci, tau), sc, p) : 0.f;
+          else ww[h] = real ? wbf(na, L, co, ci, tau, C::BF16, p) : 0.f;
         }
-        wd[e2] = pack_bf16x2(ww[0], ww[1]);
+        wd[e2] = C::SF16 ? pack_f16x2(ww[0], ww[1]) : pack_bf16x2(ww[0], ww[1]);
       }
       reinterpret_cast<u4*>(lds + Lo::FR3)[e] = u4{wd[0], wd[1], wd[2], wd[3]};
     }
@@ -399,7 +471,7 @@ __device__ __forceinline__ int block_pixel(int l, int b, int j, int gy0, int gx0
 // write spikes to LDS and, optionally, h to the trace.
 template <class C>
 __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int sp_off, int p, bool valid, int g,
-                                                float theta, float alpha, int relaxed, float* trace_t,
+                                                float theta, float alpha, int relaxed, float* trace_t, float tscale,
                                                 int cl, int choff, int gy0, int gx0, const TraceBox& tb) {
   if (C::FULL && trace_t && valid) {
     const int row = (p - C::PADF) / C::CWT, col = (p - C::PADF) % C::CWT;
@@ -411,7 +483,7 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int co = 16 * m + 4 * g + r;
-          if (co < cl) trace_t[(size_t)(choff + co) * tb.plane() + pix] = st[m][r];
+          if (co < cl) trace_t[(size_t)(choff + co) * tb.plane() + pix] = st[m][r] * tscale;
         }
     }
   }
@@ -431,7 +503,8 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
       if (!valid) s = f4{0.f, 0.f, 0.f, 0.f};
     }
     if constexpr (C::S16) {
-      uint2 w2 = {pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
+      const uint2 w2 = C::SF16 ? uint2{pack_f16x2(s[0], s[1]), pack_f16x2(s[2], s[3])}
+                               : uint2{pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
       // channels 16m + 4g .. +3: plane 2m + g/2, half (g & 1) of the pixel's 16 bytes
       *reinterpret_cast<uint2*>(lds + Layout<C>::SP + sp_off + (2 * m + (g >> 1)) * C::SPL + p * 16 + 8 * (g & 1)) = w2;
     } else {
@@ -452,7 +525,7 @@ __device__ __forceinline__ bool interior(int p, int& row, int& col) {
 template <class C, int NB>
 __device__ __forceinline__ void write_hidden_state(const f4 (&st)[NB][C::MB], unsigned vm, const int (&ad)[NB],
                                                    int g, float* dst, int cl, int choff, int gy0, int gx0, int W,
-                                                   size_t HW) {
+                                                   size_t HW, float scale) {
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     int row, col;
@@ -463,18 +536,18 @@ __device__ __forceinline__ void write_hidden_state(const f4 (&st)[NB][C::MB], un
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int co = 16 * m + 4 * g + r;
-          if (co < cl) dst[(size_t)(choff + co) * HW + pix] = st[i][m][r];
+          if (co < cl) dst[(size_t)(choff + co) * HW + pix] = st[i][m][r] * scale;
         }
     }
   }
 }
 
-// Initial membrane state of a hidden layer: v_in (or 0) for real neurons,
-// `fill` for the others.
+// Initial membrane state of a hidden layer: v_in (or 0) times `scale` for
+// real neurons, `fill` for the others.
 template <class C, int NB>
 __device__ __forceinline__ void read_hidden_state(f4 (&st)[NB][C::MB], unsigned vm, const int (&ad)[NB], int g,
                                                   const float* src, int cl, int choff, int gy0, int gx0, int W,
-                                                  size_t HW, float fill) {
+                                                  size_t HW, float fill, float scale) {
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
@@ -488,7 +561,7 @@ __device__ __forceinline__ void read_hidden_state(f4 (&st)[NB][C::MB], unsigned 
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int co = 16 * m + 4 * g + r;
-            if (co < cl) v[r] = src[(size_t)(choff + co) * HW + pix];
+            if (co < cl) v[r] = src[(size_t)(choff + co) * HW + pix] * scale;
           }
         }
       }
@@ -514,6 +587,12 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   const size_t HW = (size_t)H * W;
   const int sumc = na.sum_c;
   const float theta = na.theta, leak = na.leak, alpha = na.alpha;
+  // FP32 nets keep the state of the layers behind a spike conv in units of
+  // that conv's weight scale 2^s (exact): their threshold is theta 2^s, and
+  // traces, checkpoints and the final state are written unscaled
+  const float sc2 = spike_scale<C>(lds, 0), sc3 = spike_scale<C>(lds, 1);
+  const float isc2 = 1.f / sc2, isc3 = 1.f / sc3;
+  const float theta2 = theta * sc2, theta3 = theta * sc3;
   const int relaxed = na.relaxed;                   // 0 hard, 1 sigmoid, 2 arctangent step
   const int c1 = na.ch[1], c2 = na.ch[2];
   const int cout = na.ch[na.n_layers];
@@ -566,12 +645,13 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   float vo[C::NBO];         // output potential (MFMA form)
   const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * ca.vin_nstride : nullptr;
   const float fill = C::RELAX ? 0.f : __builtin_nanf("");
-  if constexpr (C::NH >= 1) read_hidden_state<C, C::NB1>(st1, vm1, a1, g, vin, c1, 0, gy0, gx0, W, HW, fill);
-  if constexpr (C::NH >= 2) read_hidden_state<C, C::NB2>(st2, vm2, a2, g, vin, c2, choff2, gy0, gx0, W, HW, fill);
+  if constexpr (C::NH >= 1) read_hidden_state<C, C::NB1>(st1, vm1, a1, g, vin, c1, 0, gy0, gx0, W, HW, fill, 1.f);
+  if constexpr (C::NH >= 2)
+    read_hidden_state<C, C::NB2>(st2, vm2, a2, g, vin, c2, choff2, gy0, gx0, W, HW, fill, sc2);
 #pragma unroll
   for (int i = 0; i < C::NBO; ++i) {
     vo[i] = 0.f;
-    if (C::OMF && vin && oo[i] >= 0) vo[i] = vin[(size_t)choffo * HW + oo[i]];
+    if (C::OMF && vin && oo[i] >= 0) vo[i] = vin[(size_t)choffo * HW + oo[i]] * sc3;
   }
 #pragma unroll
   for (int k = 0; k < C::NOUT; ++k) {
@@ -664,19 +744,27 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     }
   };
   auto load_x = [&](int tt) __attribute__((always_inline)) { fetch_x(C::LOGX ? tt + 1 : tt); };
+  // split nets: records of staged pixel group k (pixels tid + NT k)
+  auto store_group = [&](int k) __attribute__((always_inline)) {
+    if constexpr (C::XSPLIT) {
+      const int q = tid + C::NT * k;
+      if (q < C::NPIX) {
+        uint2 rec[3];
+        split3_records(xpf[3 * k], xpf[3 * k + 1], xpf[3 * k + 2], rec);
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          *reinterpret_cast<uint2*>(lds + Lo::XS + (b * C::NPIXL + C::PADF + q) * 8) = rec[b];
+      }
+    }
+  };
+  // three-layer split nets store the next frame's records inside the
+  // layer-2 block loop (group k after block k's MFMAs are issued), the
+  // others right after the layer-1 barrier
+  constexpr bool STAGE_IN_L2 = C::XSPLIT && C::NH == 2 && C::BO;
   auto store_x = [&]() __attribute__((always_inline)) {
     if constexpr (C::XSPLIT) {
 #pragma unroll
-      for (int k = 0; k < C::XPP; ++k) {
-        const int q = tid + C::NT * k;
-        if (q < C::NPIX) {
-          uint2 rec[3];
-          split3_records(xpf[3 * k], xpf[3 * k + 1], xpf[3 * k + 2], rec);
-#pragma unroll
-          for (int b = 0; b < 3; ++b)
-            *reinterpret_cast<uint2*>(lds + Lo::XS + (b * C::NPIXL + C::PADF + q) * 8) = rec[b];
-        }
-      }
+      for (int k = 0; k < C::XPP; ++k) store_group(k);
     } else if constexpr (!C::XDMA) {
 #pragma unroll
       for (int k = 0; k < C::XPF; ++k) {
@@ -721,8 +809,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   const int nseg = ca.ckpt_every > 0 ? cdiv(T, ca.ckpt_every) : 0;
   const TraceBox tb{ca.tb_y0, ca.tb_x0, ca.tb_h, ca.tb_w};
   auto write_state = [&](float* dst) __attribute__((always_inline)) {
-    if constexpr (C::NH >= 1) write_hidden_state<C, C::NB1>(st1, vm1, a1, g, dst, c1, 0, gy0, gx0, W, HW);
-    if constexpr (C::NH >= 2) write_hidden_state<C, C::NB2>(st2, vm2, a2, g, dst, c2, choff2, gy0, gx0, W, HW);
+    if constexpr (C::NH >= 1) write_hidden_state<C, C::NB1>(st1, vm1, a1, g, dst, c1, 0, gy0, gx0, W, HW, 1.f);
+    if constexpr (C::NH >= 2) write_hidden_state<C, C::NB2>(st2, vm2, a2, g, dst, c2, choff2, gy0, gx0, W, HW, isc2);
 #pragma unroll
     for (int k = 0; k < C::NOUT; ++k) {
       if (!C::OMF && ((ovm >> k) & 1u)) {
@@ -735,7 +823,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     }
 #pragma unroll
     for (int i = 0; i < C::NBO; ++i)
-      if (C::OMF && oo[i] >= 0) dst[(size_t)choffo * HW + oo[i]] = vo[i];
+      if (C::OMF && oo[i] >= 0) dst[(size_t)choffo * HW + oo[i]] = vo[i] * isc3;
   };
 
   // ---- prologue: frame 0 into LDS, frame 1 in flight (DMA) or in registers
@@ -785,17 +873,17 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
         for (int m = 0; m < C::MB; ++m) st1[i][m] *= leak;
       if constexpr (C::XSPLIT) {
-        // bf16 MFMA over the split records: per block, 4 part-h k-steps
-        // accumulate onto leak * v, 3 part-m and 2 part-l k-steps into
-        // temporaries added at the end; the records of block i+1 load and
-        // the epilogue of block i-1 runs while block i multiplies
+        // bf16 MFMA over the split records: per block, the 9 fragment
+        // products (parts h, m, l interleaved per k-step) accumulate onto
+        // leak * v in one chain (dependent MFMAs issue back to back); the
+        // records of block i+1 load and the epilogue of block i-1 runs
+        // while block i multiplies
         const char* const xr = lds + Lo::XS;
         const u4* const fr = reinterpret_cast<const u4*>(lds + Lo::FR1) + lane;
         u4 af[C::NFR1];
 #pragma unroll
         for (int f = 0; f < C::NFR1; ++f) af[f] = fr[f * 64];
         u4 bq[2][4];
-        f4 tm[2], tl2[2];
         auto ldb = [&](int i, int sl) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -811,26 +899,19 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             if (i + 1 < C::NB1) ldb(i + 1, (i + 1) & 1);
             const u4 (&b)[4] = bq[i & 1];
             f4& h = st1[i][0];
-            f4& am = tm[i & 1];
-            f4& al = tl2[i & 1];
-            am = f4{0.f, 0.f, 0.f, 0.f};
-            al = f4{0.f, 0.f, 0.f, 0.f};
             h = mfma_bf16(af[0], b[0], h);
-            am = mfma_bf16(af[4], b[0], am);
-            al = mfma_bf16(af[7], b[0], al);
+            h = mfma_bf16(af[4], b[0], h);
+            h = mfma_bf16(af[7], b[0], h);
             h = mfma_bf16(af[1], b[1], h);
-            am = mfma_bf16(af[5], b[1], am);
-            al = mfma_bf16(af[8], b[1], al);
+            h = mfma_bf16(af[5], b[1], h);
+            h = mfma_bf16(af[8], b[1], h);
             h = mfma_bf16(af[2], b[2], h);
-            am = mfma_bf16(af[6], b[2], am);
+            h = mfma_bf16(af[6], b[2], h);
             h = mfma_bf16(af[3], b[3], h);
           }
-          if (i > 0) {
-            const int k = i - 1;
-            st1[k][0] += tm[k & 1] + tl2[k & 1];
-            hidden_epilogue<C>(st1[k], lds, 0, e1[k], (vm1 >> k) & 1u, g, theta, alpha, relaxed, trace_t, c1, 0,
-                               gy0, gx0, tb);
-          }
+          if (i > 0)
+            hidden_epilogue<C>(st1[i - 1], lds, 0, e1[i - 1], (vm1 >> (i - 1)) & 1u, g, theta, alpha, relaxed, trace_t,
+                               1.f, c1, 0, gy0, gx0, tb);
         }
       } else if constexpr (!C::BF16) {
         // f32 MFMA; the operands of k-step q+1 load while those of q multiply
@@ -886,8 +967,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       if constexpr (!C::XSPLIT) {
 #pragma unroll
         for (int i = 0; i < C::NB1; ++i)
-          hidden_epilogue<C>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, c1, 0, gy0,
-                             gx0, tb);
+          hidden_epilogue<C>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, 1.f, c1, 0,
+                             gy0, gx0, tb);
       }
       lds_barrier();                                   // B1: s1 visible, x buffer (t & 1) free
       if constexpr (C::XDMA) {
@@ -895,7 +976,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         // orders every LDS store after LDS DMA still in flight, and the
         // output layer + next layer-1 MFMAs are the longest store-free stretch
         if (C::NH == 1 && t + 2 < T) issue_x(t + 2, t & 1);
-      } else {
+      } else if constexpr (!STAGE_IN_L2) {
         if (t + 1 < T) store_x();
         if (t + 2 < T) load_x(t + 2);
       }
@@ -907,7 +988,49 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       for (int i = 0; i < C::NB2; ++i)
 #pragma unroll
         for (int m = 0; m < C::MB; ++m) st2[i][m] *= leak;
-      if constexpr (C::S16) {
+      if constexpr (C::BO) {
+        // block by block: the fragments of all k-steps and parts stay in
+        // registers; block i+1's spikes load and block i-1's epilogue runs
+        // while block i multiplies (per block the MFMA order is the same as
+        // k-step by k-step: kb outer, part inner)
+        const u4* fr2 = reinterpret_cast<const u4*>(lds + Lo::FR2) + lane;
+        u4 aw[C::KB][C::NSP];
+#pragma unroll
+        for (int kb = 0; kb < C::KB; ++kb)
+#pragma unroll
+          for (int p = 0; p < C::NSP; ++p) aw[kb][p] = fr2[(kb * C::NSP + p) * 64];
+        u4 bq[2][C::KB];
+        auto ldb2 = [&](int i, int sl) __attribute__((always_inline)) {
+#pragma unroll
+          for (int kb = 0; kb < C::KB; ++kb) {
+            int tau, cib;
+            kslot<C::CH>(kb, g, tau, cib);
+            const int o = (cib >> 3) * C::SPL + tap_off(tau > 8 ? 8 : tau, C::CWT) * 16;   // tap 9: zero weights
+            bq[sl][kb] = *reinterpret_cast<const u4*>(sp1 + e2[i] * 16 + o);
+          }
+        };
+        ldb2(0, 0);
+#pragma unroll
+        for (int i = 0; i <= C::NB2; ++i) {
+          if (i < C::NB2) {
+            if (i + 1 < C::NB2) ldb2(i + 1, (i + 1) & 1);
+#pragma unroll
+            for (int kb = 0; kb < C::KB; ++kb)
+#pragma unroll
+              for (int p = 0; p < C::NSP; ++p) st2[i][0] = mfma_sp<C>(aw[kb][p], bq[i & 1][kb], st2[i][0]);
+          }
+          if (STAGE_IN_L2 && i < C::XPP && t + 1 < T) store_group(i);
+          if (i > 0)
+            hidden_epilogue<C>(st2[i - 1], lds, C::S2OFF, e2[i - 1], (vm2 >> (i - 1)) & 1u, g, theta2, alpha, relaxed,
+                               trace_t, isc2, c2, choff2, gy0, gx0, tb);
+        }
+        if constexpr (STAGE_IN_L2) {
+#pragma unroll
+          for (int k = C::NB2 + 1; k < C::XPP; ++k)
+            if (t + 1 < T) store_group(k);
+          if (t + 2 < T) load_x(t + 2);
+        }
+      } else if constexpr (C::S16) {
         // the spike fragment of k-step kb is loaded once and multiplied by
         // the NSP weight parts; k-step kb+1 loads while kb multiplies
         const u4* fr2 = reinterpret_cast<const u4*>(lds + Lo::FR2) + lane;
@@ -932,7 +1055,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
             for (int m = 0; m < C::MB; ++m)
 #pragma unroll
-              for (int i = 0; i < C::NB2; ++i) st2[i][m] = mfma_bf16(aq[kb & 1][p][m], bq[kb & 1][i], st2[i][m]);
+              for (int i = 0; i < C::NB2; ++i) st2[i][m] = mfma_sp<C>(aq[kb & 1][p][m], bq[kb & 1][i], st2[i][m]);
         }
       } else {
         const float* spf = reinterpret_cast<const float*>(sp1);
@@ -960,10 +1083,12 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         }
       }
       if constexpr (!C::SEP) lds_barrier();            // B2: all reads of s1 done
+      if constexpr (!C::BO) {
 #pragma unroll
-      for (int i = 0; i < C::NB2; ++i)
-        hidden_epilogue<C>(st2[i], lds, C::S2OFF, e2[i], (vm2 >> i) & 1u, g, theta, alpha, relaxed, trace_t, c2,
-                           choff2, gy0, gx0, tb);
+        for (int i = 0; i < C::NB2; ++i)
+          hidden_epilogue<C>(st2[i], lds, C::S2OFF, e2[i], (vm2 >> i) & 1u, g, theta2, alpha, relaxed, trace_t, isc2,
+                             c2, choff2, gy0, gx0, tb);
+      }
       if constexpr (C::XDMA) {
         if (t + 2 < T) issue_x(t + 2, t & 1);
         // x(t+1) was issued one frame ago: wait for it, not for x(t+2)
@@ -980,39 +1105,20 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       // ================= output layer on MFMA: rows 4co + p, K = tap * CH + ci
       const char* const sob = C::NH == 2 ? sp2 : sp1;
       const u4* fr3 = reinterpret_cast<const u4*>(lds + Lo::FR3) + lane;
-      f4 acc[C::NBO];
-#pragma unroll
-      for (int i = 0; i < C::NBO; ++i) acc[i] = f4{leak * vo[i], 0.f, 0.f, 0.f};
-      u4 bq[2][C::NBO], aq[2];
-      auto ld3 = [&](int kb, int s) __attribute__((always_inline)) {
-        int tau, cib;
-        kslot<C::CH>(kb, g, tau, cib);
-        const int o = (cib >> 3) * C::SPL + tap_off(tau > 8 ? 8 : tau, C::CWT) * 16;
-#pragma unroll
-        for (int i = 0; i < C::NBO; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sob + eo[i] * 16 + o);
-        aq[s] = fr3[kb * 64];
-      };
-      ld3(0, 0);
-#pragma unroll
-      for (int kb = 0; kb < C::KB; ++kb) {
-        if (kb + 1 < C::KB) ld3(kb + 1, (kb + 1) & 1);
-#pragma unroll
-        for (int i = 0; i < C::NBO; ++i) acc[i] = mfma_bf16(aq[kb & 1], bq[kb & 1][i], acc[i]);
-      }
-      if (g < 2) {
-        // lanes of group g hold output channel g of pixel j
-        int8_t* const s8 = reinterpret_cast<int8_t*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
-        float* const s32 = reinterpret_cast<float*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
-#pragma unroll
-        for (int i = 0; i < C::NBO; ++i) {
-          const float h = C::NSP == 3 ? (acc[i][0] + acc[i][1]) + acc[i][2] : acc[i][0];
+      int8_t* const s8 = reinterpret_cast<int8_t*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
+      float* const s32 = reinterpret_cast<float*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
+      // fire/reset of output block i; lanes of group g < 2 hold output
+      // channel g of pixel j (rows 4g + p of the accumulator)
+      auto out_epilogue = [&](int i, const f4& acc) __attribute__((always_inline)) {
+        if (g < 2) {
+          const float h = C::NSP == 2 ? acc[0] + acc[1] : acc[0];
           if (C::FULL && oo[i] >= 0 && trace_t) {
             const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
             const int gy = gy0 + row, gx = gx0 + col;
-            if (tb.has(gy, gx)) trace_t[(size_t)(choffo + g) * tb.plane() + tb.idx(gy, gx)] = h;
+            if (tb.has(gy, gx)) trace_t[(size_t)(choffo + g) * tb.plane() + tb.idx(gy, gx)] = h * isc3;
           }
           float v = h;
-          const float sp = bilif(v, theta, alpha, false);
+          const float sp = bilif(v, theta3, alpha, false);
           asm volatile("" : "+v"(v));
           vo[i] = v;
           if (oo[i] >= 0 && ca.s_out) {
@@ -1020,6 +1126,57 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             else s8[oo[i]] = (int8_t)sp;
           }
         }
+      };
+      if constexpr (C::BO) {
+        // block by block, as layer 2: all k-step fragments in registers,
+        // block i-1's epilogue overlaps block i's MFMAs
+        u4 a3[C::KB];
+#pragma unroll
+        for (int kb = 0; kb < C::KB; ++kb) a3[kb] = fr3[kb * 64];
+        u4 bq[2][C::KB];
+        f4 acc[2];
+        auto ldb3 = [&](int i, int sl) __attribute__((always_inline)) {
+#pragma unroll
+          for (int kb = 0; kb < C::KB; ++kb) {
+            int tau, cib;
+            kslot<C::CH>(kb, g, tau, cib);
+            const int o = (cib >> 3) * C::SPL + tap_off(tau > 8 ? 8 : tau, C::CWT) * 16;
+            bq[sl][kb] = *reinterpret_cast<const u4*>(sob + eo[i] * 16 + o);
+          }
+        };
+        ldb3(0, 0);
+#pragma unroll
+        for (int i = 0; i <= C::NBO; ++i) {
+          if (i < C::NBO) {
+            if (i + 1 < C::NBO) ldb3(i + 1, (i + 1) & 1);
+            acc[i & 1] = f4{leak * vo[i], 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < C::KB; ++kb) acc[i & 1] = mfma_sp<C>(a3[kb], bq[i & 1][kb], acc[i & 1]);
+          }
+          if (i > 0) out_epilogue(i - 1, acc[(i - 1) & 1]);
+        }
+      } else {
+        f4 acc[C::NBO];
+#pragma unroll
+        for (int i = 0; i < C::NBO; ++i) acc[i] = f4{leak * vo[i], 0.f, 0.f, 0.f};
+        u4 bq[2][C::NBO], aq[2];
+        auto ld3 = [&](int kb, int s) __attribute__((always_inline)) {
+          int tau, cib;
+          kslot<C::CH>(kb, g, tau, cib);
+          const int o = (cib >> 3) * C::SPL + tap_off(tau > 8 ? 8 : tau, C::CWT) * 16;
+#pragma unroll
+          for (int i = 0; i < C::NBO; ++i) bq[s][i] = *reinterpret_cast<const u4*>(sob + eo[i] * 16 + o);
+          aq[s] = fr3[kb * 64];
+        };
+        ld3(0, 0);
+#pragma unroll
+        for (int kb = 0; kb < C::KB; ++kb) {
+          if (kb + 1 < C::KB) ld3(kb + 1, (kb + 1) & 1);
+#pragma unroll
+          for (int i = 0; i < C::NBO; ++i) acc[i] = mfma_sp<C>(aq[kb & 1], bq[kb & 1][i], acc[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < C::NBO; ++i) out_epilogue(i, acc[i]);
       }
     } else {
       // ================= output layer (VALU), weights broadcast from LDS
