@@ -38,11 +38,11 @@ def conv_flops_per_px(channels):
 def mfma_peak(channels, prec):
     """Dense matrix-core peak (TFLOP/s) for the conv mix the forward runs:
     BF16 nets run every conv on the bf16 pipe.  FP32 nets run every conv
-    that reads spikes on the bf16 pipe with each weight split exactly into
-    three bf16 parts (a third of the bf16 rate); their first conv runs on
-    the bf16 pipe with x and W both split into three parts, six part
-    products kept (a sixth of the bf16 rate) for 3 -> 16 nets, and on the
-    f32 pipe otherwise.  Harmonic mean over the layers' flops."""
+    that reads spikes on the fp16 pipe (same rate as bf16) with each weight
+    split into two fp16 parts (half the rate); their first conv runs on the
+    bf16 pipe with x and W both split into three parts, six part products
+    kept (a sixth of the rate) for 3 -> 16 nets, and on the f32 pipe
+    otherwise.  Harmonic mean over the layers' flops."""
     layers = list(zip(channels[:-1], channels[1:]))
     t = fl = 0.0
     for l, (ci, co) in enumerate(layers):
@@ -53,7 +53,7 @@ def mfma_peak(channels, prec):
             split_l1 = ci == 3 and len(layers) >= 2 and co == 16
             peak = BF16_MFMA_PEAK / 6 if split_l1 else FP32_MFMA_PEAK
         else:
-            peak = BF16_MFMA_PEAK / 3
+            peak = BF16_MFMA_PEAK / 2
         t += f / peak
         fl += f
     return fl / t
@@ -412,9 +412,9 @@ def main():
                    "step": "fused forward" + (" + event compaction" if "compact" in forms else "")},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "peak_note": "all convs on the bf16 pipe with exact FP32 emulation: conv 1 at 1/6 of "
+                     "peak_note": "all convs on the 16-bit matrix pipes with FP32 emulation: conv 1 at 1/6 of "
                                   "the bf16 rate (x and W split into 3 bf16 parts, 6 part products), the spike "
-                                  "convs at 1/3 (3-part weight split); vs the FP32 dense peak 157.3: "
+                                  "convs at 1/2 (2 fp16 weight parts); vs the FP32 dense peak 157.3: "
                                   f"{achieved / FP32_MFMA_PEAK:.3f}",
                      "traffic": traffic_from_profile("fwd_L3_h16_f32", px_frames),
                      "kernel": "fwd_kernel<L3 h16 f32>", "kernel_ms": round(fwd_avg, 3),

@@ -11,20 +11,23 @@
 //     the neighbouring tile because every pixel is computed by the same
 //     instruction sequence.  The pixels of each layer's region are packed
 //     densely into 16-pixel MFMA column blocks.
-//   * Per frame, the x tile (+halo) is staged in LDS (register prefetch of
-//     frame t+1 overlaps frame t), and every conv runs as a transposed GEMM
-//     D[cout][pixel] = W[cout][K] * S[K][pixel] on MFMA with K = (tap, cin)
-//     and the pixel operand gathered from LDS; the accumulator fragment IS
-//     the membrane state (C input = leak * v), so BiLIF runs in place.
-//   * Hidden spikes are exactly -1, 0 or +1, so they are stored in LDS as
-//     bf16 and every conv that reads spikes runs on the bf16 matrix core.
-//     FP32 nets keep FP32 semantics there: each FP32 weight is split exactly
-//     into three bf16 parts (hi + mid + lo, 8 significant bits each), the
-//     products with a spike are exact and the sums accumulate in FP32; the
-//     spike fragment of a tap pair is loaded once and multiplied by the
-//     three parts.  BF16 nets use the bf16-rounded weights (one part).  The
-//     first layer reads the FP32 input and stays on the f32 MFMA (FP32 nets)
-//     or on the bf16 one with bf16-rounded input (BF16 nets).
+//   * Per frame, the x tile (+halo) is staged in LDS (the next frame's
+//     loads overlap the current frame), and every conv runs as a transposed
+//     GEMM D[cout][pixel] = W[cout][K] * S[K][pixel] on MFMA with
+//     K = (tap, cin) and the pixel operand gathered from LDS; the
+//     accumulator fragment IS the membrane state (C input = leak * v), so
+//     BiLIF runs in place.
+//   * Hidden spikes are exactly -1, 0 or +1, so every conv that reads them
+//     runs on a 16-bit matrix core.  BF16 nets: bf16 spikes and bf16-rounded
+//     weights.  FP32 nets keep FP32 accuracy: fp16 spikes and each weight,
+//     scaled by a power of two per layer, split into two fp16 parts (every
+//     product within 2^-22, sums in FP32; the state behind the conv is kept
+//     in the scaled units, which is exact).  The spike fragment of a k-step
+//     is loaded once and multiplied by the parts.
+//   * The first layer of FP32 3 -> 16 nets splits both x and W into three
+//     bf16 parts (exact) and keeps six of the nine part products (the
+//     dropped ones are below 2^-23 |w x|); other FP32 nets use the f32 MFMA
+//     for it, BF16 nets the bf16 one with bf16-rounded input.
 //   * The output layer (1-2 channels) puts its (channel, part) pairs on the
 //     MFMA rows: row 4c + p holds part p of channel c, and the potentials
 //     are the sums of the part rows.
