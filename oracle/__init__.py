@@ -12,12 +12,17 @@ helpers).  It is written from the paper (arXiv 2508.18071):
 * ``emd``     -- the 1-D EMD as a difference of cumulative sums (Eq. 7), its
   bidirectional form (Eq. 8), the polarity split (Eq. 9) and the spike-count
   term (Eq. 10-11), with their (sub)gradients.
+* ``prologue`` -- the network input of Eq. 1 (luminance, lin-log map, temporal
+  difference) and contrast-crossing target events.
+* ``tnet``    -- the paper's own temporal EvSNet (Sec. 3.3, Eq. 5-6): a
+  kernel-7 Conv1d encoder with residual blocks, a point-wise projection and
+  one BiLIF unit per pixel.
 
 Every function is pinned by tests that do not re-type its formula: closed
 forms, invariants, library special cases, brute force and finite
 differences.  Nothing here is parity-unpinned.
 """
 
-from . import evsnet, emd
+from . import evsnet, emd, prologue, tnet
 
-__all__ = ["evsnet", "emd"]
+__all__ = ["evsnet", "emd", "prologue", "tnet"]

@@ -569,3 +569,119 @@ def test_contrast_events_step_constant_and_balance():
     resid = lg[-1] - lg[0] - C * (E[:, 0] - E[:, 1]).sum(axis=0)
     assert np.all(np.abs(resid) < C + 1e-12)
     assert np.all(prologue.contrast_events(np.stack([fr[0]] * 6), C) == 0)
+
+
+# ---------------------------------------------------------------- temporal EvSNet (Sec. 3.3, Eq. 5-6)
+
+def test_tnet_conv1d_matches_torch():
+    from oracle import tnet
+    rng = np.random.default_rng(1)
+    h = rng.normal(size=(3, 5, 19))
+    w = rng.normal(size=(4, 5, 7))
+    b = rng.normal(size=4)
+    ref = torch.nn.functional.conv1d(torch.from_numpy(h), torch.from_numpy(w), torch.from_numpy(b), padding=3)
+    np.testing.assert_allclose(tnet.conv1d(h, w, b), ref.numpy(), rtol=1e-13, atol=1e-13)
+
+
+def test_tnet_receptive_field_is_43_frames():
+    """With positive input and weights every ReLU passes its argument, the
+    net is a cascade of seven kernel-7 convolutions, and a change of X at
+    frame t0 moves u exactly on t0-21 .. t0+21 (Sec. 4: W = 43)."""
+    from oracle import tnet
+    p = tnet.init_params(C=4, seed=3)
+    rng = np.random.default_rng(4)
+    p["w0"] = np.abs(p["w0"]) + 0.01
+    for k in range(1, 7):
+        p["w"][k] = np.abs(p["w"][k]) + 0.01
+        p["b"][k] = np.abs(p["b"][k])
+    p["b0"] = np.abs(p["b0"])
+    p["wp"] = np.abs(p["wp"]) + 0.01
+    x = rng.uniform(0.1, 1.0, size=(1, 120))
+    t0 = 60
+    x2 = x.copy()
+    x2[0, t0] += 0.5
+    du = tnet.encode(x2, p)[0] - tnet.encode(x, p)[0]
+    changed = np.nonzero(np.abs(du[0]) > 0)[0]
+    assert changed.min() == t0 - 21 and changed.max() == t0 + 21
+    assert len(changed) == 43
+
+
+def test_tnet_inner_convs_zero_reduce_to_one_conv():
+    """Zero residual branches: h_i = ReLU(h_{i-1}) = h_{i-1}, so u is the
+    point-wise projection of ReLU(conv_0 X), computed here with scipy."""
+    import scipy.signal
+    from oracle import tnet
+    C = 5
+    p = tnet.init_params(C=C, seed=5)
+    for k in range(1, 7):
+        p["w"][k] = np.zeros_like(p["w"][k])
+        p["b"][k] = np.zeros_like(p["b"][k])
+    x = np.random.default_rng(6).normal(size=(2, 40))
+    u, _ = tnet.encode(x, p)
+    for n in range(2):
+        h0 = np.stack([np.maximum(scipy.signal.correlate(x[n], p["w0"][c, 0], mode="same") + p["b0"][c], 0.0)
+                       for c in range(C)])
+        np.testing.assert_allclose(u[n], p["wp"] @ h0 + p["bp"], rtol=1e-12, atol=1e-12)
+    # zero input, zero biases: nothing fires
+    for k in range(1, 7):
+        p["b"][k][:] = 0.0
+    p["b0"][:] = 0.0
+    p["bp"] = 0.0
+    out = tnet.forward(np.zeros((3, 30)), p, 0.5, 0.9)
+    assert np.all(out["u"] == 0) and np.all(out["s"] == 0)
+
+
+def test_tnet_centred_padding_time_reversal():
+    """With symmetric kernels, centred zero padding makes the encoder commute
+    with reversing time (a causal padding would not)."""
+    from oracle import tnet
+    p = tnet.init_params(C=4, seed=7)
+    sym = lambda w: 0.5 * (w + w[..., ::-1])
+    p["w0"] = sym(p["w0"])
+    for k in range(1, 7):
+        p["w"][k] = sym(p["w"][k])
+    x = np.random.default_rng(8).normal(size=(3, 50))
+    u = tnet.encode(x, p)[0]
+    ur = tnet.encode(x[:, ::-1].copy(), p)[0]
+    np.testing.assert_allclose(ur[:, ::-1], u, rtol=1e-12, atol=1e-12)
+    # and a non-symmetric kernel breaks it
+    p["w0"][:, 0, 0] += 0.3
+    ur = tnet.encode(x[:, ::-1].copy(), p)[0]
+    assert np.abs(ur[:, ::-1] - tnet.encode(x, p)[0]).max() > 1e-3
+
+
+def test_tnet_delta_net_is_bilif_of_relu_input():
+    """conv_0 a centred delta on channel 0, zero residual branches, point-wise
+    weight e_0: u = ReLU(X), and the spikes equal the (separately pinned)
+    conv3x3 forward of a one-channel centre-tap identity net on ReLU(X)."""
+    from oracle import tnet
+    C = 3
+    p = tnet.init_params(C=C, seed=9)
+    p["w0"] = np.zeros((C, 1, 7))
+    p["w0"][0, 0, 3] = 1.0
+    p["b0"][:] = 0.0
+    for k in range(1, 7):
+        p["w"][k] = np.zeros_like(p["w"][k])
+        p["b"][k][:] = 0.0
+    p["wp"] = np.zeros(C)
+    p["wp"][0] = 1.0
+    p["bp"] = 0.0
+    x = np.random.default_rng(10).normal(0.2, 0.6, size=(4, 60))
+    out = tnet.forward(x, p, 0.5, 0.9)
+    np.testing.assert_array_equal(out["u"], np.maximum(x, 0.0))
+    w = np.zeros((1, 1, 3, 3))
+    w[0, 0, 1, 1] = 1.0
+    ref = evsnet.forward(np.maximum(x, 0.0).T[:, None, None, :], [w], 0.5, 0.9)
+    np.testing.assert_array_equal(out["s"], ref["s"][:, 0, 0, :].T)
+
+
+def test_tnet_quant_rounds_through_float32_to_bf16():
+    """The BF16 mirror rounds input, weights and stored activations exactly
+    as torch's float32 -> bfloat16 conversion does."""
+    from oracle import tnet
+    p = tnet.init_params(C=3, seed=11)
+    x = np.random.default_rng(12).normal(size=(2, 20))
+    u, layers = tnet.encode(x, p, quant=True)
+    for a in layers:
+        t = torch.from_numpy(a.astype(np.float32))
+        assert np.array_equal(a, t.to(torch.bfloat16).to(torch.float64).numpy())
