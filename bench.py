@@ -297,6 +297,48 @@ def prologue_form(torch, evs, x, args):
     return res
 
 
+TNET_FRAMES = 100
+TNET_FLOPS_PX = 2 * 7 * 16 + 6 * 2 * 7 * 16 * 16 + 2 * 16       # conv0, six 16->16 convs, projection
+
+
+def tnet_form(torch, evs, x, args):
+    """The paper's temporal EvSNet (kernel-7 Conv1d encoder, 3 residual
+    blocks, projection, BiLIF; hidden width 16, BF16 operands) on the Eq. (1)
+    input of the first 101 frames of the 720p clip (100 input frames).
+    Random He-style weights (seeded) in the library's weight order."""
+    T = TNET_FRAMES
+    X = evs.logdiff(x[:, :T + 1].contiguous())[:, :, 0].contiguous()      # [1, T, H, W]
+    net = evs.TNet(hidden=16, theta=0.5, leak=0.9)
+    rng = np.random.default_rng(77)
+    parts = [rng.normal(0, np.sqrt(2.0 / 7), 16 * 7), rng.normal(0, 0.05, 16)]
+    for _ in range(6):
+        parts += [rng.normal(0, np.sqrt(1.0 / (16 * 7)), 16 * 16 * 7), rng.normal(0, 0.05, 16)]
+    parts += [rng.normal(0, np.sqrt(2.0 / 16), 16), rng.normal(0, 0.05, 1)]
+    w = torch.from_numpy(np.concatenate(parts).astype(np.float32)).to(x.device)
+    assert w.numel() == evs.tnet_weight_floats(net)
+    S = torch.empty(X.shape, dtype=torch.int8, device=x.device)
+    for _ in range(max(1, args.warmup)):
+        evs.tnet_forward(net, w, X, out=S)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(max(3, args.steps // 2)):
+        tm = Timer(torch)
+        with tm:
+            evs.tnet_forward(net, w, X, out=S)
+        ts.append(tm)
+    torch.cuda.synchronize()
+    ms = float(np.mean([t.ms() for t in ts]))
+    px_frames = X.numel()
+    tflops = TNET_FLOPS_PX * px_frames / (ms / 1e3) / 1e12
+    log(f"tnet: {ms:.2f} ms for {T} frames, {tflops:.1f} TFLOP/s")
+    return {"workload": f"paper's temporal EvSNet (Conv1d k=7, M=3, width 16, BF16) on Eq. (1) input of "
+                        f"{T} frames of the 720p clip",
+            "frames": T, "ms": round(ms, 3), "value": round(px_frames / PX720 / (ms / 1e3), 1),
+            "unit": "720p event-frames/s", "alg_flops_per_px_frame": TNET_FLOPS_PX,
+            "tflops": round(tflops, 2), "mfma_frac": round(tflops / BF16_MFMA_PEAK, 4),
+            "spikes_per_px_frame": round(float(S.abs().sum()) / px_frames, 4)}
+
+
 def cpu_baseline(x_host, ws, channels, theta, leak, frames):
     from oracle import evsnet
     try:
@@ -319,7 +361,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1000, help="clip length of the headline workload")
-    ap.add_argument("--forms", default="fp32,compact,w32,prologue,train,batched")
+    ap.add_argument("--forms", default="fp32,compact,w32,prologue,tnet,train,batched")
     ap.add_argument("--cpu-frames", type=int, default=16)
     ap.add_argument("--batch-window", type=int, default=200, help="frames per window of the batched form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -468,6 +510,8 @@ def main():
         rec["forms"]["prologue"] = prologue_form(torch, evs, x, args)
     if events is not None:
         del events, cws
+    if "tnet" in forms:
+        rec["forms"]["tnet"] = tnet_form(torch, evs, x, args)
     if "train" in forms:
         del out
         rec["forms"]["train_step"] = train_form(torch, synth, evs, dev, x, args)

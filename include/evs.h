@@ -258,6 +258,36 @@ int evs_logdiff(const float* rgb, int32_t N, int32_t T, int32_t H, int32_t W,
 int evs_contrast_events(const float* rgb, int32_t N, int32_t T, int32_t H, int32_t W,
                         float lum_scale, float knee, float C, int8_t* e_out, void* stream);
 
+/* The paper's own temporal EvSNet (Sec. 3.3, Eq. 5-6; kernel size 7 and
+ * depth M = 3 from Sec. 4): per pixel of a one-channel input sequence X,
+ *     h0 = ReLU(conv0 X),
+ *     h_i = ReLU(h_{i-1} + conv_{2i}(ReLU(conv_{2i-1} h_{i-1}))), i = 1..3,
+ *     u = wp . h3 + bp,  S = BiLIF(u) over time (Eq. 2-3, v starts at 0).
+ * Every conv is a kernel-7 cross-correlation over frames with zero padding
+ * of 3 frames on both sides (centred: frame t sees t-21 .. t+21 overall)
+ * and a bias per output channel; pixels are independent.  Operands are
+ * rounded to bfloat16 (input, weights, stored activations h_i, a_i),
+ * sums, biases and the BiLIF state are FP32.
+ *   net      hidden = 16 (the only width compiled), theta > 0, leak in [0, 1]
+ *   weights  device float32, evs_tnet_weight_floats() values in this order:
+ *            w0 [16][7], b0 [16]; then for k = 1..6: w_k [16][16][7]
+ *            ([out][in][tap]), b_k [16]; then wp [16], bp [1]
+ *   x        [N][T][H][W] float32 (e.g. the output of evs_logdiff)
+ *   s_out    [N][T][H][W] int8 spikes in {-1, 0, 1}
+ *   debug    NULL, or [N][T][7*16 + 2][H][W] float32: the activations h0,
+ *            a1, h1, a2, h2, a3, h3 (16 channels each, bf16 values), u and
+ *            the charged BiLIF potential leak * v + u, per frame
+ * Returns EVS_EUNSUPPORTED for other widths, EVS_EINVAL / EVS_EOVERFLOW
+ * for bad arguments (checked before anything is enqueued).              */
+typedef struct evs_tnet {
+  int32_t hidden;
+  float theta;
+  float leak;
+} evs_tnet;
+size_t evs_tnet_weight_floats(const evs_tnet* net);
+int evs_tnet_forward(const evs_tnet* net, const float* weights, const float* x, int32_t N, int32_t T,
+                     int32_t H, int32_t W, int8_t* s_out, float* debug, void* stream);
+
 /* Time the compiled tile shapes for this network and frame size on
  * `stream` (allocates its own scratch; not capture-safe) and remember the
  * fastest for later evs_forward calls with this (net, H, W).  If the

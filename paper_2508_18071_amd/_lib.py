@@ -36,6 +36,14 @@ class EvsNet(ctypes.Structure):
     ]
 
 
+class EvsTnet(ctypes.Structure):
+    _fields_ = [
+        ("hidden", ctypes.c_int32),
+        ("theta", ctypes.c_float),
+        ("leak", ctypes.c_float),
+    ]
+
+
 class EvsClip(ctypes.Structure):
     _fields_ = [
         ("N", ctypes.c_int32), ("T", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
@@ -67,6 +75,9 @@ _SIGS = [
     ("evs_compact_events", ctypes.c_int,
      [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P,
       _P, ctypes.c_size_t, _P]),
+    ("evs_tnet_weight_floats", ctypes.c_size_t, [_P]),
+    ("evs_tnet_forward", ctypes.c_int,
+     [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     ("evs_logdiff", ctypes.c_int,
      [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _P, _P]),
     ("evs_contrast_events", ctypes.c_int,

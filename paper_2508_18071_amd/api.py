@@ -12,7 +12,7 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _lib
-from ._lib import EvsClip, EvsNet, check, lib
+from ._lib import EvsClip, EvsNet, EvsTnet, check, lib
 
 
 @dataclass
@@ -277,6 +277,43 @@ def contrast_events(rgb: torch.Tensor, C: float = 0.2, lum_scale: float = 255.0,
     check(lib().evs_contrast_events(rgb.data_ptr(), N, T, H, W, float(lum_scale), float(knee), float(C),
                                     e.data_ptr(), _stream(stream)), "contrast_events")
     return e[0] if squeeze else e
+
+
+@dataclass
+class TNet:
+    """The paper's temporal EvSNet: kernel-7 Conv1d encoder with 3 residual
+    blocks, point-wise projection and one BiLIF unit per pixel."""
+    hidden: int = 16
+    theta: float = 0.5
+    leak: float = 0.9
+
+    def c(self) -> EvsTnet:
+        n = EvsTnet()
+        n.hidden, n.theta, n.leak = self.hidden, self.theta, self.leak
+        return n
+
+
+def tnet_weight_floats(net: TNet) -> int:
+    cn = net.c()
+    return int(lib().evs_tnet_weight_floats(ctypes.byref(cn)))
+
+
+def tnet_forward(net: TNet, weights: torch.Tensor, x: torch.Tensor, debug: bool = False, out=None, stream=None):
+    """x [N, T, H, W] (or [N, T, 1, H, W]) float32 -> spikes int8 of the same
+    shape; with debug, also [N, T, 7*16 + 2, H, W] float32 activations, u and
+    the charged potential (see evs_tnet_forward)."""
+    if x.dim() == 5:
+        x = x[:, :, 0]
+    _check_dev(x, weights)
+    if x.dtype != torch.float32 or weights.dtype != torch.float32:
+        raise ValueError("x and weights must be float32")
+    N, T, H, W = x.shape
+    s = out if out is not None else torch.empty(N, T, H, W, dtype=torch.int8, device=x.device)
+    d = torch.empty(N, T, 7 * net.hidden + 2, H, W, dtype=torch.float32, device=x.device) if debug else None
+    cn = net.c()
+    check(lib().evs_tnet_forward(ctypes.byref(cn), weights.data_ptr(), x.data_ptr(), N, T, H, W, s.data_ptr(),
+                                 d.data_ptr() if d is not None else None, _stream(stream)), "tnet_forward")
+    return s, d
 
 
 def backward(net: Net, packed, x, ckpt, ckpt_every, grad_s, want_dx=False, want_dv=False, stream=None):

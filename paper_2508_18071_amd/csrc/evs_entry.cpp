@@ -17,6 +17,15 @@ int evs_compact_events(const int8_t* s, int32_t T, int32_t C, int32_t H, int32_t
                        int64_t capacity, int64_t* count, void* ws, size_t wsb, void* stream) {
   return evs::compact_events(s, T, C, H, W, events, capacity, count, ws, wsb, (hipStream_t)stream);
 }
+size_t evs_tnet_weight_floats(const evs_tnet* net) {
+  if (!net || net->hidden != 16) return (size_t)-1;
+  return evs::tnet_weight_floats();
+}
+int evs_tnet_forward(const evs_tnet* net, const float* weights, const float* x, int32_t N, int32_t T, int32_t H,
+                     int32_t W, int8_t* s_out, float* debug, void* stream) {
+  if (!net) return evs::fail(EVS_EINVAL, "tnet: net is NULL");
+  return evs::tnet_forward(*net, weights, x, N, T, H, W, s_out, debug, (hipStream_t)stream);
+}
 int evs_logdiff(const float* rgb, int32_t N, int32_t T, int32_t H, int32_t W, float lum_scale, float knee,
                 float* x_out, void* stream) {
   return evs::logdiff(rgb, N, T, H, W, lum_scale, knee, x_out, (hipStream_t)stream);

@@ -21,6 +21,10 @@ size_t compact_workspace_bytes(int T, int C, int H, int W);
 int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events, int64_t cap,
                    int64_t* count, void* ws, size_t ws_bytes, hipStream_t st);
 
+// the paper's temporal EvSNet (evs_tnet.hip)
+size_t tnet_weight_floats();
+int tnet_forward(const evs_tnet& net, const float* weights, const float* x, int N, int T, int H, int W, int8_t* s_out,
+                 float* debug, hipStream_t st);
 // network input of Eq. 1 and contrast-crossing targets (evs_prologue.hip)
 int logdiff(const float* rgb, int N, int T, int H, int W, float scale, float knee, float* x_out, hipStream_t st);
 int contrast_events(const float* rgb, int N, int T, int H, int W, float scale, float knee, float C, int8_t* e_out,

@@ -1,0 +1,148 @@
+"""GPU parity of the paper's temporal EvSNet (Sec. 3.3, Eq. 5-6) through the
+C ABI against the FP64 oracle (oracle/tnet.py).
+
+* Teacher-forced, layer by layer: each conv is recomputed in FP64 from the
+  kernel's own (bf16) inputs with bf16 weights; the kernel stores its FP32
+  sum rounded to bf16, so it must lie within half a bf16 unit (2^-8
+  relative) plus the FP32 summation error, and match exactly almost
+  everywhere.  The projection u within FP32 rounding, the BiLIF step
+  exactly consistent with its own potential.
+* End to end: spikes of the BF16 oracle (no forcing) on >= 99% of outputs.
+* The 43-frame receptive field on the GPU: changing X at frame t0 leaves u
+  bit-identical outside t0-21 .. t0+21 (the streaming rings, delays and the
+  zero padding at both ends of the clip).
+* Ragged pixel blocks, short clips (T < 7, T = 1), several clips.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+from oracle import evsnet, tnet  # noqa: E402
+
+C = 16
+THETA, LEAK = float(np.float32(0.5)), float(np.float32(0.9))
+
+
+@pytest.fixture(scope="module")
+def evs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_18071_amd as m
+    m.lib()
+    return m
+
+
+def _setup(evs, N, T, H, W, seed=0):
+    p = tnet.init_params(C=C, seed=seed)
+    flat = tnet.flatten_params(p).astype(np.float32)
+    net = evs.TNet(hidden=C, theta=THETA, leak=LEAK)
+    assert evs.tnet_weight_floats(net) == flat.size
+    rng = np.random.default_rng(seed + 100)
+    x = rng.normal(0.0, 0.8, size=(N, T, H, W)).astype(np.float32)
+    return p, flat, net, x
+
+
+def _run(evs, net, flat, x, debug=True):
+    s, d = evs.tnet_forward(net, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(), debug=debug)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), (d.cpu().numpy().astype(np.float64) if d is not None else None)
+
+
+def _bf(a):
+    return evsnet.bf16_round(a)
+
+
+@pytest.mark.parametrize("N,T,H,W", [(2, 50, 5, 9), (1, 6, 4, 4), (3, 1, 3, 7), (1, 40, 16, 16)])
+def test_tnet_teacher_forced_layers(evs, N, T, H, W):
+    p, flat, net, x = _setup(evs, N, T, H, W, seed=N + T)
+    s, d = _run(evs, net, flat, x)
+    P = H * W
+    q = {"w0": _bf(p["w0"]), "w": [None] + [_bf(w) for w in p["w"][1:]], "wp": _bf(p["wp"])}
+    worst = 0.0
+    exact = total = 0
+    for n in range(N):
+        D = d[n].reshape(T, 7 * C + 2, P).transpose(2, 1, 0)        # [P][ch][T]
+        layers = [D[:, L * C:(L + 1) * C, :] for L in range(7)]
+        u_gpu, h_gpu = D[:, 7 * C, :], D[:, 7 * C + 1, :]
+        xin = _bf(x[n].reshape(T, P).T)[:, None, :]
+        for L in range(7):
+            inp = xin if L == 0 else layers[L - 1]
+            w = q["w0"] if L == 0 else q["w"][L]
+            b = p["b0"] if L == 0 else p["b"][L]
+            pre = tnet.conv1d(inp, w, b)
+            if L in (2, 4, 6):
+                pre = pre + layers[L - 2]
+            ref = np.maximum(pre, 0.0)
+            err = np.abs(layers[L] - ref)
+            bound = 2.0 ** -8 * np.abs(ref) + 1e-6 * max(np.abs(ref).max(), 1e-30)
+            worst = max(worst, float((err / bound).max()))
+            assert np.all(err <= bound), (n, L, float((err - bound).max()))
+            exact += int((layers[L] == _bf(ref)).sum())
+            total += ref.size
+        u_ref = np.einsum("c,pct->pt", q["wp"], layers[6]) + p["bp"]
+        scale = np.einsum("c,pct->pt", np.abs(q["wp"]), np.abs(layers[6])) + abs(p["bp"])
+        assert np.all(np.abs(u_gpu - u_ref) <= 1e-6 * scale + 1e-30)
+        # BiLIF along the kernel's own trajectory
+        v = np.zeros(P)
+        for t in range(T):
+            hr = LEAK * v + u_gpu[:, t]
+            assert np.all(np.abs(h_gpu[:, t] - hr) <= 1e-6 * (np.abs(hr) + 1e-6))
+            st = s[n, t].reshape(P).astype(np.float64)
+            np.testing.assert_array_equal(st, evsnet.fire(h_gpu[:, t], THETA))
+            v = h_gpu[:, t] - THETA * st
+    print(f"  tnet {N}x{T}x{H}x{W}: worst err/bound {worst:.3f}, exact bf16 matches {exact}/{total}", flush=True)
+    assert exact >= 0.99 * total
+    assert int(np.abs(s).sum()) > 0 or T < 4
+
+
+def test_tnet_end_to_end_matches_bf16_oracle(evs):
+    N, T, H, W = 1, 80, 8, 12
+    p, flat, net, x = _setup(evs, N, T, H, W, seed=21)
+    s, _ = _run(evs, net, flat, x, debug=False)
+    ref = tnet.forward(x[0].reshape(T, H * W).T.astype(np.float64), p, THETA, LEAK, quant=True)
+    agree = float((ref["s"].T.reshape(T, H, W) == s[0]).mean())
+    print(f"  tnet end to end: spike agreement {agree:.5f}, spikes {int(np.abs(s).sum())}", flush=True)
+    assert agree >= 0.99
+    assert int(np.abs(s).sum()) > 0
+
+
+def test_tnet_receptive_field_on_gpu(evs):
+    N, T, H, W = 1, 90, 4, 8
+    p, flat, net, x = _setup(evs, N, T, H, W, seed=31)
+    t0 = 45
+    x2 = x.copy()
+    x2[0, t0] += 1.0
+    _, d1 = _run(evs, net, flat, x)
+    _, d2 = _run(evs, net, flat, x2)
+    du = np.abs(d2[0, :, 7 * C] - d1[0, :, 7 * C]).reshape(T, -1).max(axis=1)
+    changed = np.nonzero(du > 0)[0]
+    assert changed.min() >= t0 - 21 and changed.max() <= t0 + 21, changed
+    assert np.array_equal(d1[0, :t0 - 21], d2[0, :t0 - 21])
+    assert changed.min() <= t0 - 15 and changed.max() >= t0 + 15
+
+
+def test_tnet_zero_input_and_bias_is_silent(evs):
+    N, T, H, W = 1, 30, 4, 5
+    p, flat, net, x = _setup(evs, N, T, H, W, seed=41)
+    p["b0"][:] = 0.0
+    for k in range(1, 7):
+        p["b"][k][:] = 0.0
+    p["bp"] = 0.0
+    flat = tnet.flatten_params(p).astype(np.float32)
+    s, d = _run(evs, net, flat, np.zeros_like(x))
+    assert np.all(s == 0) and np.all(d == 0)
+
+
+def test_tnet_rejects_bad_arguments(evs):
+    import ctypes
+    net = evs.TNet(hidden=32).c()
+    st = evs.lib().evs_tnet_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 4, 4, 4,
+                                    ctypes.c_void_p(16), None, None)
+    assert st == 2
+    net = evs.TNet(theta=0.0).c()
+    st = evs.lib().evs_tnet_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 4, 4, 4,
+                                    ctypes.c_void_p(16), None, None)
+    assert st == 1
