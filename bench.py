@@ -148,7 +148,7 @@ def train_form(torch, synth, evs, dev, x720, args):
         xs.append(x720[0, t0:t0 + wl.T, :, y0:y0 + wl.H, x0:x0 + wl.W])
         clean = synth.make_clip(synth.WORKLOADS["planes720"], device=dev, t0=t0, T=wl.T, y0=y0, x0=x0,
                                 H=wl.H, W=wl.W, clean=True)
-        es.append(synth.contrast_events(clean))
+        es.append(evs.contrast_events(clean))
     xb = torch.stack(xs).contiguous()
     eb = torch.stack(es).contiguous()
     res = {"workload": "4 crops x 64 frames x 256x256 of the 720p clip, net 3->16->16->2, "

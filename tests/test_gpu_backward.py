@@ -161,7 +161,8 @@ def test_autograd_training_step_matches_oracle(evs):
     T, H, W = 8, 24, 24
     x, ws, net, packed = _setup(evs, channels, "fp32", T, H, W, seed=11)
     clean = synth.make_clip(synth.WORKLOADS["planes720"], T=T, H=H, W=W, y0=37, x0=51, clean=True)
-    e = synth.contrast_events(clean)
+    from oracle import prologue
+    e = torch.from_numpy(prologue.contrast_events(clean.numpy().astype(np.float64)))
     wt = [torch.from_numpy(w).cuda().requires_grad_(True) for w in ws]
     xg = x.cuda()
     s = ag.evsnet(net, xg, wt, ckpt_every=4)
