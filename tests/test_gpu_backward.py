@@ -172,7 +172,7 @@ def test_autograd_training_step_matches_oracle(evs):
     ref = evsnet.forward(x[0].numpy(), ws, THETA, LEAK)
     assert np.array_equal(ref["s"], s[0].detach().cpu().numpy())
     l_ref, g_s = emd.loss_and_grad(ref["s"], e[:, 0].numpy(), e[:, 1].numpy())
-    assert float(loss) == pytest.approx(l_ref, rel=1e-6)
+    assert float(loss.detach()) == pytest.approx(l_ref, rel=1e-6)
     g = evsnet.backward(x[0].numpy(), ws, THETA, LEAK, g_s)
     for l in range(3):
         assert _rel(wt[l].grad.cpu().numpy(), g["dW"][l]) < 1e-4
