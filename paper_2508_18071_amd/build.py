@@ -24,6 +24,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
 
 
+# Per-source extra flags.  evs_tnet.hip keeps its register rings as 16-dword
+# vectors whose 4-dword slices feed the MFMAs in place; LLVM's splitting of
+# large vector phis into 32-bit pieces would turn those slices into copies.
+EXTRA = {"evs_tnet.hip": ["-mllvm", "-amdgpu-codegenprepare-break-large-phis=false"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
@@ -31,7 +37,7 @@ def sources():
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, *COMMON, "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
