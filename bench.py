@@ -297,17 +297,17 @@ def prologue_form(torch, evs, x, args):
     return res
 
 
-TNET_FRAMES = 100
 TNET_FLOPS_PX = 2 * 7 * 16 + 6 * 2 * 7 * 16 * 16 + 2 * 16       # conv0, six 16->16 convs, projection
 
 
 def tnet_form(torch, evs, x, args):
     """The paper's temporal EvSNet (kernel-7 Conv1d encoder, 3 residual
     blocks, projection, BiLIF; hidden width 16, BF16 operands) on the Eq. (1)
-    input of the first 101 frames of the 720p clip (100 input frames).
-    Random He-style weights (seeded) in the library's weight order."""
-    T = TNET_FRAMES
-    X = evs.logdiff(x[:, :T + 1].contiguous())[:, :, 0].contiguous()      # [1, T, H, W]
+    input of the whole 720p clip (T+1 RGB frames give T input frames: one
+    second of 1000 FPS event video).  Random He-style weights (seeded) in the
+    library's weight order."""
+    T = x.shape[1] - 1
+    X = evs.logdiff(x[:, :T + 1])[:, :, 0].contiguous()                 # [1, T, H, W]
     net = evs.TNet(hidden=16, theta=0.5, leak=0.9)
     rng = np.random.default_rng(77)
     parts = [rng.normal(0, np.sqrt(2.0 / 7), 16 * 7), rng.normal(0, 0.05, 16)]
@@ -331,8 +331,9 @@ def tnet_form(torch, evs, x, args):
     px_frames = X.numel()
     tflops = TNET_FLOPS_PX * px_frames / (ms / 1e3) / 1e12
     log(f"tnet: {ms:.2f} ms for {T} frames, {tflops:.1f} TFLOP/s")
+    del X
     return {"workload": f"paper's temporal EvSNet (Conv1d k=7, M=3, width 16, BF16) on Eq. (1) input of "
-                        f"{T} frames of the 720p clip",
+                        f"{T} frames of the 720p clip (one launch)",
             "frames": T, "ms": round(ms, 3), "value": round(px_frames / PX720 / (ms / 1e3), 1),
             "unit": "720p event-frames/s", "alg_flops_per_px_frame": TNET_FLOPS_PX,
             "tflops": round(tflops, 2), "mfma_frac": round(tflops / BF16_MFMA_PEAK, 4),

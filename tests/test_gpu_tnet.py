@@ -149,17 +149,18 @@ def test_tnet_rejects_bad_arguments(evs):
 
 
 def test_tnet_full_720p_sampled_pixels(evs):
-    """The benchmarked launch: one 1280x720 clip of 100 Eq. (1) input frames
-    (from the 1-SPP textured-planes workload) in one call; spikes at 256
-    sampled pixels (the four corners, the centre, the rest seeded) against
-    the BF16 oracle fed by the FP64 oracle of Eq. (1)."""
+    """The benchmarked launch: one 1280x720 clip of 999 Eq. (1) input frames
+    (1000 RGB frames of the 1-SPP textured-planes workload) in one call;
+    spikes at 256 sampled pixels (64 columns, the edge columns among them, on
+    the top, middle, bottom and one seeded row) against the BF16 oracle fed
+    by the FP64 oracle of Eq. (1)."""
     import synth
     from oracle import prologue
     wl = synth.WORKLOADS["planes720"]
-    T, H, W = 100, wl.H, wl.W
+    T, H, W = 999, wl.H, wl.W
     rng = np.random.default_rng(5)
-    pts = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, W // 2)]
-    pts += [(int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(251)]
+    rows = [0, H // 2, H - 1, int(rng.integers(1, H - 1))]
+    cols = [np.concatenate([[0, W - 1], rng.choice(np.arange(1, W - 1), 62, replace=False)]) for _ in rows]
     p = tnet.init_params(C=C, seed=9, scale=0.5)
     flat = tnet.flatten_params(p).astype(np.float32)
     net = evs.TNet(hidden=C, theta=THETA, leak=LEAK)
@@ -168,16 +169,20 @@ def test_tnet_full_720p_sampled_pixels(evs):
     del clip
     s, _ = evs.tnet_forward(net, torch.from_numpy(flat).cuda(), X, debug=False)
     torch.cuda.synchronize()
-    ys = torch.tensor([q[0] for q in pts], device="cuda")
-    xs = torch.tensor([q[1] for q in pts], device="cuda")
+    ys = torch.tensor(np.repeat(rows, 64), device="cuda")
+    xs = torch.tensor(np.concatenate(cols), device="cuda")
     s_px = s[0][:, ys, xs].T.cpu().numpy().astype(np.float64)           # [P][T]
     x_px = X[0][:, ys, xs].T.cpu().numpy().astype(np.float64)
-    xr = np.stack([prologue.logdiff(synth.make_clip(wl, T=T + 1, y0=y, x0=x, H=1, W=1).numpy())[:, 0, 0, 0]
-                   for y, x in pts])
+    del X, s
+    xr = []
+    for r, cs in zip(rows, cols):
+        row = synth.make_clip(wl, T=T + 1, y0=r, H=1, W=W).numpy()
+        xr.append(prologue.logdiff(row[:, :, :, cs].astype(np.float64))[:, 0, 0, :].T)
+    xr = np.concatenate(xr)
     assert np.all(np.abs(x_px - xr) <= 1e-5 * (1.0 + np.abs(xr)))
     ref = tnet.forward(xr, p, THETA, LEAK, quant=True)["s"]
     agree = float((ref == s_px).mean())
-    print(f"  tnet 720p x {T}: spike agreement {agree:.5f} at {len(pts)} pixels, "
+    print(f"  tnet 720p x {T}: spike agreement {agree:.5f} at {len(xr)} pixels, "
           f"rate {np.abs(s_px).mean():.3f}", flush=True)
     assert agree >= 0.99
     assert 0.05 < np.abs(s_px).mean() < 0.95
