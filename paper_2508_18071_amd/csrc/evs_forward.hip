@@ -170,9 +170,11 @@ template <int N>
 constexpr int kVmcntEncoded = (N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14);
 static_assert(kVmcntEncoded<0> == 0x0f70, "s_waitcnt encoding");
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ inline unsigned pack_bf16x2(float lo, float hi) {
-  // both values are exact in bf16: take the upper halves of the floats
-  return (__builtin_bit_cast(unsigned, lo) >> 16) | (__builtin_bit_cast(unsigned, hi) & 0xffff0000u);
+  // both values are exact in bf16: one hardware conversion of the pair
+  const bf16x2 p = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(unsigned, p);
 }
 
 // Split three FP32 values into bf16 parts x = h + m + l (round to nearest:
@@ -785,7 +787,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             v = __fsub_rn(l, xl_prev[k]);
             xl_prev[k] = l;
           }
-          if constexpr (C::BF16) xsb[c * C::XPL + C::PADF + rem] = f32_to_bf16_rne(v);
+          if constexpr (C::BF16) xsb[c * C::XPL + C::PADF + rem] = __builtin_bit_cast(uint16_t, (__bf16)v);
           else xsf[c * C::XPL + C::PADF + rem] = v;
         }
       }
