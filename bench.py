@@ -340,6 +340,46 @@ def tnet_form(torch, evs, x, args):
             "spikes_per_px_frame": round(float(S.abs().sum()) / px_frames, 4)}
 
 
+def attainable_peaks(torch, dev):
+    """What plain library work reaches on this GPU, as context for the spec
+    peaks the roofline uses: a 4 GiB device copy (read + write bytes) and a
+    square bf16 GEMM (torch.mm, 8192^3)."""
+    a = torch.empty(1 << 30, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        tm = Timer(torch)
+        with tm:
+            b.copy_(a)
+        ts.append(tm)
+    torch.cuda.synchronize()
+    copy_ms = min(t.ms() for t in ts)
+    del a, b
+    n = 8192
+    ma = torch.randn(n, n, device=dev).to(torch.bfloat16)
+    mb = torch.randn(n, n, device=dev).to(torch.bfloat16)
+    mc = torch.mm(ma, mb)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(10):
+        tm = Timer(torch)
+        with tm:
+            torch.mm(ma, mb, out=mc)
+        ts.append(tm)
+    torch.cuda.synchronize()
+    mm_ms = min(t.ms() for t in ts)
+    del ma, mb, mc
+    torch.cuda.empty_cache()
+    gbs = 2 * 4 * (1 << 30) / (copy_ms / 1e3) / 1e9
+    tfs = 2 * n ** 3 / (mm_ms / 1e3) / 1e12
+    log(f"attainable: copy {gbs:.0f} GB/s, bf16 GEMM {tfs:.0f} TFLOP/s")
+    return {"hbm_copy_GBps": round(gbs, 1), "hbm_copy_frac_of_spec": round(gbs / 8000.0, 4),
+            "bf16_gemm_TFLOPs": round(tfs, 1), "bf16_gemm_frac_of_spec": round(tfs / BF16_MFMA_PEAK, 4),
+            "note": "torch device copy of 4 GiB and torch.mm bf16 8192^3 (hipBLASLt), best of 5/10"}
+
+
 def cpu_baseline(x_host, ws, channels, theta, leak, frames):
     from oracle import evsnet
     try:
@@ -521,6 +561,10 @@ def main():
         torch.cuda.empty_cache()
         rec["forms"]["batched"] = batched_form(torch, synth, evs, dev, args)
         x = None
+
+    # ------------------------------------------------------------ attainable peaks (context)
+    if "attainable" in forms or forms >= {"fp32", "tnet"}:
+        rec["attainable"] = attainable_peaks(torch, dev)
 
     # ------------------------------------------------------------ CPU baseline
     if not args.no_cpu_baseline:
