@@ -67,6 +67,11 @@ struct Cfg {
   static_assert(!(BF16_ && MODE_ == 2), "relaxed spikes are FP32 only");
   static constexpr int CO = 2;                       // output channels (max)
   static constexpr int NH = NL - 1;                  // hidden layers
+  // BF16 nets compute layer 1 over whole canvas rows (the two edge columns
+  // are junk nobody reads), so a lane's canvas pixel advances by the same
+  // amount from block to block and every layer-1 x gather is a per-lane base
+  // plus an immediate offset
+  static constexpr bool L1LIN = BF16_ && NL >= 2;
   static constexpr int CHT = TH + 2 * NL, CWT = TW + 2 * NL;
   static constexpr int NPIX = CHT * CWT;
   static constexpr int PADF = 32;                    // front pad of every LDS plane (pixels)
@@ -75,7 +80,7 @@ struct Cfg {
   // layer l (1 = first hidden layer, NL = output layer) covers canvas rows
   // [l, CHT-l) and columns [l, CWT-l)
   static constexpr int rgh(int l) { return CHT - 2 * l; }
-  static constexpr int rgw(int l) { return CWT - 2 * l; }
+  static constexpr int rgw(int l) { return (L1LIN && l == 1) ? CWT : CWT - 2 * l; }
   static constexpr int nblk(int l) { return cdiv(rgh(l) * rgw(l), 16); }
   static constexpr int NB1 = NH >= 1 ? cdiv(nblk(1), NW) : 1;
   static constexpr int NB2 = NH >= 2 ? cdiv(nblk(2), NW) : 1;
@@ -121,7 +126,11 @@ struct Cfg {
   // x buffer: front pad, CIN planes and the zero plane back to back (plane
   // stride NPIX), then room for the neighbourhood of the junk pixel
   static constexpr int XPL = NPIX;
-  static constexpr int XS1 = align16((PADF + (CIN + 1) * XPL + 2 * CWT + 4) * XELEM);
+  // room after the zero plane: tap offsets of real pixels, and the linear
+  // layer-1 gathers of the tail lanes of the last block
+  static constexpr int XTAIL = L1LIN && 16 * NW * NB1 + 2 * CWT + 2 - XPL > 2 * CWT + 4
+                                   ? 16 * NW * NB1 + 2 * CWT + 2 - XPL : 2 * CWT + 4;
+  static constexpr int XS1 = align16((PADF + (CIN + 1) * XPL + XTAIL) * XELEM);
   static constexpr int XS_BYTES = XSPLIT ? 3 * NPIXL * 8 : XS1 * (XDMA ? 2 : 1);
   static constexpr int SELEM = S16 ? 2 : 4;
   // bf16 spikes are stored as CH/8 planes of [pixel][8 channels] (16 B per
@@ -136,6 +145,8 @@ struct Cfg {
   static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
   static_assert(NB1 <= 32 && NB2 <= 32 && NBO <= 32 && NOUT <= 32, "mask words overflow");
   static_assert(PADF + JP + CWT + 1 < NPIXL, "junk pixel neighbourhood outside the planes");
+  static_assert(!L1LIN || PADF + CIN * XPL + 2 * CWT + 16 * NW * NB1 < XS1 / XELEM,
+                "linear layer-1 gathers outside the x buffer");
   static_assert(CWT <= 64, "a canvas row must fit one wave");
 };
 
@@ -470,7 +481,7 @@ __device__ __forceinline__ int block_pixel(int l, int b, int j, int gy0, int gx0
     ok = false;
     return C::PADF + C::JP;
   }
-  const int row = l + q / w, col = l + q % w;
+  const int row = l + q / w, col = ((C::L1LIN && l == 1) ? 0 : l) + q % w;
   const int gy = gy0 + row, gx = gx0 + col;
   ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
   return C::PADF + row * C::CWT + col;
@@ -957,13 +968,17 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             const int tap = K / C::CIN, c = K - tap * C::CIN;
             o[e] = K < C::K1 ? c * C::XPL + tap_off(tap, C::CWT) : C::CIN * C::XPL;
           }
+          // lane (j, wave) of block i sits at canvas pixel l1b + 16 NW i
+          // (whole-row layer-1 region); tail lanes of the last block read
+          // inside the buffer's tail room and are not stored
+          const uint16_t* xl = xsb + C::PADF + C::CWT + 16 * wave + j;
           u4 bv[C::NB1];
 #pragma unroll
           for (int i = 0; i < C::NB1; ++i) {
             unsigned wd[4];
 #pragma unroll
             for (int e2 = 0; e2 < 4; ++e2) {
-              const unsigned r0 = xsb[e1[i] + o[2 * e2]], r1 = xsb[e1[i] + o[2 * e2 + 1]];
+              const unsigned r0 = xl[o[2 * e2] + 16 * C::NW * i], r1 = xl[o[2 * e2 + 1] + 16 * C::NW * i];
               wd[e2] = r0 | (r1 << 16);
             }
             bv[i] = u4{wd[0], wd[1], wd[2], wd[3]};
