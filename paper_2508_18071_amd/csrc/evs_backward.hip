@@ -186,14 +186,30 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
   }
 }
 
-// acc[e] += sum_b partial[b][e] in block order (e over padded pairs x 9)
-__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ partial, int nblocks, int E,
-                                                   float* __restrict__ acc) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= E) return;
+// acc[e] += sum_b partial[b][e] (e over padded pairs x 9).  A workgroup
+// takes 32 consecutive e; each of its 8 b-lanes sums the partials b = lane,
+// lane + 8, ... in order, then the 8 lane sums are added in lane order: a
+// fixed association, so the result is the same on every run.
+constexpr int kRedE = 32, kRedB = 8;
+__global__ __launch_bounds__(kRedE * kRedB) void k_dw_reduce(const float* __restrict__ partial, int nblocks,
+                                                            int E, float* __restrict__ acc) {
+  __shared__ float red[kRedB][kRedE];
+  const int el = threadIdx.x % kRedE, bl = threadIdx.x / kRedE;
+  const int e = blockIdx.x * kRedE + el;
   float s = 0.f;
-  for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * E + e];
-  acc[e] += s;
+  if (e < E) {
+    const float* p = partial + e;
+#pragma unroll 8
+    for (int b = bl; b < nblocks; b += kRedB) s += p[(size_t)b * E];
+  }
+  red[bl][el] = s;
+  __syncthreads();
+  if (bl == 0 && e < E) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRedB; ++k) t += red[k][el];
+    acc[e] += t;
+  }
 }
 
 // grad_w[co][ci][tap] (real layout) from the padded accumulator
@@ -359,7 +375,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
 #undef EVS_CALL_DW
       EVS_HIP(hipGetLastError());
       const int E = CI * CO * 9;
-      hipLaunchKernelGGL(k_dw_reduce, dim3((E + 255) / 256), dim3(256), 0, st, partial,
+      hipLaunchKernelGGL(k_dw_reduce, dim3((E + kRedE - 1) / kRedE), dim3(kRedE * kRedB), 0, st, partial,
                          Lo.tiles_x * Lo.tiles_y * N, E, acc + accofs[l - 1]);
       EVS_HIP(hipGetLastError());
       // gradient for the layer below (or the input)
