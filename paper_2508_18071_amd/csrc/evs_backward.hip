@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
   for (int k = 0; k < PPT; ++k)
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) acc[k][tap] = 0.f;
-  const int sub = TPP > 1 ? threadIdx.x / P : 0;      // pixel subset of this thread
+  const int sub = TPP > 1 ? threadIdx.x / P : 0;      // row subset of this thread
   for (int t = 0; t < len; ++t) {
     __syncthreads();
     const float* g = gh + ((size_t)n * len + t) * Cout * HW;
@@ -156,12 +156,29 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
     for (int k = 0; k < PPT; ++k) {
       const int pr = (TPP > 1 ? threadIdx.x % P : threadIdx.x + NTH * k);
       const int co = pr / CINP, ci = pr % CINP;
-      for (int p = sub; p < TT * TT; p += TPP) {
-        const float gvv = ghs[co][p];
-        const int py = p / TT, px = p % TT;
+      // rows sub, sub + TPP, ...; along a row the 3x3 input window slides,
+      // so each pixel reads one new column of three values
+      for (int py = sub; py < TT; py += TPP) {
+        const float* r0 = &ss[ci][py][0];
+        const float* r1 = &ss[ci][py + 1][0];
+        const float* r2 = &ss[ci][py + 2][0];
+        const float* gr = &ghs[co][py * TT];
+        float a0 = r0[0], a1 = r0[1], b0 = r1[0], b1 = r1[1], c0 = r2[0], c1 = r2[1];
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap)
-          acc[k][tap] = fmaf(gvv, ss[ci][py + tap / 3][px + tap % 3], acc[k][tap]);
+        for (int px = 0; px < TT; ++px) {
+          const float a2 = r0[px + 2], b2 = r1[px + 2], c2 = r2[px + 2];
+          const float gvv = gr[px];
+          acc[k][0] = fmaf(gvv, a0, acc[k][0]);
+          acc[k][1] = fmaf(gvv, a1, acc[k][1]);
+          acc[k][2] = fmaf(gvv, a2, acc[k][2]);
+          acc[k][3] = fmaf(gvv, b0, acc[k][3]);
+          acc[k][4] = fmaf(gvv, b1, acc[k][4]);
+          acc[k][5] = fmaf(gvv, b2, acc[k][5]);
+          acc[k][6] = fmaf(gvv, c0, acc[k][6]);
+          acc[k][7] = fmaf(gvv, c1, acc[k][7]);
+          acc[k][8] = fmaf(gvv, c2, acc[k][8]);
+          a0 = a1; a1 = a2; b0 = b1; b1 = b2; c0 = c1; c1 = c2;
+        }
       }
     }
   }
