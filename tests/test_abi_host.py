@@ -182,3 +182,33 @@ def test_backward_rejects_rgb_input(evs):
                         ctypes.c_void_p(16), arr, None, None, ctypes.c_void_p(16), 1 << 20, None)
     assert st == 2
     assert b"evs_logdiff" in L.evs_last_error()
+
+
+@pytest.mark.parametrize("hidden,theta,leak,N,T,H,W,code", [
+    (32, 0.5, 0.9, 1, 4, 4, 4, 2),        # only width 16 is compiled
+    (16, 0.0, 0.9, 1, 4, 4, 4, 1),        # theta must be positive
+    (16, 0.5, 1.5, 1, 4, 4, 4, 1),        # leak outside [0, 1]
+    (16, 0.5, 0.9, 0, 4, 4, 4, 1),        # empty batch
+    (16, 0.5, 0.9, 1, 0, 4, 4, 1),        # empty clip
+    (16, 0.5, 0.9, 1, 4, 0, 4, 1),
+])
+def test_tnet_rejects_bad_arguments_before_launch(evs, hidden, theta, leak, N, T, H, W, code):
+    """The temporal EvSNet entry point validates its arguments on the host and
+    touches no pointer when they are bad (dummy addresses suffice)."""
+    net = evs.TNet(hidden=hidden, theta=theta, leak=leak).c()
+    st = evs.lib().evs_tnet_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.c_void_p(16), N, T, H, W,
+                                    ctypes.c_void_p(16), None, None)
+    assert st == code
+    assert evs.lib().evs_last_error()
+
+
+def test_tnet_rejects_null_pointers(evs):
+    net = evs.TNet().c()
+    L = evs.lib()
+    assert L.evs_tnet_forward(ctypes.byref(net), None, ctypes.c_void_p(16), 1, 4, 4, 4, ctypes.c_void_p(16),
+                              None, None) == 1
+    assert L.evs_tnet_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 4, 4, 4, None,
+                              None, None) == 1
+    assert L.evs_tnet_forward(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 4, 4, 4, ctypes.c_void_p(16),
+                              None, None) == 1
+    assert L.evs_tnet_weight_floats(ctypes.byref(net)) == 16 * 7 + 16 + 6 * (16 * 16 * 7 + 16) + 16 + 1
