@@ -337,7 +337,10 @@ def tnet_form(torch, evs, x, args):
             "frames": T, "ms": round(ms, 3), "value": round(px_frames / PX720 / (ms / 1e3), 1),
             "unit": "720p event-frames/s", "alg_flops_per_px_frame": TNET_FLOPS_PX,
             "tflops": round(tflops, 2), "mfma_frac": round(tflops / BF16_MFMA_PEAK, 4),
-            "spikes_per_px_frame": round(float(S.abs().sum()) / px_frames, 4)}
+            "spikes_per_px_frame": round(float(S.abs().sum()) / px_frames, 4),
+            "paper_context": "the paper reports 22.85 ms per EvSNet inference on an RTX 4090 (TensorRT), "
+                             "unit not stated; read as one 360p event frame it is about 11 720p "
+                             "event-frames/s; other hardware and precision, context only"}
 
 
 def attainable_peaks(torch, dev):
