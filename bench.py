@@ -405,7 +405,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1000, help="clip length of the headline workload")
-    ap.add_argument("--forms", default="fp32,compact,w32,prologue,tnet,train,batched")
+    ap.add_argument("--forms", default="fp32,compact,bf16,w32,prologue,tnet,train,batched")
     ap.add_argument("--cpu-frames", type=int, default=16)
     ap.add_argument("--batch-window", type=int, default=200, help="frames per window of the batched form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -517,6 +517,28 @@ def main():
                                       "hbm_gbs": round(cbytes / (cms / 1e3) / 1e9, 1),
                                       "hbm_frac": round(cbytes / (cms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"fp32 3-16-16-2: {ms_per_step:.2f} ms/step, {value:.0f} fps, {achieved:.1f} TFLOP/s")
+
+    # ------------------------------------------------------------ headline net in BF16
+    if "bf16" in forms:
+        nb = evs.Net(chans, theta=wl.theta, leak=wl.leak, precision="bf16")
+        pb = evs.pack_weights(nb, [torch.from_numpy(w).to(dev) for w in ws])
+        for _ in range(args.warmup):
+            evs.forward(nb, pb, x, out=out)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(3, args.steps // 2)):
+            tm = Timer(torch)
+            with tm:
+                evs.forward(nb, pb, x, out=out)
+            ts.append(tm)
+        torch.cuda.synchronize()
+        ms = float(np.mean([t.ms() for t in ts]))
+        tf = conv_flops_per_px(chans) * px_frames / (ms / 1e3) / 1e12
+        rec["forms"]["bf16"] = {
+            "value": round(px_frames / PX720 / (ms / 1e3), 1), "unit": "720p event-frames/s",
+            "ms": round(ms, 3), "tflops": round(tf, 2), "mfma_frac": round(tf / mfma_peak(chans, "bf16"), 4),
+            "workload": "same clip and net (3->16->16->2), BF16 operands, FP32 membrane/compare/reset"}
+        log(f"bf16 3-16-16-2: {ms:.2f} ms, {px_frames / PX720 / (ms / 1e3):.0f} fps")
 
     # ------------------------------------------------------------ precision form 3->32->2
     if "w32" in forms:

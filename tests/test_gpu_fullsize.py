@@ -79,7 +79,8 @@ def _window_check(x, ws, h, y0, x0, channels, theta, leak, qws=None, quant=False
     return worst, worst_q, outside
 
 
-@pytest.mark.parametrize("channels,prec", [((3, 16, 16, 2), "fp32"), ((3, 32, 2), "bf16"), ((3, 32, 2), "fp32")])
+@pytest.mark.parametrize("channels,prec", [((3, 16, 16, 2), "fp32"), ((3, 16, 16, 2), "bf16"), ((3, 32, 2), "bf16"),
+                                          ((3, 32, 2), "fp32")])
 def test_fullsize_720p_1000_frames(clip720, channels, prec):
     import paper_2508_18071_amd as evs
     import synth
