@@ -41,8 +41,9 @@ def mfma_peak(channels, prec):
     that reads spikes on the fp16 pipe (same rate as bf16) with each weight
     split into two fp16 parts (half the rate); their first conv runs on the
     bf16 pipe with x and W both split into three parts, six part products
-    kept (a sixth of the rate) for 3 -> 16 nets, and on the f32 pipe
-    otherwise.  Harmonic mean over the layers' flops."""
+    kept (a sixth of the rate) when x has three channels and a hidden layer
+    follows, and on the f32 pipe otherwise.  Harmonic mean over the layers'
+    flops."""
     layers = list(zip(channels[:-1], channels[1:]))
     t = fl = 0.0
     for l, (ci, co) in enumerate(layers):
@@ -50,7 +51,7 @@ def mfma_peak(channels, prec):
         if prec == "bf16":
             peak = BF16_MFMA_PEAK
         elif l == 0:
-            split_l1 = ci == 3 and len(layers) >= 2 and co == 16
+            split_l1 = ci == 3 and len(layers) >= 2
             peak = BF16_MFMA_PEAK / 6 if split_l1 else FP32_MFMA_PEAK
         else:
             peak = BF16_MFMA_PEAK / 2

@@ -110,11 +110,11 @@ struct Cfg {
   // x planes plus one all-zero plane read by the padded K slots of layer 1;
   // FP32 nets with hidden layers fill them by direct global -> LDS loads of
   // 64-pixel chunks into two buffers (frame t+1 lands while t is read)
-  // FP32 nets with three input channels and 16 hidden channels run layer 1
+  // FP32 nets with three input channels (16 or 32 hidden channels) run layer 1
   // on the bf16 pipe as well: each staged x value is split into three bf16
   // parts (x = xh + xm + xl exactly) stored as per-pixel records of the three
   // channels, one record plane per part (register staging, no raw x in LDS)
-  static constexpr bool XSPLIT = !BF16 && CIN == 3 && CH == 16 && NH >= 1 && !RELAX && !LOGX;
+  static constexpr bool XSPLIT = !BF16 && CIN == 3 && NH >= 1 && !RELAX && !LOGX;
   static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX && !LOGX && !XSPLIT;
   static constexpr int XPP = cdiv(NPIX, NT);         // canvas pixels staged per thread (XSPLIT)
   // 16-channel spike convs run block by block with all weight fragments in
@@ -289,7 +289,7 @@ struct Layout {
   static constexpr int WL = SP + C::SP_BYTES;                   // VALU output weights [9][CI][2] f32
   static constexpr int FR1 = WL + align16(C::WL_FLOATS * 4);    // layer-1 A fragments
   static constexpr int FR1_BYTES =
-      C::NH >= 1 ? (C::XSPLIT ? C::NFR1 * 64 * 16 : C::KS1 * C::MB * 64 * (C::BF16 ? 16 : 4)) : 0;
+      C::NH >= 1 ? (C::XSPLIT ? C::NFR1 * C::MB * 64 * 16 : C::KS1 * C::MB * 64 * (C::BF16 ? 16 : 4)) : 0;
   static constexpr int FR2 = FR1 + FR1_BYTES;                   // layer-2 A fragments
   static constexpr int FR2_BYTES =
       C::NH >= 2 ? (C::S16 ? C::KB * C::NSP * C::MB * 64 * 16 : 9 * (C::CH / 16) * C::MB * 64 * 16) : 0;
@@ -343,10 +343,10 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
   }
   if constexpr (C::XSPLIT) {
     const int c1 = na.ch[1];
-    // entry (f, lane): row co = lane%16, lane group g = lane/16
-    for (int e = threadIdx.x; e < C::NFR1 * 64; e += C::NT) {
-      const int lane = e % 64, f = e / 64;
-      const int co = lane & 15, g = lane >> 4;
+    // entry (m, f, lane): row co = 16m + lane%16, lane group g = lane/16
+    for (int e = threadIdx.x; e < C::MB * C::NFR1 * 64; e += C::NT) {
+      const int lane = e % 64, f = (e / 64) % C::NFR1, m = e / (64 * C::NFR1);
+      const int co = 16 * m + (lane & 15), g = lane >> 4;
       int p, q;
       split_frag(f, p, q);
       unsigned wd[4];
@@ -901,9 +901,11 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         // while block i multiplies
         const char* const xr = lds + Lo::XS;
         const u4* const fr = reinterpret_cast<const u4*>(lds + Lo::FR1) + lane;
-        u4 af[C::NFR1];
+        u4 af[C::MB][C::NFR1];
 #pragma unroll
-        for (int f = 0; f < C::NFR1; ++f) af[f] = fr[f * 64];
+        for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+          for (int f = 0; f < C::NFR1; ++f) af[m][f] = fr[(m * C::NFR1 + f) * 64];
         u4 bq[2][4];
         auto ldb = [&](int i, int sl) __attribute__((always_inline)) {
 #pragma unroll
@@ -919,16 +921,19 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           if (i < C::NB1) {
             if (i + 1 < C::NB1) ldb(i + 1, (i + 1) & 1);
             const u4 (&b)[4] = bq[i & 1];
-            f4& h = st1[i][0];
-            h = mfma_bf16(af[0], b[0], h);
-            h = mfma_bf16(af[4], b[0], h);
-            h = mfma_bf16(af[7], b[0], h);
-            h = mfma_bf16(af[1], b[1], h);
-            h = mfma_bf16(af[5], b[1], h);
-            h = mfma_bf16(af[8], b[1], h);
-            h = mfma_bf16(af[2], b[2], h);
-            h = mfma_bf16(af[6], b[2], h);
-            h = mfma_bf16(af[3], b[3], h);
+#pragma unroll
+            for (int m = 0; m < C::MB; ++m) {
+              f4& h = st1[i][m];
+              h = mfma_bf16(af[m][0], b[0], h);
+              h = mfma_bf16(af[m][4], b[0], h);
+              h = mfma_bf16(af[m][7], b[0], h);
+              h = mfma_bf16(af[m][1], b[1], h);
+              h = mfma_bf16(af[m][5], b[1], h);
+              h = mfma_bf16(af[m][8], b[1], h);
+              h = mfma_bf16(af[m][2], b[2], h);
+              h = mfma_bf16(af[m][6], b[2], h);
+              h = mfma_bf16(af[m][3], b[3], h);
+            }
           }
           if (i > 0)
             hidden_epilogue<C>(st1[i - 1], lds, 0, e1[i - 1], (vm1 >> (i - 1)) & 1u, g, theta, alpha, relaxed, trace_t,
