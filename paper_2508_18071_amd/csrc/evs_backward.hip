@@ -203,6 +203,126 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
   }
 }
 
+// Weight gradient of a 16 -> 16 conv fed by hard spikes, on the bf16 matrix
+// pipe.  Per tap, dW[co][ci] = sum_p g_h[co][p] s[ci][p + tap] is a 16 x 16
+// product over pixels: g_h as the A operand (rows co), the shifted spikes as
+// B (columns ci), 32 pixels per MFMA.  Spikes are exact in bf16 and g_h is
+// split exactly into three bf16 parts (h = bf16(g), m = bf16(g - h),
+// l = g - h - m), so every product is exact and the sums accumulate in FP32.
+// Per frame the tile's g_h parts and its spikes, in three copies shifted by
+// the tap column (16-byte operand reads), are staged in LDS from registers
+// that were loaded during the previous frame's products; wave w takes pixel
+// rows 4w .. 4w+3, and the four waves' partials are added in wave order at
+// the end (fixed association: reproducible).
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+constexpr int kGspBytes = 3 * 16 * TT * TT * 2;          // g_h parts [part][co][pixel]
+constexpr int kSsbBytes = 3 * 16 * (TT + 2) * TT * 2;    // spikes [dx][ci][row][col]
+constexpr int kSsPerThread = (16 * (TT + 2) * (TT + 2) + NTH - 1) / NTH;
+__device__ inline uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+
+__global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+                                                 int W, int tiles_x, const float* __restrict__ hseg, int sumc,
+                                                 int choff_in, float theta, float* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) char lds[kGspBytes + kSsbBytes];
+  uint16_t* const gsp = reinterpret_cast<uint16_t*>(lds);
+  uint16_t* const ssb = reinterpret_cast<uint16_t*>(lds + kGspBytes);
+  const int tile = blockIdx.x, n = blockIdx.y;
+  const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
+  const int HW = H * W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  // staging: this thread's g_h pixel (all 16 channels) and spike-tile entries
+  const int gy = ty0 + threadIdx.x / TT, gx = tx0 + threadIdx.x % TT;
+  const bool gin = gy < H && gx < W;
+  float gr[16], hr[kSsPerThread];
+  auto fetch = [&](int t) __attribute__((always_inline)) {
+    const float* gf = gh + ((size_t)n * len + t) * Cout * HW + (size_t)gy * W + gx;
+#pragma unroll
+    for (int co = 0; co < 16; ++co) gr[co] = (co < Cout && gin) ? gf[(size_t)co * HW] : 0.f;
+#pragma unroll
+    for (int k = 0; k < kSsPerThread; ++k) {
+      const int e = threadIdx.x + NTH * k;
+      const int ci = e / ((TT + 2) * (TT + 2)), rr = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+      const int y = ty0 - 1 + rr, xx = tx0 - 1 + cc;
+      const bool in = e < 16 * (TT + 2) * (TT + 2) && ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W;
+      // out-of-image entries hold a value whose spike is 0
+      hr[k] = in ? hseg[(((size_t)n * len + t) * sumc + choff_in + ci) * HW + (size_t)y * W + xx] : 0.f;
+    }
+  };
+  f4 acc[9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) acc[tap] = f4{0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  for (int t = 0; t < len; ++t) {
+    __syncthreads();                                   // the previous frame's operands are consumed
+#pragma unroll
+    for (int co = 0; co < 16; ++co) {
+      const float v = gr[co];
+      const float h = (float)(__bf16)v, r = v - h, m = (float)(__bf16)r;
+      gsp[(0 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(h);
+      gsp[(1 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(m);
+      gsp[(2 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(r - m);
+    }
+#pragma unroll
+    for (int k = 0; k < kSsPerThread; ++k) {
+      const int e = threadIdx.x + NTH * k;
+      if (e < 16 * (TT + 2) * (TT + 2)) {
+        const int ci = e / ((TT + 2) * (TT + 2)), rr = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+        const uint16_t b = bf16_bits(spike_of(hr[k], theta, 0.f, 0));
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const int c2 = cc - dx;
+          if (c2 >= 0 && c2 < TT) ssb[((dx * 16 + ci) * (TT + 2) + rr) * TT + c2] = b;
+        }
+      }
+    }
+    if (t + 1 < len) fetch(t + 1);                     // in flight while this frame multiplies
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      // k-step: pixel rows 4 wave + 2q, +1; lane group g takes 8 pixels of
+      // row 4 wave + 2q + g/2 starting at column 8 (g & 1)
+      const int row = 4 * wave + 2 * q + (g >> 1), c0 = 8 * (g & 1);
+      u4 a[3];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) a[b] = *reinterpret_cast<const u4*>(gsp + (b * 16 + j) * TT * TT + row * TT + c0);
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+        const u4 bv = *reinterpret_cast<const u4*>(ssb + ((dx * 16 + j) * (TT + 2) + row + dy) * TT + c0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[b]), __builtin_bit_cast(bf8, bv),
+                                                            acc[tap], 0, 0, 0);
+      }
+    }
+  }
+  // lane (ci = j, g) holds dW[co = 4g + r][ci][tap] of its wave's pixels
+  __syncthreads();
+  float* rb = reinterpret_cast<float*>(lds);             // waves 1..3: [wave - 1][lane][36]
+  if (wave > 0) {
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rb[((wave - 1) * 64 + lane) * 36 + tap * 4 + r] = acc[tap][r];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    float* out = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 256 * 9;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[tap][r];
+#pragma unroll
+        for (int w2 = 0; w2 < 3; ++w2) v += rb[(w2 * 64 + lane) * 36 + tap * 4 + r];
+        out[((4 * g + r) * 16 + j) * 9 + tap] = v;
+      }
+  }
+}
+
 // acc[e] += sum_b partial[b][e] (e over padded pairs x 9).  A workgroup
 // takes 32 consecutive e; each of its 8 b-lanes sums the partials b = lane,
 // lane + 8, ... in order, then the 8 lane sums are added in lane order: a
@@ -247,6 +367,11 @@ template <int CINP, int COUTP>
 void launch_dw(dim3 g, hipStream_t st, const float* gh, int Cout, int Cin, int len, int H, int W, int tx,
                const float* x, long long xns, int bfx, const float* hseg, int sumc, int choff_in, float theta,
                float alpha, int relaxed, float* partial) {
+  if (CINP == 16 && COUTP == 16 && hseg && !relaxed) {   // hard spikes in: bf16 matrix pipe
+    hipLaunchKernelGGL(k_dw_mfma, g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, hseg, sumc, choff_in, theta,
+                       partial);
+    return;
+  }
   hipLaunchKernelGGL((k_dw<CINP, COUTP>), g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, x, xns, bfx, hseg,
                      sumc, choff_in, theta, alpha, relaxed, partial);
 }
