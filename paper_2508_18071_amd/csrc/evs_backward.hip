@@ -28,6 +28,10 @@ constexpr int NTH = TT * TT;      // threads per workgroup
 inline int pad_in(int c) { return c <= 4 ? 4 : (c <= 16 ? 16 : 32); }
 inline int pad_out(int c) { return c <= 2 ? 2 : (c <= 16 ? 16 : 32); }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
 __device__ inline float wq(const float* w, int idx, bool bf) {
   const float v = w[idx];
   return bf ? round_bf16(v) : v;
@@ -59,48 +63,268 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ hseg,
 }
 
 // ---------------------------------------------------------------- conv transpose
-// out[n][t][ci][y][x] = sum_{co,tap} W[co][ci][tap] * gh[n][t][co][y-dy][x-dx]
-template <int CINP, int COUTP>
-__global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int Cout, int Cin, int len,
-                                               int H, int W, int tiles_x, const float* __restrict__ w, int bf,
+// A layer's weights in [tap][co][ci] order, zero-padded to COUTP x CINP and
+// rounded as the forward used them: one (tap, co) row of CINP weights is a
+// single uniform (scalar-register) load in the conv-transpose kernel.
+__global__ void k_pack_wT(const float* __restrict__ w, int Cout, int Cin, int CINP, int COUTP, int bf,
+                          float* __restrict__ wT) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= 9 * COUTP * CINP) return;
+  const int ci = e % CINP, co = (e / CINP) % COUTP, tap = e / (CINP * COUTP);
+  wT[e] = (co < Cout && ci < Cin) ? wq(w, (co * Cin + ci) * 9 + tap, bf) : 0.f;
+}
+
+// G[n][t][ci][y][x] = sum_{co,tap} W[co][ci][tap] * gh[n][t][co][y-dy][x-dx]
+// One workgroup per (tile, clip) walks the segment's frames from the last to
+// the first, the next frame's haloed g_h tile loading into registers while
+// the current one is used from LDS.  The weights are uniform operands (no
+// LDS traffic for them).  With ADJ, G never leaves registers: it drives the
+// adjoint scan (Eq. 4) of the layer below at the same pixel,
+//     g_h = (G - theta g_v) psi(h) + g_v,   g_v <- leak g_h,
+// with g_v held in registers for the whole segment, and that layer's g_h is
+// written to out [n][t][Cin][H][W]; without ADJ G itself is written (grad_x).
+// The arithmetic and its order are those of a separate conv-transpose pass
+// followed by a separate scan.
+template <int CINP, int COUTP, bool ADJ>
+__global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+                                               int W, int tiles_x, const float* __restrict__ wT,
                                                float* __restrict__ out, long long out_nstride,
-                                               long long out_tstride) {
+                                               long long out_tstride, const float* __restrict__ hseg, int sumc,
+                                               int choff, float* __restrict__ gv, float theta, float leak,
+                                               float alpha, int surr, int detach) {
+  constexpr int kTile = COUTP * (TT + 2) * (TT + 2);
+  constexpr int kStage = (kTile + NTH - 1) / NTH;
   __shared__ float ghs[COUTP][TT + 2][TT + 2];
-  __shared__ __attribute__((aligned(16))) float wls[9][COUTP][CINP];
-  const int tile = blockIdx.x, t = blockIdx.y, n = blockIdx.z;
+  const int tile = blockIdx.x, n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
   const int HW = H * W;
-  const float* g = gh + ((size_t)n * len + t) * Cout * HW;
-  for (int e = threadIdx.x; e < COUTP * (TT + 2) * (TT + 2); e += NTH) {
-    const int co = e / ((TT + 2) * (TT + 2)), r = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
-    const int y = ty0 - 1 + r, x = tx0 - 1 + cc;
-    ghs[co][r][cc] = (co < Cout && y >= 0 && y < H && x >= 0 && x < W) ? g[(size_t)co * HW + y * W + x] : 0.f;
-  }
-  for (int e = threadIdx.x; e < 9 * COUTP * CINP; e += NTH) {
-    const int ci = e % CINP, co = (e / CINP) % COUTP, tap = e / (CINP * COUTP);
-    wls[tap][co][ci] = (co < Cout && ci < Cin) ? wq(w, (co * Cin + ci) * 9 + tap, bf) : 0.f;
-  }
-  __syncthreads();
   const int ty = threadIdx.x / TT, tx = threadIdx.x % TT;
-  float acc[CINP];
-#pragma unroll
-  for (int ci = 0; ci < CINP; ++ci) acc[ci] = 0.f;
-  for (int co = 0; co < Cout; ++co) {
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      const float gv = ghs[co][ty + 1 - dy][tx + 1 - dx];
-#pragma unroll
-      for (int ci = 0; ci < CINP; ++ci) acc[ci] = fmaf(wls[tap][co][ci], gv, acc[ci]);
-    }
-  }
   const int y = ty0 + ty, x = tx0 + tx;
-  if (y < H && x < W) {
-    float* o = out + (size_t)n * out_nstride + (size_t)t * out_tstride + (size_t)y * W + x;
+  const bool own = y < H && x < W;
+  float pre[kStage];
+  auto fetch = [&](int t) __attribute__((always_inline)) {
+    const float* g = gh + ((size_t)n * len + t) * Cout * HW;
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int e = threadIdx.x + NTH * k;
+      const int co = e / ((TT + 2) * (TT + 2)), r = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+      const int yy = ty0 - 1 + r, xx = tx0 - 1 + cc;
+      pre[k] = (e < kTile && co < Cout && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                   ? g[(size_t)co * HW + (size_t)yy * W + xx] : 0.f;
+    }
+  };
+  float g_v[CINP];
+  if constexpr (ADJ) {
 #pragma unroll
     for (int ci = 0; ci < CINP; ++ci)
-      if (ci < Cin) o[(size_t)ci * HW] = acc[ci];
+      g_v[ci] = (own && ci < Cin) ? gv[((size_t)n * sumc + choff + ci) * HW + (size_t)y * W + x] : 0.f;
   }
+  fetch(len - 1);
+  for (int t = len - 1; t >= 0; --t) {
+    __syncthreads();                                   // the previous frame's tile is consumed
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int e = threadIdx.x + NTH * k;
+      if (e < kTile) (&ghs[0][0][0])[e] = pre[k];
+    }
+    float hv[CINP];
+    if constexpr (ADJ) {
+      const float* hp = hseg + (((size_t)n * len + t) * sumc + choff) * HW + (size_t)y * W + x;
+#pragma unroll
+      for (int ci = 0; ci < CINP; ++ci) hv[ci] = (own && ci < Cin) ? hp[(size_t)ci * HW] : 0.f;
+    }
+    if (t > 0) fetch(t - 1);                           // in flight while this frame is used
+    __syncthreads();
+    float acc[CINP];
+#pragma unroll
+    for (int ci = 0; ci < CINP; ++ci) acc[ci] = 0.f;
+#pragma unroll 2
+    for (int co = 0; co < Cout; ++co) {
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const float g = ghs[co][ty + 1 - dy][tx + 1 - dx];
+        const float* wr = wT + (tap * COUTP + co) * CINP;
+#pragma unroll
+        for (int ci = 0; ci < CINP; ++ci) acc[ci] = fmaf(wr[ci], g, acc[ci]);
+      }
+    }
+    if (own) {
+      if constexpr (ADJ) {
+        float* o = out + (((size_t)n * len + t) * Cin) * HW + (size_t)y * W + x;
+#pragma unroll
+        for (int ci = 0; ci < CINP; ++ci) {
+          if (ci < Cin) {
+            const float psi = surrogate(hv[ci], theta, alpha, surr);
+            const float g = detach ? fmaf(acc[ci], psi, g_v[ci]) : fmaf(fmaf(-theta, g_v[ci], acc[ci]), psi, g_v[ci]);
+            o[(size_t)ci * HW] = g;
+            g_v[ci] = leak * g;
+          }
+        }
+      } else {
+        float* o = out + (size_t)n * out_nstride + (size_t)t * out_tstride + (size_t)y * W + x;
+#pragma unroll
+        for (int ci = 0; ci < CINP; ++ci)
+          if (ci < Cin) o[(size_t)ci * HW] = acc[ci];
+      }
+    }
+  }
+  if constexpr (ADJ) {
+    if (own) {
+#pragma unroll
+      for (int ci = 0; ci < CINP; ++ci)
+        if (ci < Cin) gv[((size_t)n * sumc + choff + ci) * HW + (size_t)y * W + x] = g_v[ci];
+    }
+  }
+}
+
+// The same conv-transpose + adjoint for a layer below with 5..16 channels,
+// on the FP32 matrix pipe.  Per 16-pixel tile row, G[ci][pixel] is a 16 x 16
+// product over K = (tap, co): v_mfma_f32_16x16x4_f32 with the weights as the
+// A operand (lane (ci, k) holds W[co][ci][tap], staged in LDS once per
+// workgroup) and the haloed g_h tile as B, read from LDS at an immediate
+// offset from a per-lane base (K is ordered tap-major, co in lane
+// groups of 4; output widths below 4 are padded with zero weights).  Lane
+// (pixel j, group g) receives G for channels 4g..4g+3 of pixel j and runs the
+// adjoint scan on them; wave w takes tile rows 4w..4w+3.  The g_h planes are
+// 336 floats apart (16 banks mod 64), so the four lane groups of a read hit
+// distinct banks.  FP32 products and sums, in the matrix pipe's own order.
+template <int COUTP>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(COUTP > 16 ? 2 : 3))) void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+                                                    int W, int tiles_x, const float* __restrict__ wT,
+                                                    float* __restrict__ out, const float* __restrict__ hseg,
+                                                    int sumc, int choff, float* __restrict__ gv, float theta,
+                                                    float leak, float alpha, int surr, int detach) {
+  constexpr int E = TT + 2;                            // haloed tile edge
+  constexpr int PS = (E * E + 47) / 64 * 64 + 16;      // plane stride, 16 mod 64
+  constexpr int COG = COUTP < 4 ? 4 : COUTP;           // co slots per tap
+  constexpr int KS = 9 * COG / 4;                      // k-steps
+  static_assert(COG % 4 == 0, "co slots come in lane groups of 4");
+  static_assert(E * E > NTH && E * E <= 2 * NTH, "a tile plane is staged in two passes");
+  __shared__ float ghs[COUTP * PS];
+  const int tile = blockIdx.x, n = blockIdx.y;
+  const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
+  const int HW = H * W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  // weights: k-step s, lane group g -> tap s / (COG/4), co 4 (s % (COG/4)) + g;
+  // held in LDS as [s / 4][lane][s % 4], one 16-byte read per lane for four
+  // k-steps (the A operand would otherwise take 36-72 registers)
+  constexpr int KS4 = (KS + 3) / 4;
+  __shared__ f4 wl[KS4 * 64];
+  for (int idx = threadIdx.x; idx < KS4 * 4 * 64; idx += NTH) {
+    const int s = idx / 64, l = idx % 64;
+    const int tap = s / (COG / 4), co = 4 * (s % (COG / 4)) + l / 16;
+    wl[(s / 4) * 64 + l][s % 4] = (s < KS && co < COUTP) ? wT[(tap * COUTP + co) * 16 + l % 16] : 0.f;
+  }
+  // B read of (row r, k-step s): base + r E + imm(s); planes past COUTP
+  // (zero weights) read plane g % COUTP, whose values are finite
+  const int plane = COUTP < 4 ? g % COUTP : g;
+  const float* const bbase = ghs + plane * PS + 4 * wave * E + j;
+  // this lane's 16 neurons: rows 4 wave + r (uniform in the wave), column j,
+  // channels 4g + i.  Their [ch][H][W] planes are read and written through
+  // buffer resources bounded to the layer's Cin planes: voff[i] + r W 4 is
+  // the byte offset of neuron (r, i); a lane past the image's right edge has
+  // offsets of 2^31 and up, and one past Cin offsets beyond the last plane,
+  // so their loads return 0 and their stores are dropped.  Rows past the
+  // bottom edge are skipped by a branch that is uniform in the wave.
+  constexpr unsigned kDead = 0x80000000u;
+  const int x = tx0 + j, y0 = ty0 + 4 * wave;
+  const unsigned bytes = (unsigned)Cin * (unsigned)HW * 4u;
+  unsigned voff[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    voff[i] = x < W ? 4u * ((unsigned)(4 * g + i) * (unsigned)HW + (unsigned)(y0 * W + x)) : kDead;
+  // staging: this thread loads haloed-tile entries q = tid and tid + 256 of
+  // every g_h plane; entries outside the image read 0 the same way
+  unsigned qoff[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int q = threadIdx.x + NTH * k;
+    const int yy = ty0 - 1 + q / E, xx = tx0 - 1 + q % E;
+    qoff[k] = (q < E * E && yy >= 0 && yy < H && xx >= 0 && xx < W) ? 4u * (unsigned)(yy * W + xx) : kDead;
+  }
+  const __amdgpu_buffer_rsrc_t rv =
+      __builtin_amdgcn_make_buffer_rsrc(gv + ((size_t)n * sumc + choff) * HW, (short)0, (int)bytes, 0x00020000);
+  float g_v[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      g_v[r][i] = y0 + r < H ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, voff[i], r * W * 4, 0))
+                             : 0.f;
+  for (int t = len - 1; t >= 0; --t) {
+    __syncthreads();                                   // the previous frame's tile is consumed
+    const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)((unsigned)Cout * (unsigned)HW * 4u), 0x00020000);
+    // every load of the frame is issued before the first LDS store; planes
+    // past Cout fall outside the resource and read 0
+    float st0[COUTP], st1[COUTP];
+#pragma unroll
+    for (int co = 0; co < COUTP; ++co)
+      st0[co] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, qoff[0] + 4u * co * HW, 0, 0));
+    if (threadIdx.x < E * E - NTH) {
+#pragma unroll
+      for (int co = 0; co < COUTP; ++co)
+        st1[co] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, qoff[1] + 4u * co * HW, 0, 0));
+    }
+#pragma unroll
+    for (int co = 0; co < COUTP; ++co) ghs[co * PS + threadIdx.x] = st0[co];
+    if (threadIdx.x < E * E - NTH) {
+#pragma unroll
+      for (int co = 0; co < COUTP; ++co) ghs[co * PS + threadIdx.x + NTH] = st1[co];
+    }
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(hseg + (((size_t)n * len + t) * sumc + choff) * HW), (short)0, (int)bytes, 0x00020000);
+    float hv[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        hv[r][i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff[i], r * W * 4, 0));
+    f4 acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s4 = 0; s4 < KS4; ++s4) {
+      const f4 w = wl[s4 * 64 + lane];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = 4 * s4 + u;
+        if (s < KS) {
+          const int tap = s / (COG / 4), cq = s % (COG / 4);
+          const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+          const int imm = (COUTP < 4 ? 0 : 4 * cq * PS) + (1 - dy) * E + (1 - dx);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[u], bbase[r * E + imm], acc[r], 0, 0, 0);
+        }
+      }
+    }
+    const __amdgpu_buffer_rsrc_t ro =
+        __builtin_amdgcn_make_buffer_rsrc(out + ((size_t)n * len + t) * Cin * HW, (short)0, (int)bytes, 0x00020000);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (y0 + r < H) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float Gv = acc[r][i];
+          const float psi = surrogate(hv[r][i], theta, alpha, surr);
+          const float gn = detach ? fmaf(Gv, psi, g_v[r][i]) : fmaf(fmaf(-theta, g_v[r][i], Gv), psi, g_v[r][i]);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, gn), ro, voff[i], r * W * 4, 0);
+          g_v[r][i] = leak * gn;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (y0 + r < H) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, g_v[r][i]), rv, voff[i], r * W * 4, 0);
+    }
 }
 
 // ---------------------------------------------------------------- weight gradient
@@ -214,9 +438,6 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
 // that were loaded during the previous frame's products; wave w takes pixel
 // rows 4w .. 4w+3, and the four waves' partials are added in wave order at
 // the end (fixed association: reproducible).
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef unsigned u4 __attribute__((ext_vector_type(4)));
 constexpr int kGspBytes = 3 * 16 * TT * TT * 2;          // g_h parts [part][co][pixel]
 constexpr int kSsbBytes = 3 * 16 * (TT + 2) * TT * 2;    // spikes [dx][ci][row][col]
 constexpr int kSsPerThread = (16 * (TT + 2) * (TT + 2) + NTH - 1) / NTH;
@@ -357,11 +578,24 @@ __global__ void k_dw_out(const float* __restrict__ acc, int Cout, int Cin, int C
   gw[e] = acc[(co * CINP + ci) * 9 + tap];
 }
 
+struct ConvTArgs {
+  const float* gh; int Cout, Cin, len, H, W, tiles_x; const float* wT;
+  float* out; long long ons, ots;
+  const float* hseg; int sumc, choff; float* gv; float theta, leak, alpha; int surr, detach;
+};
 template <int CINP, int COUTP>
-void launch_convT(dim3 g, hipStream_t st, const float* gh, int Cout, int Cin, int len, int H, int W, int tx,
-                  const float* w, int bf, float* out, long long ons, long long ots) {
-  hipLaunchKernelGGL((k_convT<CINP, COUTP>), g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, w, bf, out, ons,
-                     ots);
+void launch_convT(dim3 g, hipStream_t st, bool adj, const ConvTArgs& a) {
+  if (adj && CINP == 16)
+    hipLaunchKernelGGL((k_convT_mfma<COUTP>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W, a.tiles_x,
+                       a.wT, a.out, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha, a.surr, a.detach);
+  else if (adj)
+    hipLaunchKernelGGL((k_convT<CINP, COUTP, true>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
+                       a.tiles_x, a.wT, a.out, a.ons, a.ots, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha,
+                       a.surr, a.detach);
+  else
+    hipLaunchKernelGGL((k_convT<CINP, COUTP, false>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
+                       a.tiles_x, a.wT, a.out, a.ons, a.ots, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha,
+                       a.surr, a.detach);
 }
 template <int CINP, int COUTP>
 void launch_dw(dim3 g, hipStream_t st, const float* gh, int Cout, int Cin, int len, int H, int W, int tx,
@@ -390,7 +624,7 @@ void launch_dw(dim3 g, hipStream_t st, const float* gh, int Cout, int Cin, int l
   } while (0)
 
 struct BwdLayout {
-  size_t hseg, gv, gh, ga, gb, partial, acc, total;
+  size_t hseg, gv, gh, gh2, partial, acc, wT, total;
   int k, nseg, cmax, tiles_x, tiles_y;
 };
 
@@ -415,10 +649,10 @@ BwdLayout layout(const evs_net& net, const evs_clip& c, int k) {
   L.hseg = o; o += align256((size_t)c.N * k * sumc * HW * 4);
   L.gv = o; o += align256((size_t)c.N * sumc * HW * 4);
   L.gh = o; o += align256((size_t)c.N * k * cmax * HW * 4);
-  L.ga = o; o += align256((size_t)c.N * k * cmax * HW * 4);
-  L.gb = o; o += align256((size_t)c.N * k * cmax * HW * 4);
+  L.gh2 = o; o += align256((size_t)c.N * k * cmax * HW * 4);
   L.partial = o; o += align256(nblk * emax * 4);
   L.acc = o; o += align256((size_t)accsum * 4);
+  L.wT = o; o += align256((size_t)accsum * 4);
   L.total = o;
   return L;
 }
@@ -450,10 +684,11 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
   char* w8 = reinterpret_cast<char*>(ws);
   float* hseg = reinterpret_cast<float*>(w8 + Lo.hseg);
   float* gv = reinterpret_cast<float*>(w8 + Lo.gv);
-  float* gh = reinterpret_cast<float*>(w8 + Lo.gh);
-  float* Gbuf[2] = {reinterpret_cast<float*>(w8 + Lo.ga), reinterpret_cast<float*>(w8 + Lo.gb)};
+  // g_h of layer l and of the layer below, swapped after each layer
+  float* ghb[2] = {reinterpret_cast<float*>(w8 + Lo.gh), reinterpret_cast<float*>(w8 + Lo.gh2)};
   float* partial = reinterpret_cast<float*>(w8 + Lo.partial);
   float* acc = reinterpret_cast<float*>(w8 + Lo.acc);
+  float* wT = reinterpret_cast<float*>(w8 + Lo.wT);
   const int N = clip.N, T = clip.T, H = clip.H, W = clip.W, L = net.n_layers;
   const long long HW = (long long)H * W;
   const int sumc = real_sum_channels(net);
@@ -468,11 +703,16 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
 
   if ((rc = zero_f32(gv, (size_t)N * sumc * HW, st))) return rc;
   if ((rc = zero_f32(acc, (size_t)accofs[L], st))) return rc;
+  for (int l = 1; l <= L; ++l) {
+    const int CI = pad_in(net.ch[l - 1]), CO = pad_out(net.ch[l]);
+    hipLaunchKernelGGL(k_pack_wT, dim3((9 * CI * CO + 255) / 256), dim3(256), 0, st, wbase + na.wofs[l - 1],
+                       net.ch[l], net.ch[l - 1], CI, CO, bf ? 1 : 0, wT + accofs[l - 1]);
+    EVS_HIP(hipGetLastError());
+  }
   const int tile = choose_tile(net, H, W);
   int th = 0, tw = 0;
   forward_tile_dims(net, tile, &th, &tw);
   if (th == 0) return fail(EVS_EUNSUPPORTED, "backward: no forward kernel for this network");
-  const dim3 gconv((unsigned)(Lo.tiles_x * Lo.tiles_y), 1, (unsigned)N);
 
   for (int s = Lo.nseg - 1; s >= 0; --s) {
     const int t0 = s * k;
@@ -493,17 +733,21 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
     ca.tiles_y = (H + th - 1) / th;
     if ((rc = launch_forward(net, na, ca, tile, st))) return rc;
 
-    // 2-4. layers L..1
-    const float* G = grad_s + (size_t)t0 * cout * HW;
-    long long G_ns = (long long)T * cout * HW, G_ts = (long long)cout * HW;
-    int gsel = 0;
-    for (int l = L; l >= 1; --l) {
-      const int C = net.ch[l], Cin = net.ch[l - 1];
+    // 2-4. layers L..1: the top layer's adjoint scan reads grad_s; each
+    // lower layer's scan runs inside the conv-transpose of the layer above
+    {
+      const int C = net.ch[L];
       const long long tot = (long long)N * C * HW;
       hipLaunchKernelGGL(k_adjoint, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, hseg, sumc,
-                         choff[l - 1], C, len, N, (int)HW, G, G_ns, G_ts, gh, gv, net.theta, net.leak,
-                         net.surr_alpha, net.surrogate, net.detach_reset);
+                         choff[L - 1], C, len, N, (int)HW, grad_s + (size_t)t0 * cout * HW, (long long)T * cout * HW,
+                         (long long)cout * HW, ghb[0], gv, net.theta, net.leak, net.surr_alpha, net.surrogate,
+                         net.detach_reset);
       EVS_HIP(hipGetLastError());
+    }
+    int cur = 0;
+    for (int l = L; l >= 1; --l) {
+      const int C = net.ch[l], Cin = net.ch[l - 1];
+      float* gh = ghb[cur];
       // weight gradient partials for this segment, then fixed-order reduction
       const int CI = pad_in(Cin), CO = pad_out(C);
       const dim3 gdw((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)N);
@@ -520,31 +764,27 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
       hipLaunchKernelGGL(k_dw_reduce, dim3((E + kRedE - 1) / kRedE), dim3(kRedE * kRedB), 0, st, partial,
                          Lo.tiles_x * Lo.tiles_y * N, E, acc + accofs[l - 1]);
       EVS_HIP(hipGetLastError());
-      // gradient for the layer below (or the input)
+      // g_h of the layer below (conv-transpose + its adjoint scan), or grad_x
       if (l >= 2 || grad_x) {
-        float* out;
-        long long ons, ots;
+        ConvTArgs a{};
+        a.gh = gh; a.Cout = C; a.Cin = Cin; a.len = len; a.H = H; a.W = W; a.tiles_x = Lo.tiles_x;
+        a.wT = wT + accofs[l - 1];
+        a.theta = net.theta; a.leak = net.leak; a.alpha = net.surr_alpha; a.surr = net.surrogate;
+        a.detach = net.detach_reset; a.sumc = sumc;
         if (l >= 2) {
-          out = Gbuf[gsel];
-          ons = (long long)len * Cin * HW;
-          ots = (long long)Cin * HW;
+          a.out = ghb[cur ^ 1];
+          a.hseg = hseg; a.choff = choff[l - 2]; a.gv = gv;
         } else {
-          out = grad_x + (size_t)t0 * cin0 * HW;
-          ons = (long long)T * cin0 * HW;
-          ots = (long long)cin0 * HW;
+          a.out = grad_x + (size_t)t0 * cin0 * HW;
+          a.ons = (long long)T * cin0 * HW;
+          a.ots = (long long)cin0 * HW;
         }
-        const dim3 gct((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)len, (unsigned)N);
-        const float* wl = wbase + na.wofs[l - 1];
-#define EVS_CALL_CT(A, B) launch_convT<A, B>(gct, st, gh, C, Cin, len, H, W, Lo.tiles_x, wl, bf ? 1 : 0, out, ons, ots)
+        const dim3 gct((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)N);
+#define EVS_CALL_CT(A, B) launch_convT<A, B>(gct, st, l >= 2, a)
         EVS_DISPATCH_PAD(CI, CO, EVS_CALL_CT);
 #undef EVS_CALL_CT
         EVS_HIP(hipGetLastError());
-        if (l >= 2) {
-          G = out;
-          G_ns = ons;
-          G_ts = ots;
-          gsel ^= 1;
-        }
+        cur ^= 1;
       }
     }
   }
@@ -558,7 +798,6 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
   if (grad_v) {
     if ((rc = copy_f32(grad_v, gv, (size_t)N * sumc * HW, st))) return rc;
   }
-  (void)gconv;
   return EVS_OK;
 }
 
