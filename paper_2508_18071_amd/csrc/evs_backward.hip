@@ -352,29 +352,65 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) acc[k][tap] = 0.f;
   const int sub = TPP > 1 ? threadIdx.x / P : 0;      // row subset of this thread
+  // staging: this thread's entries of the g_h tile and of the haloed input
+  // tile, loaded into registers one frame ahead (all loads of a frame in
+  // flight together, while the previous frame is being multiplied)
+  constexpr int kG = COUTP * TT * TT, kS = CINP * (TT + 2) * (TT + 2);
+  constexpr int kGt = (kG + NTH - 1) / NTH, kSt = (kS + NTH - 1) / NTH;
+  // Loads go through buffer resources bounded to the frame's planes, at
+  // 32-bit byte offsets fixed for the whole segment; entries outside the
+  // image (or past the real channels) get offsets of 2^31 and up, which read
+  // 0 -- and 0 stages as 0 (its spike and its bf16 rounding are 0).
+  constexpr unsigned kDead = 0x80000000u;
+  unsigned goff[kGt], soff[kSt];
+#pragma unroll
+  for (int k = 0; k < kGt; ++k) {
+    const int e = threadIdx.x + NTH * k;
+    const int co = e / (TT * TT), r = (e / TT) % TT, cc = e % TT;
+    const int y = ty0 + r, xx = tx0 + cc;
+    goff[k] = (e < kG && co < Cout && y < H && xx < W) ? 4u * ((unsigned)co * (unsigned)HW + (unsigned)(y * W + xx))
+                                                       : kDead;
+  }
+#pragma unroll
+  for (int k = 0; k < kSt; ++k) {
+    const int e = threadIdx.x + NTH * k;
+    const int ci = e / ((TT + 2) * (TT + 2)), r = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+    const int y = ty0 - 1 + r, xx = tx0 - 1 + cc;
+    soff[k] = (e < kS && ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W)
+                  ? 4u * ((unsigned)ci * (unsigned)HW + (unsigned)(y * W + xx)) : kDead;
+  }
+  float gpre[kGt], spre[kSt];
+  auto fetch = [&](int t) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)(4u * Cout * HW), 0x00020000);
+    const float* sb = hseg ? hseg + (((size_t)n * len + t) * sumc + choff_in) * HW
+                           : x + (size_t)n * x_nstride + (size_t)t * Cin * HW;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(sb), (short)0, (int)(4u * Cin * HW), 0x00020000);
+#pragma unroll
+    for (int k = 0; k < kGt; ++k)
+      gpre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, goff[k], 0, 0));
+#pragma unroll
+    for (int k = 0; k < kSt; ++k)
+      spre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, soff[k], 0, 0));
+  };
+  fetch(0);
   for (int t = 0; t < len; ++t) {
-    __syncthreads();
-    const float* g = gh + ((size_t)n * len + t) * Cout * HW;
-    for (int e = threadIdx.x; e < COUTP * TT * TT; e += NTH) {
-      const int co = e / (TT * TT), r = (e / TT) % TT, cc = e % TT;
-      const int y = ty0 + r, xx = tx0 + cc;
-      ghs[co][r * TT + cc] = (co < Cout && y < H && xx < W) ? g[(size_t)co * HW + y * W + xx] : 0.f;
+    __syncthreads();                                   // the previous frame's tiles are consumed
+#pragma unroll
+    for (int k = 0; k < kGt; ++k) {
+      const int e = threadIdx.x + NTH * k;
+      if (e < kG) (&ghs[0][0])[e] = gpre[k];
     }
-    for (int e = threadIdx.x; e < CINP * (TT + 2) * (TT + 2); e += NTH) {
-      const int ci = e / ((TT + 2) * (TT + 2)), r = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
-      const int y = ty0 - 1 + r, xx = tx0 - 1 + cc;
-      float v = 0.f;
-      if (ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W) {
-        if (hseg) {
-          const float h = hseg[(((size_t)n * len + t) * sumc + choff_in + ci) * HW + (size_t)y * W + xx];
-          v = spike_of(h, theta, alpha, relaxed);
-        } else {
-          v = x[(size_t)n * x_nstride + ((size_t)t * Cin + ci) * HW + (size_t)y * W + xx];
-          if (bf_x) v = round_bf16(v);
-        }
+#pragma unroll
+    for (int k = 0; k < kSt; ++k) {
+      const int e = threadIdx.x + NTH * k;
+      if (e < kS) {
+        const float v = spre[k];
+        (&ss[0][0][0])[e] = hseg ? spike_of(v, theta, alpha, relaxed) : (bf_x ? round_bf16(v) : v);
       }
-      ss[ci][r][cc] = v;
     }
+    if (t + 1 < len) fetch(t + 1);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -676,6 +712,10 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
   if (ckpt_every < 1) return fail(EVS_EINVAL, "backward: ckpt_every must be >= 1");
   for (int l = 0; l < net.n_layers; ++l)
     if (!grad_w[l]) return fail(EVS_EINVAL, "backward: NULL grad_w entry");
+  // the gradient kernels address a frame's planes of one layer with 32-bit
+  // byte offsets
+  if ((size_t)32 * clip.H * clip.W * 4 >= ((size_t)1 << 31))
+    return fail(EVS_EUNSUPPORTED, "backward: frame too large (32 x H x W x 4 bytes must stay below 2 GiB)");
   const int k = ckpt_every < clip.T ? ckpt_every : clip.T;
   const BwdLayout Lo = layout(net, clip, k);
   if (!ws || ws_bytes < Lo.total) return fail(EVS_EWORKSPACE, "backward: workspace too small");
