@@ -253,13 +253,16 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(COUTP > 16 
     for (int i = 0; i < 4; ++i)
       g_v[r][i] = y0 + r < H ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, voff[i], r * W * 4, 0))
                              : 0.f;
-  for (int t = len - 1; t >= 0; --t) {
-    __syncthreads();                                   // the previous frame's tile is consumed
+  // a frame's loads: its haloed g_h tile (every load issued before the first
+  // LDS store; planes past Cout fall outside the resource and read 0) and the
+  // h of this lane's neurons.  Narrow layers above (memory-bound: the scan
+  // dominates) load the next frame while the current one is processed.
+  constexpr bool kAhead = COUTP <= 4;
+  float st0[COUTP], st1[COUTP], hn[4][4];
+  auto load_tile = [&](int t) __attribute__((always_inline)) {
     const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)((unsigned)Cout * (unsigned)HW * 4u), 0x00020000);
-    // every load of the frame is issued before the first LDS store; planes
-    // past Cout fall outside the resource and read 0
-    float st0[COUTP], st1[COUTP];
+        const_cast<float*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0,
+        (int)((unsigned)Cout * (unsigned)HW * 4u), 0x00020000);
 #pragma unroll
     for (int co = 0; co < COUTP; ++co)
       st0[co] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, qoff[0] + 4u * co * HW, 0, 0));
@@ -268,6 +271,23 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(COUTP > 16 
       for (int co = 0; co < COUTP; ++co)
         st1[co] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, qoff[1] + 4u * co * HW, 0, 0));
     }
+  };
+  auto load_h = [&](int t) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(hseg + (((size_t)n * len + t) * sumc + choff) * HW), (short)0, (int)bytes, 0x00020000);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        hn[r][i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff[i], r * W * 4, 0));
+  };
+  if constexpr (kAhead) {
+    load_tile(len - 1);
+    load_h(len - 1);
+  }
+  for (int t = len - 1; t >= 0; --t) {
+    __syncthreads();                                   // the previous frame's tile is consumed
+    if constexpr (!kAhead) load_tile(t);
 #pragma unroll
     for (int co = 0; co < COUTP; ++co) ghs[co * PS + threadIdx.x] = st0[co];
     if (threadIdx.x < E * E - NTH) {
@@ -275,14 +295,18 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(COUTP > 16 
       for (int co = 0; co < COUTP; ++co) ghs[co * PS + threadIdx.x + NTH] = st1[co];
     }
     __syncthreads();
-    const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(hseg + (((size_t)n * len + t) * sumc + choff) * HW), (short)0, (int)bytes, 0x00020000);
+    if constexpr (!kAhead) load_h(t);
     float hv[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        hv[r][i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff[i], r * W * 4, 0));
+      for (int i = 0; i < 4; ++i) hv[r][i] = hn[r][i];
+    if constexpr (kAhead) {
+      if (t > 0) {
+        load_tile(t - 1);
+        load_h(t - 1);
+      }
+    }
     f4 acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
@@ -492,21 +516,33 @@ __global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, i
   const int j = lane & 15, g = lane >> 4;
   // staging: this thread's g_h pixel (all 16 channels) and spike-tile entries
   const int gy = ty0 + threadIdx.x / TT, gx = tx0 + threadIdx.x % TT;
-  const bool gin = gy < H && gx < W;
+  // loads through buffer resources bounded to the frame's planes, at 32-bit
+  // byte offsets fixed for the segment; entries outside the image or past
+  // the real channels sit at 2^31 and up and read 0 (whose spike is 0)
+  constexpr unsigned kDead = 0x80000000u;
+  const unsigned goff = (gy < H && gx < W) ? 4u * (unsigned)(gy * W + gx) : kDead;
+  unsigned soff[kSsPerThread];
+#pragma unroll
+  for (int k = 0; k < kSsPerThread; ++k) {
+    const int e = threadIdx.x + NTH * k;
+    const int ci = e / ((TT + 2) * (TT + 2)), rr = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+    const int y = ty0 - 1 + rr, xx = tx0 - 1 + cc;
+    soff[k] = (e < 16 * (TT + 2) * (TT + 2) && ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W)
+                  ? 4u * ((unsigned)ci * (unsigned)HW + (unsigned)(y * W + xx)) : kDead;
+  }
   float gr[16], hr[kSsPerThread];
   auto fetch = [&](int t) __attribute__((always_inline)) {
-    const float* gf = gh + ((size_t)n * len + t) * Cout * HW + (size_t)gy * W + gx;
+    const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)(4u * Cout * HW), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(hseg + (((size_t)n * len + t) * sumc + choff_in) * HW), (short)0, (int)(4u * Cin * HW),
+        0x00020000);
 #pragma unroll
-    for (int co = 0; co < 16; ++co) gr[co] = (co < Cout && gin) ? gf[(size_t)co * HW] : 0.f;
+    for (int co = 0; co < 16; ++co)
+      gr[co] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, goff + 4u * co * HW, 0, 0));
 #pragma unroll
-    for (int k = 0; k < kSsPerThread; ++k) {
-      const int e = threadIdx.x + NTH * k;
-      const int ci = e / ((TT + 2) * (TT + 2)), rr = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
-      const int y = ty0 - 1 + rr, xx = tx0 - 1 + cc;
-      const bool in = e < 16 * (TT + 2) * (TT + 2) && ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W;
-      // out-of-image entries hold a value whose spike is 0
-      hr[k] = in ? hseg[(((size_t)n * len + t) * sumc + choff_in + ci) * HW + (size_t)y * W + xx] : 0.f;
-    }
+    for (int k = 0; k < kSsPerThread; ++k)
+      hr[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, soff[k], 0, 0));
   };
   f4 acc[9];
 #pragma unroll
