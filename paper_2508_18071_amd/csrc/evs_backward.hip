@@ -5,15 +5,17 @@
 //   1. the forward kernel recomputes the segment's charged potentials h of
 //      every layer from the segment's checkpoint (bit-identical to the
 //      original forward: same kernel, same state);
-//   2. for layers L..1: a reverse-time adjoint scan per neuron
+//   2. the top layer's reverse-time adjoint scan per neuron
 //          g_h = (G - theta g_v) psi(h) + g_v     (G psi(h) + g_v detached)
 //          g_v <- leak * g_h
-//      with g_v carried across segment boundaries;
-//   3. the weight gradient dW[co][ci][tap] = sum_t,p g_h[co][p] s_in[ci][p+tap]
+//      on G = grad_s, with g_v carried across segment boundaries;
+//   3. for layers L..1: the weight gradient
+//          dW[co][ci][tap] = sum_t,p g_h[co][p] s_in[ci][p+tap]
 //      as per-tile partial sums in registers, reduced in a fixed order (no
-//      float atomics: results are bitwise reproducible);
-//   4. the incoming gradient of the layer below, G = conv_transpose(g_h, W)
-//      (grad_x for layer 1).
+//      float atomics: results are bitwise reproducible); then the incoming
+//      gradient of the layer below, G = conv_transpose(g_h, W), which for
+//      l >= 2 feeds that layer's adjoint scan in the same kernel (G stays in
+//      registers), and for l = 1 is grad_x.
 // Spikes fed to dW are recomputed from h with the forward's own device
 // function, so they equal the forward's spikes bit for bit.
 #include "evs_device.hpp"
