@@ -62,10 +62,16 @@ __device__ inline float spike_of(float h, float theta, float alpha, int relaxed)
 
 // Surrogate derivative of the spike (Eq. 4):
 // psi(h) = step'(h - theta) + step'(-h - theta), kind 0 sigmoid, 1 arctangent.
+// Only gradients use it, so its reciprocals are the hardware's (within 1 ulp)
+// rather than correctly rounded: two per neuron and frame, in kernels where
+// the vector ALU is shared with the matrix pipe.
 __device__ inline float surrogate(float h, float theta, float alpha, int kind) {
-  if (kind == 1) return surr_slope(h - theta, alpha, 1) + surr_slope(-h - theta, alpha, 1);
-  const float a = sigm_fast(alpha * (h - theta));
-  const float b = sigm_fast(alpha * (-h - theta));
+  if (kind == 1) {
+    const float qa = 1.57079633f * alpha * (h - theta), qb = 1.57079633f * alpha * (-h - theta);
+    return 0.5f * alpha * (__builtin_amdgcn_rcpf(fmaf(qa, qa, 1.0f)) + __builtin_amdgcn_rcpf(fmaf(qb, qb, 1.0f)));
+  }
+  const float a = __builtin_amdgcn_rcpf(1.0f + __expf(-alpha * (h - theta)));
+  const float b = __builtin_amdgcn_rcpf(1.0f + __expf(-alpha * (-h - theta)));
   return alpha * (a * (1.0f - a) + b * (1.0f - b));
 }
 
