@@ -192,7 +192,7 @@ __global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int
 // 336 floats apart (16 banks mod 64), so the four lane groups of a read hit
 // distinct banks.  FP32 products and sums, in the matrix pipe's own order.
 template <int COUTP>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(COUTP > 16 ? 2 : 3))) void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3))) void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
                                                     int W, int tiles_x, const float* __restrict__ wT,
                                                     float* __restrict__ out, const float* __restrict__ hseg,
                                                     int sumc, int choff, float* __restrict__ gv, float theta,
@@ -659,15 +659,24 @@ struct ConvTArgs {
 };
 template <int CINP, int COUTP>
 void launch_convT(dim3 g, hipStream_t st, bool adj, const ConvTArgs& a) {
-  if (adj && CINP == 16)
-    hipLaunchKernelGGL((k_convT_mfma<COUTP>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W, a.tiles_x,
-                       a.wT, a.out, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha, a.surr, a.detach);
-  else if (adj)
-    hipLaunchKernelGGL((k_convT<CINP, COUTP, true>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
-                       a.tiles_x, a.wT, a.out, a.ons, a.ots, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha,
-                       a.surr, a.detach);
-  else
-    hipLaunchKernelGGL((k_convT<CINP, COUTP, false>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
+  // hidden layers have equal widths, so the matrix-pipe kernel serves 16-wide
+  // hidden layers below a 16-wide layer or the output layer
+  if constexpr (CINP == 16 && COUTP <= 16) {
+    if (adj) {
+      hipLaunchKernelGGL((k_convT_mfma<COUTP>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
+                         a.tiles_x, a.wT, a.out, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha, a.surr,
+                         a.detach);
+      return;
+    }
+  } else {
+    if (adj) {
+      hipLaunchKernelGGL((k_convT<CINP, COUTP, true>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
+                         a.tiles_x, a.wT, a.out, a.ons, a.ots, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak,
+                         a.alpha, a.surr, a.detach);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_convT<CINP, COUTP, false>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
                        a.tiles_x, a.wT, a.out, a.ons, a.ots, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha,
                        a.surr, a.detach);
 }

@@ -53,6 +53,10 @@ def _setup(evs, channels, prec, T, H, W, N=1, seed=0, scale=1.0, relaxed=False, 
                                                        ((3, 16, 16, 2), "fp32", False, "atan"),
                                                        ((3, 32, 2), "bf16", False, "sigmoid"),
                                                        ((3, 16, 16, 2), "bf16", False, "sigmoid"),
+                                                       # widths that are not multiples of 4; two
+                                                       # 32-wide hidden layers
+                                                       ((3, 10, 10, 2), "fp32", False, "sigmoid"),
+                                                       ((3, 32, 32, 2), "bf16", False, "sigmoid"),
                                                        ((1, 1), "fp32", False, "sigmoid")])
 @pytest.mark.parametrize("k", [4, 100])
 def test_backward_matches_oracle(evs, channels, prec, detach, surr, k):
