@@ -196,7 +196,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3))) void k
                                                     int W, int tiles_x, const float* __restrict__ wT,
                                                     float* __restrict__ out, const float* __restrict__ hseg,
                                                     int sumc, int choff, float* __restrict__ gv, float theta,
-                                                    float leak, float alpha, int surr, int detach) {
+                                                    float leak, float alpha, int surr, int detach, int relaxed,
+                                                    float* __restrict__ dw_partial) {
   constexpr int E = TT + 2;                            // haloed tile edge
   constexpr int PS = (E * E + 47) / 64 * 64 + 16;      // plane stride, 16 mod 64
   constexpr int COG = COUTP < 4 ? 4 : COUTP;           // co slots per tap
@@ -223,6 +224,28 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3))) void k
   // (zero weights) read plane g % COUTP, whose values are finite
   const int plane = COUTP < 4 ? g % COUTP : g;
   const float* const bbase = ghs + plane * PS + 4 * wave * E + j;
+  // Narrow layers (output widths <= 4) also form their own weight gradient
+  // dW[co][ci][tap] = sum_q s[ci][q] g_h[co][q - tap] (s: the spikes of the
+  // layer below, from the h this kernel reads anyway) as a 16 (ci) x 16
+  // ((co, tap), two column tiles) product over the wave's 64 pixels per
+  // frame: the spikes go through LDS into the A layout, g_h is read from the
+  // haloed tile already in LDS.  Per-wave sums stay in registers for the
+  // segment and are added in wave order at the end.
+  constexpr bool kDW = COUTP <= 4;
+  constexpr int kDWCols = COUTP * 9;
+  static_assert(!kDW || kDWCols <= 32, "two column tiles");
+  constexpr int SBS = NTH + 4;                         // ci stride: lanes j hit banks 4j + g
+  __shared__ float sb[kDW ? 16 * SBS : 1];
+  f4 dacc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+  int dwoff[2];
+  bool dwcol[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const int idx = 16 * nt + j, co = idx / 9, tap = idx % 9;
+    dwcol[nt] = kDW && idx < kDWCols && co < Cout;
+    // B of pixel (row, col) of the wave's rows: g_h[co][row - dy][col - dx]
+    dwoff[nt] = dwcol[nt] ? co * PS + (1 - (tap / 3 - 1)) * E + (1 - (tap % 3 - 1)) + 4 * wave * E + g : 0;
+  }
   // this lane's 16 neurons: rows 4 wave + r (uniform in the wave), column j,
   // channels 4g + i.  Their [ch][H][W] planes are read and written through
   // buffer resources bounded to the layer's Cin planes: voff[i] + r W 4 is
@@ -340,6 +363,56 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3))) void k
           const float gn = detach ? fmaf(Gv, psi, g_v[r][i]) : fmaf(fmaf(-theta, g_v[r][i], Gv), psi, g_v[r][i]);
           __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, gn), ro, voff[i], r * W * 4, 0);
           g_v[r][i] = leak * gn;
+        }
+      }
+    }
+    if constexpr (kDW) {
+      // the wave's own pixels only: rows 4 wave .. 4 wave + 3 of the tile
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          sb[(4 * g + i) * SBS + (4 * wave + r) * TT + j] =
+              y0 + r < H ? spike_of(hv[r][i], theta, alpha, relaxed) : 0.f;
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        // k-step: pixels 4 kk .. 4 kk + 3 of the wave; lane group g takes
+        // pixel 4 kk + g = (row kk / 4, column 4 (kk % 4) + g)
+        const float av = sb[j * SBS + (4 * wave + kk / 4) * TT + 4 * (kk % 4) + g];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          const float bv = dwcol[nt] ? ghs[dwoff[nt] + (kk / 4) * E + 4 * (kk % 4)] : 0.f;
+          dacc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, dacc[nt], 0, 0, 0);
+        }
+      }
+    }
+  }
+  if constexpr (kDW) {
+    // lane (column j, group g) holds dW for ci 4g..4g+3 of column 16 nt + j;
+    // the four waves' sums are added in wave order
+    __syncthreads();
+    float* red = sb;                                   // [wave - 1][lane][8]
+    if (wave > 0) {
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[((wave - 1) * 64 + lane) * 8 + 4 * nt + i] = dacc[nt][i];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      float* o = dw_partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (16 * COUTP * 9);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const int idx = 16 * nt + j, co = idx / 9, tap = idx % 9;
+        if (idx < kDWCols) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float v = dacc[nt][i];
+#pragma unroll
+            for (int w2 = 0; w2 < 3; ++w2) v += red[(w2 * 64 + lane) * 8 + 4 * nt + i];
+            o[(co * 16 + 4 * g + i) * 9 + tap] = v;      // [co][ci][tap], as the VALU kernel
+          }
         }
       }
     }
@@ -656,6 +729,7 @@ struct ConvTArgs {
   const float* gh; int Cout, Cin, len, H, W, tiles_x; const float* wT;
   float* out; long long ons, ots;
   const float* hseg; int sumc, choff; float* gv; float theta, leak, alpha; int surr, detach;
+  int relaxed; float* dw_partial;     // the fused weight gradient of narrow layers
 };
 template <int CINP, int COUTP>
 void launch_convT(dim3 g, hipStream_t st, bool adj, const ConvTArgs& a) {
@@ -665,7 +739,7 @@ void launch_convT(dim3 g, hipStream_t st, bool adj, const ConvTArgs& a) {
     if (adj) {
       hipLaunchKernelGGL((k_convT_mfma<COUTP>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
                          a.tiles_x, a.wT, a.out, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha, a.surr,
-                         a.detach);
+                         a.detach, a.relaxed, a.dw_partial);
       return;
     }
   } else {
@@ -835,29 +909,33 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
     for (int l = L; l >= 1; --l) {
       const int C = net.ch[l], Cin = net.ch[l - 1];
       float* gh = ghb[cur];
-      // weight gradient partials for this segment, then fixed-order reduction
+      // weight gradient partials for this segment (a narrow layer above a
+      // 16-wide one forms them inside its conv-transpose), then the
+      // fixed-order reduction; then the g_h of the layer below (the
+      // conv-transpose and that layer's adjoint scan), or grad_x
       const int CI = pad_in(Cin), CO = pad_out(C);
+      const bool fused_dw = l >= 2 && CI == 16 && CO <= 4;
       const dim3 gdw((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)N);
-      const float* hin = l >= 2 ? hseg : nullptr;
-      const int choff_in = l >= 2 ? choff[l - 2] : 0;
+      if (!fused_dw) {
+        const float* hin = l >= 2 ? hseg : nullptr;
+        const int choff_in = l >= 2 ? choff[l - 2] : 0;
 #define EVS_CALL_DW(A, B)                                                                              \
   launch_dw<A, B>(gdw, st, gh, C, Cin, len, H, W, Lo.tiles_x, clip.x + (size_t)t0 * cin0 * HW,          \
                   (long long)T * cin0 * HW, bf ? 1 : 0, hin, sumc, choff_in, net.theta, net.surr_alpha, \
                   net.relaxed ? 1 + net.surrogate : 0, partial)
-      EVS_DISPATCH_PAD(CI, CO, EVS_CALL_DW);
+        EVS_DISPATCH_PAD(CI, CO, EVS_CALL_DW);
 #undef EVS_CALL_DW
-      EVS_HIP(hipGetLastError());
-      const int E = CI * CO * 9;
-      hipLaunchKernelGGL(k_dw_reduce, dim3((E + kRedE - 1) / kRedE), dim3(kRedE * kRedB), 0, st, partial,
-                         Lo.tiles_x * Lo.tiles_y * N, E, acc + accofs[l - 1]);
-      EVS_HIP(hipGetLastError());
-      // g_h of the layer below (conv-transpose + its adjoint scan), or grad_x
-      if (l >= 2 || grad_x) {
+        EVS_HIP(hipGetLastError());
+      }
+      const bool convt = l >= 2 || grad_x;
+      if (convt) {
         ConvTArgs a{};
         a.gh = gh; a.Cout = C; a.Cin = Cin; a.len = len; a.H = H; a.W = W; a.tiles_x = Lo.tiles_x;
         a.wT = wT + accofs[l - 1];
         a.theta = net.theta; a.leak = net.leak; a.alpha = net.surr_alpha; a.surr = net.surrogate;
         a.detach = net.detach_reset; a.sumc = sumc;
+        a.relaxed = net.relaxed ? 1 + net.surrogate : 0;
+        a.dw_partial = partial;
         if (l >= 2) {
           a.out = ghb[cur ^ 1];
           a.hseg = hseg; a.choff = choff[l - 2]; a.gv = gv;
@@ -871,6 +949,12 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
         EVS_DISPATCH_PAD(CI, CO, EVS_CALL_CT);
 #undef EVS_CALL_CT
         EVS_HIP(hipGetLastError());
+      }
+      const int E = CI * CO * 9;
+      hipLaunchKernelGGL(k_dw_reduce, dim3((E + kRedE - 1) / kRedE), dim3(kRedE * kRedB), 0, st, partial,
+                         Lo.tiles_x * Lo.tiles_y * N, E, acc + accofs[l - 1]);
+      EVS_HIP(hipGetLastError());
+      if (convt) {
         cur ^= 1;
       }
     }
