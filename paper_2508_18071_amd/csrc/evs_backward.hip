@@ -192,7 +192,8 @@ __global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int
 // 336 floats apart (16 banks mod 64), so the four lane groups of a read hit
 // distinct banks.  FP32 products and sums, in the matrix pipe's own order.
 template <int COUTP>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3))) void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3)))
+void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
                                                     int W, int tiles_x, const float* __restrict__ wT,
                                                     float* __restrict__ out, const float* __restrict__ hseg,
                                                     int sumc, int choff, float* __restrict__ gv, float theta,
@@ -226,8 +227,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3))) void k
   const float* const bbase = ghs + plane * PS + 4 * wave * E + j;
   // Narrow layers (output widths <= 4) also form their own weight gradient
   // dW[co][ci][tap] = sum_q s[ci][q] g_h[co][q - tap] (s: the spikes of the
-  // layer below, from the h this kernel reads anyway) as a 16 (ci) x 16
-  // ((co, tap), two column tiles) product over the wave's 64 pixels per
+  // layer below, from the h this kernel reads anyway) as a 16 (ci) x 18
+  // ((co, tap), in two 16-column tiles) product over the wave's 64 pixels per
   // frame: the spikes go through LDS into the A layout, g_h is read from the
   // haloed tile already in LDS.  Per-wave sums stay in registers for the
   // segment and are added in wave order at the end.
