@@ -11,8 +11,10 @@
 //      on G = grad_s, with g_v carried across segment boundaries;
 //   3. for layers L..1: the weight gradient
 //          dW[co][ci][tap] = sum_t,p g_h[co][p] s_in[ci][p+tap]
-//      as per-tile partial sums in registers, reduced in a fixed order (no
-//      float atomics: results are bitwise reproducible); then the incoming
+//      as per-tile partial sums in registers, added to the tile's slot for
+//      the whole backward and reduced over the tiles once at the end, in a
+//      fixed order (no float atomics: results are bitwise reproducible);
+//      then the incoming
 //      gradient of the layer below, G = conv_transpose(g_h, W), which for
 //      l >= 2 feeds that layer's adjoint scan in the same kernel (G stays in
 //      registers), and for l = 1 is grad_x.
@@ -412,7 +414,7 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
             float v = dacc[nt][i];
 #pragma unroll
             for (int w2 = 0; w2 < 3; ++w2) v += red[(w2 * 64 + lane) * 8 + 4 * nt + i];
-            o[(co * 16 + 4 * g + i) * 9 + tap] = v;      // [co][ci][tap], as the VALU kernel
+            o[(co * 16 + 4 * g + i) * 9 + tap] += v;     // [co][ci][tap], as the VALU kernel
           }
         }
       }
@@ -552,14 +554,14 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
       for (int tap = 0; tap < 9; ++tap) {
         float sacc = 0.f;
         for (int s2 = 0; s2 < TPP; ++s2) sacc += red[(s2 * P + threadIdx.x) * 9 + tap];
-        out[threadIdx.x * 9 + tap] = sacc;
+        out[threadIdx.x * 9 + tap] += sacc;
       }
     }
   } else {
 #pragma unroll
     for (int k = 0; k < PPT; ++k)
 #pragma unroll
-      for (int tap = 0; tap < 9; ++tap) out[(threadIdx.x + NTH * k) * 9 + tap] = acc[k][tap];
+      for (int tap = 0; tap < 9; ++tap) out[(threadIdx.x + NTH * k) * 9 + tap] += acc[k][tap];
   }
 }
 
@@ -687,7 +689,7 @@ __global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, i
         float v = acc[tap][r];
 #pragma unroll
         for (int w2 = 0; w2 < 3; ++w2) v += rb[(w2 * 64 + lane) * 36 + tap * 4 + r];
-        out[((4 * g + r) * 16 + j) * 9 + tap] = v;
+        out[((4 * g + r) * 16 + j) * 9 + tap] += v;
       }
   }
 }
@@ -790,11 +792,10 @@ BwdLayout layout(const evs_net& net, const evs_clip& c, int k) {
   BwdLayout L{};
   const size_t HW = (size_t)c.H * c.W;
   const int sumc = real_sum_channels(net);
-  int cmax = 0, emax = 0, accsum = 0;
+  int cmax = 0, accsum = 0;
   for (int l = 1; l <= net.n_layers; ++l) {
     cmax = net.ch[l] > cmax ? net.ch[l] : cmax;
     const int e = pad_in(net.ch[l - 1]) * pad_out(net.ch[l]) * 9;
-    emax = e > emax ? e : emax;
     accsum += e;
   }
   L.k = k;
@@ -808,7 +809,7 @@ BwdLayout layout(const evs_net& net, const evs_clip& c, int k) {
   L.gv = o; o += align256((size_t)c.N * sumc * HW * 4);
   L.gh = o; o += align256((size_t)c.N * k * cmax * HW * 4);
   L.gh2 = o; o += align256((size_t)c.N * k * cmax * HW * 4);
-  L.partial = o; o += align256(nblk * emax * 4);
+  L.partial = o; o += align256(nblk * accsum * 4);
   L.acc = o; o += align256((size_t)accsum * 4);
   L.wT = o; o += align256((size_t)accsum * 4);
   L.total = o;
@@ -865,6 +866,10 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
 
   if ((rc = zero_f32(gv, (size_t)N * sumc * HW, st))) return rc;
   if ((rc = zero_f32(acc, (size_t)accofs[L], st))) return rc;
+  // per-workgroup dW partial sums of every layer, [layer][block][E_l],
+  // accumulated over the segments and reduced once at the end
+  const size_t nblk = (size_t)Lo.tiles_x * Lo.tiles_y * N;
+  if ((rc = zero_f32(partial, nblk * accofs[L], st))) return rc;
   for (int l = 1; l <= L; ++l) {
     const int CI = pad_in(net.ch[l - 1]), CO = pad_out(net.ch[l]);
     hipLaunchKernelGGL(k_pack_wT, dim3((9 * CI * CO + 255) / 256), dim3(256), 0, st, wbase + na.wofs[l - 1],
@@ -923,7 +928,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
 #define EVS_CALL_DW(A, B)                                                                              \
   launch_dw<A, B>(gdw, st, gh, C, Cin, len, H, W, Lo.tiles_x, clip.x + (size_t)t0 * cin0 * HW,          \
                   (long long)T * cin0 * HW, bf ? 1 : 0, hin, sumc, choff_in, net.theta, net.surr_alpha, \
-                  net.relaxed ? 1 + net.surrogate : 0, partial)
+                  net.relaxed ? 1 + net.surrogate : 0, partial + nblk * accofs[l - 1])
         EVS_DISPATCH_PAD(CI, CO, EVS_CALL_DW);
 #undef EVS_CALL_DW
         EVS_HIP(hipGetLastError());
@@ -936,7 +941,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
         a.theta = net.theta; a.leak = net.leak; a.alpha = net.surr_alpha; a.surr = net.surrogate;
         a.detach = net.detach_reset; a.sumc = sumc;
         a.relaxed = net.relaxed ? 1 + net.surrogate : 0;
-        a.dw_partial = partial;
+        a.dw_partial = partial + nblk * accofs[l - 1];
         if (l >= 2) {
           a.out = ghb[cur ^ 1];
           a.hseg = hseg; a.choff = choff[l - 2]; a.gv = gv;
@@ -951,16 +956,18 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
 #undef EVS_CALL_CT
         EVS_HIP(hipGetLastError());
       }
-      const int E = CI * CO * 9;
-      hipLaunchKernelGGL(k_dw_reduce, dim3((E + kRedE - 1) / kRedE), dim3(kRedE * kRedB), 0, st, partial,
-                         Lo.tiles_x * Lo.tiles_y * N, E, acc + accofs[l - 1]);
-      EVS_HIP(hipGetLastError());
       if (convt) {
         cur ^= 1;
       }
     }
   }
-  // outputs
+  // the fixed-order reduction of each layer's partial sums, then outputs
+  for (int l = 1; l <= L; ++l) {
+    const int E = accofs[l] - accofs[l - 1];
+    hipLaunchKernelGGL(k_dw_reduce, dim3((E + kRedE - 1) / kRedE), dim3(kRedE * kRedB), 0, st,
+                       partial + nblk * accofs[l - 1], (int)nblk, E, acc + accofs[l - 1]);
+    EVS_HIP(hipGetLastError());
+  }
   for (int l = 1; l <= L; ++l) {
     const int E = net.ch[l] * net.ch[l - 1] * 9;
     hipLaunchKernelGGL(k_dw_out, dim3((E + 255) / 256), dim3(256), 0, st, acc + accofs[l - 1], net.ch[l],
