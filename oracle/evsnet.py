@@ -258,6 +258,45 @@ def backward(x, weights, theta, leak, grad_s, v_init=None, mode="hard", alpha=4.
     return {"dW": dW, "dx": dx, "dv_init": g_v}
 
 
+def backward_along(x, weights, theta, leak, grad_s, h_traj, alpha=4.0, detach_reset=False,
+                   surr="sigmoid"):
+    """The BPTT backward of Eq. (4) along a given trajectory of hard spikes.
+
+    h_traj  list over layers of [T, C_l, H, W] charged potentials (e.g. the
+            device's own trace).  Everything the backward needs from the
+            forward is a function of them: the spikes s_l = fire(h_l) (the
+            input of layer l+1 and of its weight gradient) and the surrogate
+            psi(h_l).  No forward is run here, so a device whose FP32 sums put
+            a potential on the other side of a threshold than FP64 would is
+            still checked step by step.  With the oracle's own trajectory
+            this is the same computation as ``backward`` with mode "hard".
+
+    Returns dict with "dW", "dx" and "dv_init" as ``backward`` does.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    T, C0, H, W = x.shape
+    ws = [np.asarray(w, dtype=np.float64) for w in weights]
+    L = len(ws)
+    dW = [np.zeros_like(w) for w in ws]
+    dx = np.zeros_like(x)
+    g_v = [np.zeros((w.shape[0], H, W)) for w in ws]
+    for t in reversed(range(T)):
+        G = np.asarray(grad_s[t], dtype=np.float64)
+        for l in reversed(range(L)):
+            h = np.asarray(h_traj[l][t], dtype=np.float64)
+            psi = surrogate(h, theta, alpha, surr)
+            if detach_reset:
+                g_h = G * psi + g_v[l]
+            else:
+                g_h = (G - theta * g_v[l]) * psi + g_v[l]
+            s_in = x[t] if l == 0 else fire(np.asarray(h_traj[l - 1][t], dtype=np.float64), theta)
+            dW[l] += conv3x3_weight_grad(g_h, s_in)
+            G = conv3x3_transpose(g_h, ws[l])
+            g_v[l] = leak * g_h
+        dx[t] = G
+    return {"dW": dW, "dx": dx, "dv_init": g_v}
+
+
 # ----------------------------------------------------------------------------
 # teacher-forced one-step reference
 # ----------------------------------------------------------------------------

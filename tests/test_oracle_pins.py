@@ -357,6 +357,64 @@ def test_p13_bptt_matches_torch_autograd_and_checkpoint_invariance():
     g2 = evsnet.backward(x, ws, theta, beta, G, ckpt_every=None)
     for l in range(3):
         np.testing.assert_array_equal(g1["dW"][l], g2["dW"][l])
+    # the backward along a given trajectory, fed the autograd run's own
+    # charged potentials, gives autograd's gradients (an independent pin of
+    # backward_along: no oracle forward is involved)
+    ht = [torch.zeros(T, c, H, W, dtype=torch.float64) for c in chs[1:]]
+    v = [torch.zeros(c, H, W, dtype=torch.float64) for c in chs[1:]]
+    with torch.no_grad():
+        for t in range(T):
+            s = torch.from_numpy(x[t])
+            for l in range(3):
+                h = beta * v[l] + F.conv2d(s[None], torch.from_numpy(ws[l]), padding=1)[0]
+                ht[l][t] = h
+                s = (h >= theta).double() - (h <= -theta).double()
+                v[l] = h - theta * s
+    ga = evsnet.backward_along(x, ws, theta, beta, G, [h.numpy() for h in ht])
+    for l in range(3):
+        np.testing.assert_allclose(ga["dW"][l], wt[l].grad.numpy(), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(ga["dx"], xt.grad.numpy(), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("surr,detach", [("sigmoid", False), ("sigmoid", True), ("atan", False)])
+def test_backward_along_own_trajectory_equals_bptt(surr, detach):
+    """Fed the oracle's own hard-spike trajectory, the backward along a given
+    trajectory is the same computation as the checkpointed BPTT: identical
+    bits for the weight, input and initial-state gradients."""
+    rng = np.random.default_rng(17)
+    T, H, W, chs = 8, 7, 6, (3, 5, 4, 2)
+    x = rng.normal(size=(T, 3, H, W)) * 2
+    ws = rand_net(chs, 17)
+    G = rng.normal(size=(T, 2, H, W))
+    alpha = 4.0 if surr == "sigmoid" else 2.0
+    out = evsnet.forward(x, ws, 0.5, 0.9)
+    a = evsnet.backward_along(x, ws, 0.5, 0.9, G, out["h"], alpha=alpha, detach_reset=detach, surr=surr)
+    b = evsnet.backward(x, ws, 0.5, 0.9, G, alpha=alpha, detach_reset=detach, surr=surr, ckpt_every=3)
+    for l in range(3):
+        np.testing.assert_array_equal(a["dW"][l], b["dW"][l])
+        np.testing.assert_array_equal(a["dv_init"][l], b["dv_init"][l])
+    np.testing.assert_array_equal(a["dx"], b["dx"])
+
+
+def test_backward_along_follows_the_given_trajectory():
+    """A trajectory whose spike differs from the FP64 forward at one neuron
+    (as an FP32 device may produce at a near-threshold step) changes the
+    gradients exactly as a forward that fired there would: the backward is
+    computed along the given potentials, not along a recomputed forward."""
+    rng = np.random.default_rng(23)
+    T, H, W, chs = 6, 5, 5, (3, 4, 2)
+    x = rng.normal(size=(T, 3, H, W)) * 2
+    ws = rand_net(chs, 23)
+    G = rng.normal(size=(T, 2, H, W))
+    out = evsnet.forward(x, ws, 0.5, 0.9)
+    h = [a.copy() for a in out["h"]]
+    # find a silent hidden neuron and lift its potential onto the threshold
+    t, c, y, xx = np.argwhere(np.abs(h[0]) < 0.5)[0]
+    h[0][t, c, y, xx] = 0.5
+    g = evsnet.backward_along(x, ws, 0.5, 0.9, G, h)
+    ref = evsnet.backward_along(x, ws, 0.5, 0.9, G, out["h"])
+    # the output layer's weight gradient sees the flipped input spike
+    assert np.abs(g["dW"][1] - ref["dW"][1]).max() > 1e-6
 
 
 # ---------------------------------------------------------------- EMD pins
@@ -685,3 +743,36 @@ def test_tnet_quant_rounds_through_float32_to_bf16():
     for a in layers:
         t = torch.from_numpy(a.astype(np.float32))
         assert np.array_equal(a, t.to(torch.bfloat16).to(torch.float64).numpy())
+
+
+def _tnet_golden():
+    rows = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "tnet_residual_examples.txt")
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, val = (s.strip() for s in line.split(";"))
+        rows[key] = [float(v) for v in (val.split() if key == "weights" else val.split(","))]
+    return rows
+
+
+def test_tnet_residual_blocks_golden_example():
+    """Hand-derived one-channel worked example (tests/golden): delta kernels,
+    some negative, chosen so that the ReLU inside each residual block and the
+    ReLU after each residual add both clip on some frame.  Dropping either
+    ReLU of any block, or applying the outer one before the residual add,
+    changes u on at least one frame."""
+    from oracle import tnet
+    g = _tnet_golden()
+    wv = g["weights"]
+    delta = lambda w: np.array([0, 0, 0, w, 0, 0, 0], np.float64).reshape(1, 1, 7)
+    p = {"w0": delta(wv[0]), "b0": np.array([wv[1]]),
+         "w": [None] + [delta(wv[2 * k]) for k in range(1, 7)],
+         "b": [None] + [np.array([wv[2 * k + 1]]) for k in range(1, 7)],
+         "wp": np.array([wv[14]]), "bp": wv[15]}
+    x = np.array(g["x"])[None, :]
+    u, layers = tnet.encode(x, p)
+    for name, a in zip(("h0", "a1", "h1", "a2", "h2", "a3", "h3"), layers):
+        np.testing.assert_array_equal(a[0, 0], g[name], err_msg=name)
+    np.testing.assert_array_equal(u[0], g["u"])
