@@ -133,7 +133,7 @@ def compact_into(evs, s, events, count, ws):
     T, C, H, W = s.shape
     import torch
     _lib.check(evs.lib().evs_compact_events(s.data_ptr(), T, C, H, W, events.data_ptr(), events.numel(),
-                                            count.data_ptr(), ws.data_ptr(), ws.numel(),
+                                            count.data_ptr(), ws.data_ptr(), ws.numel(), None,
                                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
                "compact_events")
 

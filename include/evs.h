@@ -152,6 +152,33 @@ typedef struct evs_clip {
 #define EVS_EVENT_C(e)   ((uint32_t)(((e) >> 56) & 0x7fu))
 #define EVS_EVENT_NEG(e) ((uint32_t)((e) >> 63))
 
+/* Device status word: a caller-owned DEVICE array of EVS_STATUS_WORDS
+ * int32 values that evs_forward, evs_backward and evs_compact_events update
+ * from their kernels when it is passed (it may be NULL: nothing is
+ * recorded).  Updates accumulate (counts add, flag bits are OR-ed): the
+ * library never clears the word, so the caller zeroes it (e.g. a zero-filled
+ * tensor) before the calls it wants to watch.  Updating it needs no host
+ * synchronisation and no memset, so the calls stay graph-capturable.
+ *   [EVS_STATUS_NAN_X]    NaN values in the network input x of evs_forward
+ *                         (every value of every clip: [N][T][Cin][H][W],
+ *                         or the T+1 RGB frames of RGB-input nets), counted
+ *                         by one extra streaming read of x (4 bytes per
+ *                         value) that runs only when the word is given.  A
+ *                         NaN input propagates (a NaN potential never
+ *                         reaches a threshold, so its neurons stay silent);
+ *                         the NaN potentials that mask the neurons outside
+ *                         the image are not inputs and are not counted.
+ *   [EVS_STATUS_NAN_GRAD] NaN values read from grad_s by evs_backward.
+ *   [EVS_STATUS_FLAGS]    EVS_FLAG_EVENT_OVERFLOW: evs_compact_events found
+ *                         more events than `capacity` (the list was cut; the
+ *                         dense spikes and `count` stay exact).
+ *   [3]                   reserved (left unchanged).                       */
+#define EVS_STATUS_WORDS 4
+#define EVS_STATUS_NAN_X 0
+#define EVS_STATUS_NAN_GRAD 1
+#define EVS_STATUS_FLAGS 2
+#define EVS_FLAG_EVENT_OVERFLOW 1
+
 /* Operation selector for evs_workspace_bytes. */
 typedef enum {
   EVS_OP_FORWARD = 0,
@@ -184,9 +211,11 @@ int evs_pack_weights(const evs_net* net, const float* const* w, void* packed, vo
  *           float32: the membrane of every layer before frames 0, k, 2k, ...
  *           (k = ckpt_every), as needed by evs_backward.
  *   tile    tiles are chosen by the autotuner cache (evs_autotune) or a
- *           built-in default; results do not depend on the tile choice.  */
+ *           built-in default; results do not depend on the tile choice.
+ *   dev_status  NULL or the device status word (counts NaN inputs).     */
 int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, int32_t n_clips,
-                float* ckpt, int32_t ckpt_every, void* ws, size_t ws_bytes, void* stream);
+                float* ckpt, int32_t ckpt_every, void* ws, size_t ws_bytes, int32_t* dev_status,
+                void* stream);
 
 /* Surrogate-gradient BPTT backward through the whole clip (Eq. 4).
  * The surrogate is psi(h) = sigma'(h - theta) + sigma'(-h - theta), the
@@ -202,12 +231,13 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
  *           overwritten with dLoss/dW_l (summed over the batch)
  *   grad_x  NULL or [N][T][Cin][H][W] float32 dLoss/dx
  *   grad_v  NULL or [N][sum C][H][W] float32 dLoss/d(initial membrane)
+ *   dev_status  NULL or the device status word (counts NaN values of grad_s)
  * Segments are recomputed from their checkpoints in reverse order; the
  * weight gradient is reduced deterministically (no float atomics).      */
 int evs_backward(const evs_net* net, const void* packed, const evs_clip* clip,
                  const float* ckpt, int32_t ckpt_every, const float* grad_s,
                  float* const* grad_w, float* grad_x, float* grad_v,
-                 void* ws, size_t ws_bytes, void* stream);
+                 void* ws, size_t ws_bytes, int32_t* dev_status, void* stream);
 
 /* Bidirectional polarity-split EMD loss plus spike-count term (Eq. 7-11).
  *   s       [N][T][C][H][W] float32 spikes, C = 2 (channel 0 = ON stream,
@@ -228,11 +258,13 @@ int evs_emd_loss(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t 
  *   s         [T][C][H][W] int8 spikes
  *   events    device uint64 array of `capacity` records (format above)
  *   count     device int64: the number of events in s.  If it exceeds
- *             capacity, only the first `capacity` events are written.
+ *             capacity, only the first `capacity` events are written and
+ *             EVS_FLAG_EVENT_OVERFLOW is set in dev_status (NULL or the
+ *             device status word).
  * Requires W, H <= 4096, C <= 128, T < 2^32.                            */
 int evs_compact_events(const int8_t* s, int32_t T, int32_t C, int32_t H, int32_t W,
                        uint64_t* events, int64_t capacity, int64_t* count,
-                       void* ws, size_t ws_bytes, void* stream);
+                       void* ws, size_t ws_bytes, int32_t* dev_status, void* stream);
 
 /* Network input of Eq. (1) (Sec. 3.2): per pixel the Rec. 709 luminance
  * L = lum_scale * (0.2126 R + 0.7152 G + 0.0722 B) of linear RGB frames,

@@ -6,9 +6,9 @@ include/evs.h); this package only marshals torch tensors into it.
 
 from .api import (Net, TNet, Graph, pack_weights, forward, forward_batched, backward, emd_loss,
                   compact_events, logdiff, contrast_events, tnet_forward, tnet_weight_floats, autotune, set_tile,
-                  tile_count, tile_name)
+                  tile_count, tile_name, status_word)
 from ._lib import lib, EvsError, LIB_PATH, EXPORTED
 
 __all__ = ["Net", "TNet", "Graph", "pack_weights", "forward", "forward_batched", "backward", "emd_loss",
            "compact_events", "logdiff", "contrast_events", "tnet_forward", "tnet_weight_floats", "autotune",
-           "set_tile", "tile_count", "tile_name", "lib", "EvsError", "LIB_PATH", "EXPORTED"]
+           "set_tile", "tile_count", "tile_name", "status_word", "lib", "EvsError", "LIB_PATH", "EXPORTED"]

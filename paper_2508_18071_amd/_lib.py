@@ -17,6 +17,9 @@ EVS_FP32, EVS_BF16 = 0, 1
 EVS_SURR_SIGMOID, EVS_SURR_ATAN = 0, 1
 EVS_INPUT_DIRECT, EVS_INPUT_RGB_LOGDIFF = 0, 1
 EVS_OP_FORWARD, EVS_OP_BACKWARD, EVS_OP_EMD, EVS_OP_COMPACT = range(4)
+# device status word: EVS_STATUS_WORDS int32 values
+EVS_STATUS_WORDS, EVS_STATUS_NAN_X, EVS_STATUS_NAN_GRAD, EVS_STATUS_FLAGS = 4, 0, 1, 2
+EVS_FLAG_EVENT_OVERFLOW = 1
 
 
 class EvsNet(ctypes.Structure):
@@ -65,16 +68,16 @@ _SIGS = [
     ("evs_pack_weights", ctypes.c_int, [ctypes.POINTER(EvsNet), ctypes.POINTER(_P), _P, _P]),
     ("evs_forward", ctypes.c_int,
      [ctypes.POINTER(EvsNet), _P, ctypes.POINTER(EvsClip), ctypes.c_int32, _P, ctypes.c_int32,
-      _P, ctypes.c_size_t, _P]),
+      _P, ctypes.c_size_t, _P, _P]),
     ("evs_backward", ctypes.c_int,
      [ctypes.POINTER(EvsNet), _P, ctypes.POINTER(EvsClip), _P, ctypes.c_int32, _P,
-      ctypes.POINTER(_P), _P, _P, _P, ctypes.c_size_t, _P]),
+      ctypes.POINTER(_P), _P, _P, _P, ctypes.c_size_t, _P, _P]),
     ("evs_emd_loss", ctypes.c_int,
      [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
       ctypes.c_float, _P, _P, _P, ctypes.c_size_t, _P]),
     ("evs_compact_events", ctypes.c_int,
      [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P,
-      _P, ctypes.c_size_t, _P]),
+      _P, ctypes.c_size_t, _P, _P]),
     ("evs_tnet_weight_floats", ctypes.c_size_t, [_P]),
     ("evs_tnet_forward", ctypes.c_int,
      [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),

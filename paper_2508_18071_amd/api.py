@@ -84,6 +84,19 @@ def _clip(x, s_out=None, s_fp32=False, v_state=None, h_trace=None, trace_box=Non
     return c
 
 
+def status_word(device=None) -> torch.Tensor:
+    """A zeroed device status word: int32 [EVS_STATUS_WORDS] (NaN count of x,
+    NaN count of grad_s, flags, reserved); the library adds to it."""
+    return torch.zeros(_lib.EVS_STATUS_WORDS, dtype=torch.int32, device=device or "cuda")
+
+
+def _check_status(st):
+    if st is not None:
+        _check_dev(st)
+        if st.dtype != torch.int32 or st.numel() < _lib.EVS_STATUS_WORDS:
+            raise ValueError("status must be an int32 device tensor of EVS_STATUS_WORDS values")
+
+
 def _check_dev(*ts):
     for t in ts:
         if t is not None:
@@ -126,7 +139,7 @@ def workspace(net: Net, clips, op=_lib.EVS_OP_FORWARD, ckpt_every=0, device=None
 def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = False,
             v_state: torch.Tensor | None = None, trace: bool = False, ckpt_every: int = 0,
             out: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None,
-            trace_box=None):
+            trace_box=None, status: torch.Tensor | None = None):
     """Run the network over x [N,T,Cin,H,W] (float32, on the GPU).
 
     Returns a dict: "s" [N,T,Cout,H,W] (int8 or float32), "h" (the charged
@@ -134,7 +147,8 @@ def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = F
     ckpt_every > 0).  v_state [N,sumC,H,W] is read and overwritten in place.
     ``ws`` is an optional preallocated workspace (needed under graph capture,
     where nothing may be allocated).  ``trace_box`` = (y0, x0, h, w) limits
-    the trace to that window of the frame.
+    the trace to that window of the frame.  ``status`` is an optional int32
+    device status word (see status_word()).
     """
     if x.dim() == 4:
         x = x.unsqueeze(0)
@@ -165,13 +179,15 @@ def forward(net: Net, packed: torch.Tensor, x: torch.Tensor, *, s_fp32: bool = F
     else:
         nb = ws.numel()
     cn = net.c()
+    _check_status(status)
     check(lib().evs_forward(ctypes.byref(cn), packed.data_ptr(), ctypes.byref(c), 1,
                             ck.data_ptr() if ck is not None else None, ckpt_every,
-                            ws.data_ptr() if ws is not None else None, nb, _stream(stream)), "forward")
+                            ws.data_ptr() if ws is not None else None, nb, _ptr(status), _stream(stream)),
+          "forward")
     return {"s": out, "h": h, "ckpt": ck, "_ws": ws}
 
 
-def forward_batched(net: Net, packed: torch.Tensor, xs, outs, v_states=None, stream=None, ws=None):
+def forward_batched(net: Net, packed: torch.Tensor, xs, outs, v_states=None, stream=None, ws=None, status=None):
     """One persistent launch over several clips xs[i] [N_i,T_i,Cin,H_i,W_i]."""
     clips = []
     for i, (x, o) in enumerate(zip(xs, outs)):
@@ -183,8 +199,9 @@ def forward_batched(net: Net, packed: torch.Tensor, xs, outs, v_states=None, str
     nb = lib().evs_workspace_bytes(ctypes.byref(cn), arr, len(clips), 0, _lib.EVS_OP_FORWARD)
     if ws is None or ws.numel() < nb:
         ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=xs[0].device)
+    _check_status(status)
     check(lib().evs_forward(ctypes.byref(cn), packed.data_ptr(), arr, len(clips), None, 0,
-                            ws.data_ptr(), nb, _stream(stream)), "forward_batched")
+                            ws.data_ptr(), nb, _ptr(status), _stream(stream)), "forward_batched")
     return ws
 
 
@@ -230,7 +247,7 @@ def emd_loss(s: torch.Tensor, e: torch.Tensor, lambda_count: float = 0.0, grad: 
     return loss, g
 
 
-def compact_events(s: torch.Tensor, capacity: int | None = None, stream=None):
+def compact_events(s: torch.Tensor, capacity: int | None = None, stream=None, status=None):
     """Dense int8 spikes [T,C,H,W] -> (events uint64 as int64 tensor, count)."""
     _check_dev(s)
     T, C, H, W = s.shape
@@ -243,8 +260,9 @@ def compact_events(s: torch.Tensor, capacity: int | None = None, stream=None):
     net = Net((3, C)).c()
     nb = lib().evs_workspace_bytes(ctypes.byref(net), ctypes.byref(c), 1, 0, _lib.EVS_OP_COMPACT)
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=s.device)
+    _check_status(status)
     check(lib().evs_compact_events(s.data_ptr(), T, C, H, W, ev.data_ptr(), capacity, cnt.data_ptr(),
-                                   ws.data_ptr(), nb, _stream(stream)), "compact_events")
+                                   ws.data_ptr(), nb, _ptr(status), _stream(stream)), "compact_events")
     return ev, cnt
 
 
@@ -316,7 +334,8 @@ def tnet_forward(net: TNet, weights: torch.Tensor, x: torch.Tensor, debug: bool 
     return s, d
 
 
-def backward(net: Net, packed, x, ckpt, ckpt_every, grad_s, want_dx=False, want_dv=False, stream=None):
+def backward(net: Net, packed, x, ckpt, ckpt_every, grad_s, want_dx=False, want_dv=False, stream=None,
+             status=None):
     """BPTT backward; returns (list of dW, dx or None, dv or None)."""
     if x.dim() == 4:
         x = x.unsqueeze(0)
@@ -335,7 +354,8 @@ def backward(net: Net, packed, x, ckpt, ckpt_every, grad_s, want_dx=False, want_
     arr = (ctypes.c_void_p * len(gws))(*[g.data_ptr() for g in gws])
     check(lib().evs_backward(ctypes.byref(cn), packed.data_ptr(), ctypes.byref(c), ckpt.data_ptr(), ckpt_every,
                              grad_s.data_ptr(), arr, dx.data_ptr() if dx is not None else None,
-                             dv.data_ptr() if dv is not None else None, ws.data_ptr(), nb, _stream(stream)),
+                             dv.data_ptr() if dv is not None else None, ws.data_ptr(), nb, _ptr(status),
+                             _stream(stream)),
           "backward")
     return gws, dx, dv
 

@@ -208,7 +208,7 @@ size_t evs_workspace_bytes(const evs_net* net, const evs_clip* clips, int32_t n_
 }
 
 int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, int32_t n_clips,
-                float* ckpt, int32_t ckpt_every, void* ws, size_t ws_bytes, void* stream) {
+                float* ckpt, int32_t ckpt_every, void* ws, size_t ws_bytes, int32_t* dev_status, void* stream) {
   int st = validate_net(net);
   if (st) return st;
   if (!packed) return fail(EVS_EINVAL, "packed weights are NULL");
@@ -217,9 +217,20 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
   for (int i = 0; i < n_clips; ++i)
     if ((st = validate_clip(*net, clips[i], true))) return st;
   if (ckpt && (ckpt_every < 1 || n_clips != 1)) return fail(EVS_EINVAL, "ckpt needs ckpt_every >= 1 and one clip");
+  if ((reinterpret_cast<uintptr_t>(dev_status) & 3u) != 0) return fail(EVS_EINVAL, "dev_status must be 4-byte aligned");
   const size_t need = evs_workspace_bytes(net, clips, n_clips, ckpt_every, EVS_OP_FORWARD);
   if (need > 0 && (!ws || ws_bytes < need)) return fail(EVS_EWORKSPACE, "forward workspace too small");
   hipStream_t s = (hipStream_t)stream;
+  // NaN inputs: one streaming pass over each clip's x, only when asked for
+  if (dev_status) {
+    for (int i = 0; i < n_clips; ++i) {
+      const evs_clip& c = clips[i];
+      const size_t frames = net->input == EVS_INPUT_RGB_LOGDIFF ? (size_t)c.T + 1 : (size_t)c.T;
+      const size_t chans = net->input == EVS_INPUT_RGB_LOGDIFF ? 3 : (size_t)net->ch[0];
+      if ((st = count_nan(c.x, (size_t)c.N * frames * chans * c.H * c.W, dev_status + EVS_STATUS_NAN_X, s)))
+        return st;
+    }
+  }
   const FwdNetArgs na = make_net_args(*net, packed);
   const int sumc = na.sum_c;
   char* wsp = reinterpret_cast<char*>(ws);

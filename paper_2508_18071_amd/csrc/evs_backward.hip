@@ -46,10 +46,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ hseg,
                                                  int len, int N, int HW, const float* __restrict__ G,
                                                  long long G_nstride, long long G_tstride,
                                                  float* __restrict__ gh, float* __restrict__ gv, float theta,
-                                                 float leak, float alpha, int surr, int detach) {
+                                                 float leak, float alpha, int surr, int detach,
+                                                 int32_t* __restrict__ status) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long total = (long long)N * C * HW;
   if (idx >= total) return;
+  int nan = 0;
   const int p = (int)(idx % HW);
   const int c = (int)((idx / HW) % C);
   const int n = (int)(idx / ((long long)HW * C));
@@ -58,12 +60,24 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ hseg,
   for (int t = len - 1; t >= 0; --t) {
     const float h = hseg[(((size_t)n * len + t) * sumc + choff + c) * HW + p];
     const float Gv = G[(size_t)n * G_nstride + (size_t)t * G_tstride + (size_t)c * HW + p];
+    nan += Gv != Gv ? 1 : 0;
     const float psi = surrogate(h, theta, alpha, surr);
     const float g_h = detach ? fmaf(Gv, psi, g_v) : fmaf(fmaf(-theta, g_v, Gv), psi, g_v);
     gh[(((size_t)n * len + t) * C + c) * HW + p] = g_h;
     g_v = leak * g_h;
   }
   *gvp = g_v;
+  // every element of grad_s is read by exactly one thread of one call: the
+  // NaN count of the status word (saturating)
+  if (status && nan) {
+    int old = __hip_atomic_load(status + EVS_STATUS_NAN_GRAD, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+      const int nv = old > 0x7fffffff - nan ? 0x7fffffff : old + nan;
+      const int prev = atomicCAS(status + EVS_STATUS_NAN_GRAD, old, nv);
+      if (prev == old) break;
+      old = prev;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- conv transpose
@@ -825,7 +839,7 @@ size_t backward_workspace_bytes(const evs_net& net, const evs_clip& clip, int ck
 
 int backward(const evs_net& net, const void* packed, const evs_clip& clip, const float* ckpt, int ckpt_every,
              const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v, void* ws, size_t ws_bytes,
-             hipStream_t st) {
+             int32_t* status, hipStream_t st) {
   int rc = validate_net(&net);
   if (rc) return rc;
   if (net.input != EVS_INPUT_DIRECT)
@@ -833,6 +847,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
   if ((rc = validate_clip(net, clip, true))) return rc;
   if (!packed || !ckpt || !grad_s || !grad_w) return fail(EVS_EINVAL, "backward: NULL argument");
   if (ckpt_every < 1) return fail(EVS_EINVAL, "backward: ckpt_every must be >= 1");
+  if ((reinterpret_cast<uintptr_t>(status) & 3u) != 0) return fail(EVS_EINVAL, "backward: dev_status must be 4-byte aligned");
   for (int l = 0; l < net.n_layers; ++l)
     if (!grad_w[l]) return fail(EVS_EINVAL, "backward: NULL grad_w entry");
   // the gradient kernels address a frame's planes of one layer with 32-bit
@@ -908,7 +923,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
       hipLaunchKernelGGL(k_adjoint, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, hseg, sumc,
                          choff[L - 1], C, len, N, (int)HW, grad_s + (size_t)t0 * cout * HW, (long long)T * cout * HW,
                          (long long)cout * HW, ghb[0], gv, net.theta, net.leak, net.surr_alpha, net.surrogate,
-                         net.detach_reset);
+                         net.detach_reset, status);
       EVS_HIP(hipGetLastError());
     }
     int cur = 0;

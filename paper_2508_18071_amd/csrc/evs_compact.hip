@@ -119,9 +119,11 @@ __global__ __launch_bounds__(kThreads) void k_write(const int8_t* __restrict__ s
 }
 
 // Exclusive scan of the chunk counts in one workgroup (fixed order); the
-// grand total goes to *count.
+// grand total goes to *count, and a total above the capacity sets the
+// overflow flag of the status word (if given).
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ counts, long long n,
-                                               long long* __restrict__ offsets, int64_t* __restrict__ count) {
+                                               long long* __restrict__ offsets, int64_t* __restrict__ count,
+                                               long long cap, int32_t* __restrict__ status) {
   __shared__ long long part[1024];
   const long long per = (n + 1023) / 1024;
   const long long b = threadIdx.x * per;
@@ -133,6 +135,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count
     long long run = 0;
     for (int k = 0; k < 1024; ++k) { const long long v = part[k]; part[k] = run; run += v; }
     count[0] = run;
+    if (status && run > cap) atomicOr(status + EVS_STATUS_FLAGS, EVS_FLAG_EVENT_OVERFLOW);
   }
   __syncthreads();
   long long run = part[threadIdx.x];
@@ -149,10 +152,12 @@ size_t compact_workspace_bytes(int T, int C, int H, int W) {
 }
 
 int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events, int64_t cap,
-                   int64_t* count, void* ws, size_t ws_bytes, hipStream_t st) {
+                   int64_t* count, void* ws, size_t ws_bytes, int32_t* status, hipStream_t st) {
   if (!s || !count || (cap > 0 && !events)) return fail(EVS_EINVAL, "compact_events: NULL pointer");
   if (T < 1 || C < 1 || H < 1 || W < 1 || cap < 0) return fail(EVS_EINVAL, "compact_events: bad sizes");
   if (W > 4096 || H > 4096 || C > 128) return fail(EVS_EOVERFLOW, "compact_events: x/y/channel field overflow");
+  if ((reinterpret_cast<uintptr_t>(status) & 3u) != 0)
+    return fail(EVS_EINVAL, "compact_events: dev_status must be 4-byte aligned");
   const long long HW = (long long)H * W;
   const long long cpp = (HW + kChunk - 1) / kChunk;
   const long long planes = (long long)T * C;
@@ -168,7 +173,8 @@ int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events
   const int vec = ((reinterpret_cast<uintptr_t>(s) & 15) == 0 && (HW & 15) == 0) ? 1 : 0;
   hipLaunchKernelGGL(k_count, grid, dim3(kThreads), 0, st, s, (int)HW, (int)cpp, vec, counts);
   EVS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, counts, cpp * planes, offsets, count);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, counts, cpp * planes, offsets, count, (long long)cap,
+                     status);
   EVS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_write, grid, dim3(kThreads), 0, st, s, (int)HW, W, (int)cpp, C, vec, offsets, events,
                      (long long)cap);

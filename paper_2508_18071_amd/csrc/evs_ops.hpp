@@ -10,6 +10,8 @@ int zero_i32(int32_t* p, size_t n, hipStream_t s);
 int zero_f32(float* p, size_t n, hipStream_t s);
 int copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
 int fill_uniform(float* p, size_t n, uint32_t seed, float lo, float hi, hipStream_t s);
+// adds the number of NaN values in p[0, n) to the status-word counter *word
+int count_nan(const float* p, size_t n, int32_t* word, hipStream_t s);
 
 // EMD loss (evs_emd.hip)
 size_t emd_workspace_bytes(int N, int T, int C, int H, int W);
@@ -19,7 +21,7 @@ int emd_loss(const float* s, const int8_t* e, int N, int T, int C, int H, int W,
 // event compaction (evs_compact.hip)
 size_t compact_workspace_bytes(int T, int C, int H, int W);
 int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events, int64_t cap,
-                   int64_t* count, void* ws, size_t ws_bytes, hipStream_t st);
+                   int64_t* count, void* ws, size_t ws_bytes, int32_t* status, hipStream_t st);
 
 // the paper's temporal EvSNet (evs_tnet.hip)
 size_t tnet_weight_floats();
@@ -34,7 +36,7 @@ int contrast_events(const float* rgb, int N, int T, int H, int W, float scale, f
 size_t backward_workspace_bytes(const evs_net& net, const evs_clip& clip, int ckpt_every);
 int backward(const evs_net& net, const void* packed, const evs_clip& clip, const float* ckpt,
              int ckpt_every, const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v,
-             void* ws, size_t ws_bytes, hipStream_t st);
+             void* ws, size_t ws_bytes, int32_t* status, hipStream_t st);
 
 // tile selection (evs_api.cpp); the autotuner (evs_autotune.cpp)
 void load_tile_cache_once();

@@ -57,3 +57,57 @@ int fill_uniform(float* p, size_t n, uint32_t seed, float lo, float hi, hipStrea
   return EVS_OK;
 }
 }  // namespace evs
+
+namespace evs {
+namespace {
+// Adds n to a status-word counter, saturating at INT32_MAX.
+__device__ inline void sat_add(int32_t* word, unsigned n) {
+  int old = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const int nv = (unsigned)old + n > 0x7fffffffu ? 0x7fffffff : old + (int)n;
+    const int prev = atomicCAS(word, old, nv);
+    if (prev == old) return;
+    old = prev;
+  }
+}
+
+// NaN values among p[0, n): 16-byte loads over the aligned body (vec), one
+// count per workgroup added to *word.
+__global__ __launch_bounds__(256) void k_count_nan(const float* __restrict__ p, size_t n, int vec,
+                                                   int32_t* __restrict__ word) {
+  unsigned c = 0;
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t i0 = blockIdx.x * (size_t)256 + threadIdx.x;
+  size_t body = 0;
+  if (vec) {
+    body = n / 4;
+    const float4* q = reinterpret_cast<const float4*>(p);
+    for (size_t i = i0; i < body; i += stride) {
+      const float4 v = q[i];
+      c += (v.x != v.x) + (v.y != v.y) + (v.z != v.z) + (v.w != v.w);
+    }
+    body *= 4;
+  }
+  for (size_t i = body + i0; i < n; i += stride) c += p[i] != p[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+  __shared__ unsigned part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned tot = part[0] + part[1] + part[2] + part[3];
+    if (tot) sat_add(word, tot);
+  }
+}
+}  // namespace
+
+int count_nan(const float* p, size_t n, int32_t* word, hipStream_t s) {
+  if (n == 0) return EVS_OK;
+  const int vec = (reinterpret_cast<uintptr_t>(p) & 15) == 0 ? 1 : 0;
+  size_t g = (n + 256 * 16 - 1) / (256 * 16);
+  g = g < 2048 ? (g ? g : 1) : 2048;
+  hipLaunchKernelGGL(k_count_nan, dim3((unsigned)g), dim3(256), 0, s, p, n, vec, word);
+  EVS_HIP(hipGetLastError());
+  return EVS_OK;
+}
+}  // namespace evs

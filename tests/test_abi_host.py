@@ -67,7 +67,7 @@ def test_forward_rejects_bad_networks_before_launch(evs, kw, code):
     c.N, c.T, c.H, c.W = 1, 4, 8, 8
     c.x = 16  # never dereferenced: validation fails first
     st = evs.lib().evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0,
-                               None, 0, None)
+                               None, 0, None, None)
     assert st == code
     assert evs.lib().evs_last_error()
 
@@ -79,7 +79,7 @@ def test_forward_rejects_unknown_surrogate(evs):
     c.N, c.T, c.H, c.W = 1, 4, 8, 8
     c.x = 16
     st = evs.lib().evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0,
-                               None, 0, None)
+                               None, 0, None, None)
     assert st == 1
     assert b"surrogate" in evs.lib().evs_last_error()
 
@@ -110,20 +110,20 @@ def test_forward_rejects_bad_clips_and_workspace(evs):
     c = evs._lib.EvsClip()
     c.N, c.T, c.H, c.W = 1, 0, 8, 8
     c.x = 16
-    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None) == 1
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None, None) == 1
     c.T = 4
     c.x = None
-    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None) == 1
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None, None) == 1
     c.x = 16
     c.v_state = 32           # needs a workspace copy of the initial state
-    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None) == 3
-    assert L.evs_forward(ctypes.byref(net), None, ctypes.byref(c), 1, None, 0, None, 0, None) == 1
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None, None) == 3
+    assert L.evs_forward(ctypes.byref(net), None, ctypes.byref(c), 1, None, 0, None, 0, None, None) == 1
     # checkpoints need ckpt_every >= 1
     c.v_state = None
     assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1,
-                         ctypes.c_void_p(64), 0, None, 0, None) == 1
+                         ctypes.c_void_p(64), 0, None, 0, None, None) == 1
     c.H = 5000
-    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None) == 2
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0, None, None) == 2
 
 
 def test_workspace_sizes(evs):
@@ -162,7 +162,7 @@ def test_forward_rejects_bad_rgb_input(evs, kw, field, code):
     c.N, c.T, c.H, c.W = 1, 4, 8, 8
     c.x = 16
     st = evs.lib().evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0,
-                               None, 0, None)
+                               None, 0, None, None)
     assert st == code
     assert evs.lib().evs_last_error()
 
@@ -179,7 +179,7 @@ def test_backward_rejects_rgb_input(evs):
         ctypes.c_size_t(-1).value
     arr = (ctypes.c_void_p * 2)(16, 16)
     st = L.evs_backward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), ctypes.c_void_p(16), 2,
-                        ctypes.c_void_p(16), arr, None, None, ctypes.c_void_p(16), 1 << 20, None)
+                        ctypes.c_void_p(16), arr, None, None, ctypes.c_void_p(16), 1 << 20, None, None)
     assert st == 2
     assert b"evs_logdiff" in L.evs_last_error()
 
@@ -212,3 +212,46 @@ def test_tnet_rejects_null_pointers(evs):
     assert L.evs_tnet_forward(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 4, 4, 4, ctypes.c_void_p(16),
                               None, None) == 1
     assert L.evs_tnet_weight_floats(ctypes.byref(net)) == 16 * 7 + 16 + 6 * (16 * 16 * 7 + 16) + 16 + 1
+
+
+def test_misaligned_status_word_is_rejected_before_launch(evs):
+    """The device status word is optional (NULL records nothing); a pointer
+    that cannot hold int32 words is refused on the host."""
+    L = evs.lib()
+    net = _net(evs, channels=(3, 16, 16, 2))
+    c = evs._lib.EvsClip()
+    c.N, c.T, c.H, c.W = 1, 4, 8, 8
+    c.x = 16
+    assert L.evs_forward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), 1, None, 0, None, 0,
+                         ctypes.c_void_p(18), None) == 1
+    assert b"dev_status" in L.evs_last_error()
+    arr = (ctypes.c_void_p * 3)(16, 16, 16)
+    assert L.evs_backward(ctypes.byref(net), ctypes.c_void_p(16), ctypes.byref(c), ctypes.c_void_p(16), 2,
+                          ctypes.c_void_p(16), arr, None, None, ctypes.c_void_p(16), 1 << 30,
+                          ctypes.c_void_p(18), None) == 1
+    assert L.evs_compact_events(ctypes.c_void_p(16), 4, 2, 8, 8, ctypes.c_void_p(16), 10, ctypes.c_void_p(16),
+                                ctypes.c_void_p(16), 1 << 20, ctypes.c_void_p(2), None) == 1
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the behaviour without a GPU; on a GPU box the call would "
+                                           "really run with the placeholder pointers")
+def test_no_gpu_reports_hip_error_with_message(evs):
+    """Without a GPU, a call with valid arguments gets past validation and
+    reports the HIP runtime's failure as EVS_EHIP with a message."""
+    L = evs.lib()
+    st = L.evs_logdiff(ctypes.c_void_p(256), 1, 2, 4, 4, 255.0, 20.0, ctypes.c_void_p(512), None)
+    assert st == 4
+    msg = L.evs_last_error()
+    assert b"hip" in msg.lower(), msg
+    net = _net(evs, channels=(3, 8, 2))
+    arr = (ctypes.c_void_p * 2)(256, 512)
+    assert L.evs_pack_weights(ctypes.byref(net), arr, ctypes.c_void_p(1024), None) == 4
+    assert L.evs_last_error()

@@ -232,3 +232,34 @@ def test_inference_kernel_equals_traced_kernel_and_trace_window(evs, channels, p
     assert torch.equal(fast["s"], full["s"])
     assert torch.equal(win["s"], full["s"])
     assert torch.equal(win["h"], full["h"][:, :, :, 13:33, 29:60])
+
+
+@pytest.mark.parametrize("channels,prec", [((3, 16, 16, 2), "fp32"), ((3, 16, 16, 2), "bf16"),
+                                           ((3, 32, 2), "bf16"), ((3, 32, 2), "fp32"), ((3, 8, 2), "fp32")])
+@pytest.mark.parametrize("T", [4, 7])
+def test_every_tile_inference_kernel_equals_traced_kernel(evs, channels, prec, T):
+    """The inference build of every compiled tile shape (the kernels the
+    autotuner may pick) gives the spikes of the traced build, which the
+    teacher-forced parity tests hold to the oracle, bit for bit."""
+    H, W = 70, 90
+    x, ws = make_inputs(channels, T, H, W, N=2)
+    net = evs.Net(channels, theta=THETA, leak=LEAK, precision=prec)
+    packed = evs.pack_weights(net, [torch.from_numpy(w).cuda() for w in ws])
+    xg = x.cuda()
+    n = evs.tile_count(net)
+    bad = []
+    try:
+        evs.set_tile(net, 0)
+        ref = evs.forward(net, packed, xg, trace=True)["s"]
+        for t in range(n):
+            evs.set_tile(net, t)
+            o = evs.forward(net, packed, xg)["s"]
+            torch.cuda.synchronize()
+            if not torch.equal(o, ref):
+                d = (o != ref)
+                frames = sorted(set(torch.nonzero(d)[:, 1].tolist()))
+                bad.append((evs.tile_name(net, t), int(d.sum()), frames))
+    finally:
+        evs.set_tile(net, -1)
+    print(f"  {channels} {prec} T={T}: {n} tiles, differing: {bad}", flush=True)
+    assert not bad

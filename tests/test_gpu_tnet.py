@@ -186,3 +186,81 @@ def test_tnet_full_720p_sampled_pixels(evs):
           f"rate {np.abs(s_px).mean():.3f}", flush=True)
     assert agree >= 0.99
     assert 0.05 < np.abs(s_px).mean() < 0.95
+
+
+def _bf16_error_sigma(x, p):
+    """Unquantised FP64 reference u of the temporal EvSNet and the standard
+    deviation of the BF16 form's deviation from it under the probabilistic
+    model of rounding errors (each rounding independent, uniform within half
+    a unit): the BF16 form rounds the input, every weight and every stored
+    activation to bfloat16 (variance (2^-9)^2 / 3 relative each); a conv adds
+    the variances of its terms (sum w^2 var(h) + sum var(w) h^2), a ReLU does
+    not increase them, the residual add sums them.  The FP32 sums (2^-24) are
+    below this by far.  x [P][T] -> (u [P][T], sigma [P][T])."""
+    v = (2.0 ** -9) ** 2 / 3.0
+    conv = lambda h, w: tnet.conv1d(h, w, np.zeros(w.shape[0]))
+    a64 = lambda a: np.asarray(a, np.float64)
+
+    def layer(h, V, w, b):
+        w = a64(w)
+        return conv(h, w) + a64(b)[None, :, None], conv(V, w * w) + v * conv(h * h, w * w)
+
+    x = a64(x)[:, None, :]
+    pre, V = layer(x, v * x * x, p["w0"], p["b0"])
+    h = np.maximum(pre, 0.0)
+    V = V + v * h * h
+    for i in range(1, 4):
+        pa, Va = layer(h, V, p["w"][2 * i - 1], p["b"][2 * i - 1])
+        a = np.maximum(pa, 0.0)
+        Va = Va + v * a * a
+        pb, Vb = layer(a, Va, p["w"][2 * i], p["b"][2 * i])
+        h = np.maximum(h + pb, 0.0)
+        V = V + Vb + v * h * h
+    wp = a64(p["wp"])
+    u = np.einsum("c,pct->pt", wp, h) + p["bp"]
+    Vu = np.einsum("c,pct->pt", wp * wp, V) + v * np.einsum("c,pct->pt", wp * wp, h * h)
+    return u, np.sqrt(Vu)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_tnet_against_unquantised_oracle(evs, seed):
+    """BF16 kernel against the unquantised FP64 oracle (quant=False).
+
+    Tolerance: 8 standard deviations of the rounding-error model of
+    _bf16_error_sigma per pixel and frame (the oracle's own BF16 mode stays
+    within 5 of them on 51k outputs), and 2e-2 of max|u| overall (the BF16
+    membrane gate).  The projection u must lie within it; the charged
+    potential h, teacher-forced from the kernel's own previous state, too;
+    and a spike may differ from the reference's only where the reference
+    potential lies within that tolerance of a threshold."""
+    N, T, H, W = 1, 200, 16, 16
+    p, flat, net, x = _setup(evs, N, T, H, W, seed=seed)
+    s, d = _run(evs, net, flat, x)
+    P = H * W
+    D = d[0].reshape(T, 7 * C + 2, P).transpose(2, 1, 0)
+    u_gpu, h_gpu = D[:, 7 * C, :], D[:, 7 * C + 1, :]
+    u_ref, sig = _bf16_error_sigma(x[0].reshape(T, P).T, p)
+    Eu = 8.0 * sig + 1e-6 * np.abs(u_ref)
+    err = np.abs(u_gpu - u_ref)
+    rel = float(err.max() / np.abs(u_ref).max())
+    print(f"  tnet vs unquantised oracle: u max rel {rel:.2e}, worst err/sigma {float((err / sig).max()):.2f}, "
+          f"mean err/sigma {float((err / sig).mean()):.3f}", flush=True)
+    assert np.all(err <= Eu)
+    assert rel <= 2e-2
+    v = np.zeros(P)
+    mism = outside = 0
+    sg = s[0].reshape(T, P).astype(np.float64)
+    for t in range(T):
+        h_ref = LEAK * v + u_ref[:, t]
+        eh = np.abs(h_gpu[:, t] - h_ref)
+        bound = Eu[:, t] + 1e-6 * (np.abs(h_ref) + 1e-6)
+        assert np.all(eh <= bound), (t, float((eh - bound).max()))
+        sr = evsnet.fire(h_ref, THETA)
+        m = sg[t] != sr
+        mism += int(m.sum())
+        outside += int((m & (evsnet.spike_margin(h_ref, THETA) > bound)).sum())
+        v = h_gpu[:, t] - THETA * sg[t]
+    print(f"  teacher-forced spikes vs unquantised oracle: {mism} of {T * P} differ, "
+          f"{outside} outside the error band", flush=True)
+    assert outside == 0
+    assert mism <= 0.01 * T * P
