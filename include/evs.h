@@ -254,6 +254,19 @@ int evs_emd_loss(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t 
                  int32_t H, int32_t W, float lambda_count, float* loss, float* grad_s,
                  void* ws, size_t ws_bytes, void* stream);
 
+/* evs_emd_loss without a workspace, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight training loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * evs_emd_loss; its scratch (the per-block partial losses) is a static
+ * device array of 1 MiB that every GPU the library runs on holds until the
+ * process ends, so N x H x W is limited to 2^25 pixels (EVS_EWORKSPACE
+ * above that).  Allocates nothing on any call.  Every call on one GPU uses
+ * that GPU's one array: calls that overlap on one GPU (other streams,
+ * threads) race and must be serialised by the caller.                    */
+int evs_emd_loss_noalloc(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t C,
+                         int32_t H, int32_t W, float lambda_count, float* loss, float* grad_s,
+                         void* stream);
+
 /* Dense spikes -> event list in (t, c, y, x) order (Sec. 3.1 event tuples).
  *   s         [T][C][H][W] int8 spikes
  *   events    device uint64 array of `capacity` records (format above)

@@ -75,6 +75,9 @@ _SIGS = [
     ("evs_emd_loss", ctypes.c_int,
      [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
       ctypes.c_float, _P, _P, _P, ctypes.c_size_t, _P]),
+    ("evs_emd_loss_noalloc", ctypes.c_int,
+     [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+      ctypes.c_float, _P, _P, _P]),
     ("evs_compact_events", ctypes.c_int,
      [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P,
       _P, ctypes.c_size_t, _P, _P]),

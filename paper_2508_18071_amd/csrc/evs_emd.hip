@@ -9,6 +9,8 @@
 // keep the per-thread state O(1) for any T; reads are coalesced across the
 // pixel dimension.  Per-thread losses are summed in a fixed order (block
 // tree, then one block over the partials), so the loss is reproducible.
+#include <mutex>
+
 #include "evs_ops.hpp"
 
 namespace evs {
@@ -130,25 +132,93 @@ size_t emd_workspace_bytes(int N, int T, int C, int H, int W) {
   return align256((size_t)blocks * sizeof(double));
 }
 
-int emd_loss(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda,
-             float* loss, float* grad, void* ws, size_t ws_bytes, hipStream_t st) {
+namespace {
+
+int emd_check(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda, float* loss) {
   if (!s || !e || !loss) return fail(EVS_EINVAL, "emd_loss: s, e and loss must be non-NULL");
   if (N < 1 || T < 1 || H < 1 || W < 1) return fail(EVS_EINVAL, "emd_loss: sizes must be >= 1");
   if (C != 1 && C != 2) return fail(EVS_EUNSUPPORTED, "emd_loss: C must be 1 or 2");
   if ((long long)H * W > (1LL << 30)) return fail(EVS_EOVERFLOW, "emd_loss: frame too large");
+  if ((long long)N * H * W > (1LL << 38)) return fail(EVS_EOVERFLOW, "emd_loss: too many pixels");
   if (!(lambda >= 0.f)) return fail(EVS_EINVAL, "emd_loss: lambda must be >= 0");
-  const size_t need = emd_workspace_bytes(N, T, C, H, W);
-  if (!ws || ws_bytes < need) return fail(EVS_EWORKSPACE, "emd_loss: workspace too small");
-  const long long px = (long long)N * H * W;
-  const long long blocks = (px + kThreads - 1) / kThreads;
-  if (blocks > (1LL << 30)) return fail(EVS_EOVERFLOW, "emd_loss: too many pixels");
-  double* partial = reinterpret_cast<double*>(ws);
+  return EVS_OK;
+}
+
+int emd_launch(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda, float* loss,
+               float* grad, double* partial, hipStream_t st) {
+  const long long blocks = ((long long)N * H * W + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_emd, dim3((unsigned)blocks), dim3(kThreads), 0, st, s, e, N, T, C, H * W, lambda, grad,
                      partial);
   EVS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, (int)blocks, loss);
   EVS_HIP(hipGetLastError());
   return EVS_OK;
+}
+
+// Static scratch of the allocation-free entry point: the per-block partial
+// losses, one double per 256 pixels of N x H x W, fully rewritten by every
+// call (nothing has to start at zero).  Every GPU the library runs on holds
+// its own copy until the process ends; calls that overlap on one GPU share
+// it and race.
+constexpr long long kScratchBlocks = 1 << 17;            // 1 MiB: N x H x W up to 2^25 pixels
+static __device__ __align__(256) double scratch[kScratchBlocks];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices];
+
+// This GPU's scratch array, looked up once per device with that device
+// current (the array's name is a host-side stand-in, not a device address);
+// nullptr with the message set on failure.
+double* scratch_on_current_device() {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) {
+    hip_check(err, "hipGetDevice");
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    fail(EVS_EUNSUPPORTED, "emd_loss_noalloc: device index above 63");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) {
+      hip_check(err, "hipGetSymbolAddress(scratch)");
+      return nullptr;
+    }
+    if (!ptr) {
+      fail(EVS_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = reinterpret_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+int emd_loss(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda,
+             float* loss, float* grad, void* ws, size_t ws_bytes, hipStream_t st) {
+  int rc = emd_check(s, e, N, T, C, H, W, lambda, loss);
+  if (rc) return rc;
+  const size_t need = emd_workspace_bytes(N, T, C, H, W);
+  if (!ws || ws_bytes < need) return fail(EVS_EWORKSPACE, "emd_loss: workspace too small");
+  return emd_launch(s, e, N, T, C, H, W, lambda, loss, grad, reinterpret_cast<double*>(ws), st);
+}
+
+int emd_loss_noalloc(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda, float* loss,
+                     float* grad, hipStream_t st) {
+  int rc = emd_check(s, e, N, T, C, H, W, lambda, loss);
+  if (rc) return rc;
+  if ((long long)N * H * W > kScratchBlocks * kThreads)
+    return fail(EVS_EWORKSPACE, "emd_loss_noalloc: N x H x W above 2^25 pixels, the size of its static scratch "
+                                "(evs_emd_loss takes a workspace of any size)");
+  double* partial = scratch_on_current_device();
+  if (!partial) return EVS_EHIP;
+  return emd_launch(s, e, N, T, C, H, W, lambda, loss, grad, partial, st);
 }
 
 }  // namespace evs

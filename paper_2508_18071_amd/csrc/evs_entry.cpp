@@ -14,6 +14,10 @@ int evs_emd_loss(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t 
                  float lambda_count, float* loss, float* grad_s, void* ws, size_t wsb, void* stream) {
   return evs::emd_loss(s, e, N, T, C, H, W, lambda_count, loss, grad_s, ws, wsb, (hipStream_t)stream);
 }
+int evs_emd_loss_noalloc(const float* s, const int8_t* e, int32_t N, int32_t T, int32_t C, int32_t H, int32_t W,
+                         float lambda_count, float* loss, float* grad_s, void* stream) {
+  return evs::emd_loss_noalloc(s, e, N, T, C, H, W, lambda_count, loss, grad_s, (hipStream_t)stream);
+}
 int evs_compact_events(const int8_t* s, int32_t T, int32_t C, int32_t H, int32_t W, uint64_t* events,
                        int64_t capacity, int64_t* count, void* ws, size_t wsb, int32_t* dev_status, void* stream) {
   return evs::compact_events(s, T, C, H, W, events, capacity, count, ws, wsb, dev_status, (hipStream_t)stream);

@@ -17,6 +17,8 @@ int count_nan(const float* p, size_t n, int32_t* word, hipStream_t s);
 size_t emd_workspace_bytes(int N, int T, int C, int H, int W);
 int emd_loss(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda,
              float* loss, float* grad, void* ws, size_t ws_bytes, hipStream_t st);
+int emd_loss_noalloc(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda,
+                     float* loss, float* grad, hipStream_t st);
 
 // event compaction (evs_compact.hip)
 size_t compact_workspace_bytes(int T, int C, int H, int W);
