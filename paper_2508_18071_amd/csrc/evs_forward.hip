@@ -89,7 +89,14 @@ struct Cfg {
   // each weight (scaled by a power of two per layer) as two fp16 parts
   static constexpr bool SF16 = !BF16 && !RELAX;
   static constexpr int NSP = BF16 ? 1 : 2;           // parts of a spike-conv weight
-  static constexpr bool OMF = S16 && NH >= 1;        // output layer on MFMA
+  // Output layer (1-2 channels) of nets with one hidden layer, or two of
+  // width 16, in tap-major form: per block of the last hidden layer,
+  // Y[(tap, co)][pixel] = sum_ci W[co][ci][tap] s[ci][pixel] on MFMA (rows
+  // tap * 2 + co, 18 of 32 live; the spike operand comes from the registers
+  // of that layer's epilogue), stored to LDS; the output potential of a
+  // pixel is then the sum of the 9 Y values of its neighbourhood.
+  static constexpr bool OTAP = S16 && (NH == 1 || (NH == 2 && CH == 16));
+  static constexpr bool OMF = S16 && NH >= 1 && !OTAP;   // output layer on MFMA, rows (channel, part)
   static constexpr int KB = CH == 32 ? 9 : 5;        // spike-operand k-steps (32 of K = 9*CH each)
   static constexpr int NBO = OMF ? cdiv(nblk(NL), NW) : 1;
   // tail lanes of a layer's last block read around and write to this
@@ -136,14 +143,29 @@ struct Cfg {
   // bf16 spikes are stored as CH/8 planes of [pixel][8 channels] (16 B per
   // pixel): the 16 lanes of a lane group then read 256 contiguous bytes
   static constexpr int SPL = NPIXL * 16;             // bytes of one 8-channel plane
-  static constexpr int SP1_BYTES = NH >= 1 ? (S16 ? SPL * (CH / 8) : align16(NPIXL * CH * SELEM)) : 0;
+  // (the spikes of the last hidden layer of tap-major nets never reach LDS)
+  static constexpr int SP1_BYTES =
+      NH >= 1 && !(OTAP && NH == 1) ? (S16 ? SPL * (CH / 8) : align16(NPIXL * CH * SELEM)) : 0;
   // separate layer-2 spike buffer: saves two barriers per frame
-  static constexpr bool SEP = NH == 2 && CH == 16 && S16;
+  static constexpr bool SEP = NH == 2 && CH == 16 && S16 && !OTAP;
+  // tap-major output layer: Y planes over the last hidden layer's region,
+  // one float2 (co 0, 1) per tap and pixel, plane length NYPL = NYP + a
+  // junk slot for the tail lanes of the last block, rounded to 8 mod 16
+  // pixels (the two taps a lane group stores together then fill different
+  // banks)
+  static constexpr int NYP = OTAP ? rgh(NH) * rgw(NH) : 0;
+  static constexpr int NYPL = OTAP ? (NYP + 8) / 16 * 16 + 8 : 0;
+  static constexpr int YS_BYTES = OTAP ? 9 * NYPL * 8 : 0;
+  static constexpr int KY = (OTAP && SF16 && CH == 32) ? 2 : 1;     // k-steps of the Y product
+  // region row length and the column of output column 0 in it
+  static constexpr int YRW = OTAP ? rgw(NH) : 1;
+  static constexpr int YC0 = OTAP ? NL - ((L1LIN && NH == 1) ? 0 : NH) : 0;
   static constexpr int S2OFF = SEP ? SP1_BYTES : 0;
   static constexpr int SP_BYTES = SP1_BYTES * (SEP ? 2 : 1);
-  static constexpr int WL_FLOATS = OMF ? 0 : 9 * (NH >= 1 ? CH : CIN) * CO;
+  static constexpr int WL_FLOATS = (OMF || OTAP) ? 0 : 9 * (NH >= 1 ? CH : CIN) * CO;
   static_assert(CH == 16 || CH == 32, "hidden width must be padded to 16 or 32");
   static_assert(NB1 <= 32 && NB2 <= 32 && NBO <= 32 && NOUT <= 32, "mask words overflow");
+  static_assert(!OTAP || (NYPL % 16 == 8 && NYPL >= NYP + 1), "Y plane length");
   static_assert(PADF + JP + CWT + 1 < NPIXL, "junk pixel neighbourhood outside the planes");
   static_assert(!L1LIN || PADF + CIN * XPL + 2 * CWT + 16 * NW * NB1 < XS1 / XELEM,
                 "linear layer-1 gathers outside the x buffer");
@@ -295,7 +317,10 @@ struct Layout {
       C::NH >= 2 ? (C::S16 ? C::KB * C::NSP * C::MB * 64 * 16 : 9 * (C::CH / 16) * C::MB * 64 * 16) : 0;
   static constexpr int FR3 = FR2 + FR2_BYTES;                   // output-layer A fragments
   static constexpr int FR3_BYTES = C::OMF ? C::KB * 64 * 16 : 0;
-  static constexpr int XDUMMY = FR3 + FR3_BYTES;                // target of the padding x loads
+  static constexpr int FRY = FR3 + FR3_BYTES;                   // tap-major output: Y A fragments
+  static constexpr int FRY_BYTES = C::OTAP ? 2 * C::KY * 64 * 16 : 0;
+  static constexpr int YS = FRY + FRY_BYTES;                    // Y planes [9][NYPL][2] f32
+  static constexpr int XDUMMY = YS + C::YS_BYTES;               // target of the padding x loads
   static constexpr int SCL = XDUMMY + (C::XDMA ? 256 : 0);      // |w|max bits of the spike convs (u32 x 2)
   static constexpr int TOTAL = SCL + 16;
   static_assert(TOTAL <= 160 * 1024, "tile does not fit in LDS");
@@ -332,7 +357,7 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
     }
     __syncthreads();
   }
-  if constexpr (!C::OMF) {
+  if constexpr (!C::OMF && !C::OTAP) {
     float* wl = reinterpret_cast<float*>(lds + Lo::WL);
     const int cin = na.ch[L], cout = na.ch[L + 1];
     constexpr int CI = C::NH >= 1 ? C::CH : C::CIN;
@@ -422,6 +447,42 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
       }
     }
   }
+  if constexpr (C::OTAP) {
+    // tap-major output layer: entry ((rb, ks), lane) is the A fragment of
+    // row-block rb, k-step ks; row r = 16 rb + lane%16 is (tap r/2, channel
+    // r%2).  K slot 8g + e of lane group g (e = 0..7) holds input channel
+    //   16 wide: 4g + e%4, weight part e/4 (FP32) or zero for e >= 4 (BF16)
+    //   32 wide: 4g + e for e < 4, 16 + 4g + e - 4 for e >= 4, part ks (FP32)
+    // which are the channels the epilogue's registers hold for that lane
+    // group (rows 4g..4g+3 of each 16-channel accumulator block).
+    const int cin = na.ch[L], cout = na.ch[L + 1];
+    const float sc = spike_scale<C>(lds, 1);
+    for (int e = threadIdx.x; e < 2 * C::KY * 64; e += C::NT) {
+      const int lane = e % 64, ks = (e / 64) % C::KY, rb = e / (64 * C::KY);
+      const int r = 16 * rb + (lane & 15), g = lane >> 4;
+      const int tau = r >> 1, co = r & 1;
+      unsigned wd[4];
+      for (int e2 = 0; e2 < 4; ++e2) {
+        float ww[2];
+        for (int h = 0; h < 2; ++h) {
+          const int el = 2 * e2 + h;
+          int ci, part;
+          if constexpr (C::CH == 32) {
+            ci = el < 4 ? 4 * g + el : 16 + 4 * g + el - 4;
+            part = ks;
+          } else {
+            ci = 4 * g + (el & 3);
+            part = C::SF16 ? (el >> 2) : (el < 4 ? 0 : C::NSP);
+          }
+          const bool real = tau < 9 && co < cout && ci < cin && part < C::NSP;
+          if constexpr (C::SF16) ww[h] = real ? wpart16(wget(na, L, co, ci, tau), sc, part) : 0.f;
+          else ww[h] = real ? round_bf16(wget(na, L, co, ci, tau)) : 0.f;
+        }
+        wd[e2] = C::SF16 ? pack_f16x2(ww[0], ww[1]) : pack_bf16x2(ww[0], ww[1]);
+      }
+      reinterpret_cast<u4*>(lds + Lo::FRY)[e] = u4{wd[0], wd[1], wd[2], wd[3]};
+    }
+  }
   if constexpr (C::OMF) {
     // output layer: row i = 4 co + p holds part p of output channel co
     const int cin = na.ch[L], cout = na.ch[L + 1];
@@ -489,11 +550,15 @@ __device__ __forceinline__ int block_pixel(int l, int b, int j, int gy0, int gx0
 
 // Hidden-layer epilogue for one 16-pixel block: st holds the charged
 // potentials h of MB x 4 (channel, pixel) pairs of this lane; fire, reset,
-// write spikes to LDS and, optionally, h to the trace.
-template <class C>
+// write spikes to LDS and, optionally, h to the trace.  TOY (the last hidden
+// layer of a tap-major net): the spikes are not stored; they are the B
+// operand of the Y product of this block (fragments ay), whose rows are
+// stored to the Y planes at region pixel yq.
+template <class C, bool TOY = false>
 __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int sp_off, int p, bool valid, int g,
                                                 float theta, float alpha, int relaxed, float* trace_t, float tscale,
-                                                int cl, int choff, int gy0, int gx0, const TraceBox& tb) {
+                                                int cl, int choff, int gy0, int gx0, const TraceBox& tb,
+                                                const u4 (*ay)[C::KY] = nullptr, int yq = 0) {
   if (C::FULL && trace_t && valid) {
     const int row = (p - C::PADF) / C::CWT, col = (p - C::PADF) % C::CWT;
     const int gy = gy0 + row, gx = gx0 + col;
@@ -508,6 +573,7 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
         }
     }
   }
+  uint2 sw[C::MB];
 #pragma unroll
   for (int m = 0; m < C::MB; ++m) {
     f4 s;
@@ -524,14 +590,45 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
       if (!valid) s = f4{0.f, 0.f, 0.f, 0.f};
     }
     if constexpr (C::S16) {
-      const uint2 w2 = C::SF16 ? uint2{pack_f16x2(s[0], s[1]), pack_f16x2(s[2], s[3])}
-                               : uint2{pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
+      sw[m] = C::SF16 ? uint2{pack_f16x2(s[0], s[1]), pack_f16x2(s[2], s[3])}
+                      : uint2{pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
       // channels 16m + 4g .. +3: plane 2m + g/2, half (g & 1) of the pixel's 16 bytes
-      *reinterpret_cast<uint2*>(lds + Layout<C>::SP + sp_off + (2 * m + (g >> 1)) * C::SPL + p * 16 + 8 * (g & 1)) = w2;
+      if constexpr (!TOY)
+        *reinterpret_cast<uint2*>(lds + Layout<C>::SP + sp_off + (2 * m + (g >> 1)) * C::SPL + p * 16 + 8 * (g & 1)) =
+            sw[m];
     } else {
       *reinterpret_cast<f4*>(lds + Layout<C>::SP + sp_off + ((size_t)p * C::CH + 16 * m + 4 * g) * 4) = s;
     }
   }
+  if constexpr (TOY) {
+    // B operand: K slots 8g..8g+7 of column j are this lane's spikes (the
+    // 16-wide form repeats them for the second weight part, or for zero
+    // weights)
+    const u4 b = C::MB == 2 ? u4{sw[0].x, sw[0].y, sw[C::MB - 1].x, sw[C::MB - 1].y}
+                            : u4{sw[0].x, sw[0].y, sw[0].x, sw[0].y};
+    f4 y0 = {0.f, 0.f, 0.f, 0.f}, y1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < C::KY; ++ks) {
+      y0 = mfma_sp<C>(ay[0][ks], b, y0);
+      y1 = mfma_sp<C>(ay[1][ks], b, y1);
+    }
+    // rows 4g..4g+3 of row-block 0 are taps 2g and 2g+1 (channels 0, 1);
+    // rows 16, 17 (lane group 0 of row-block 1) tap 8
+    float* const ys = reinterpret_cast<float*>(lds + Layout<C>::YS);
+    *reinterpret_cast<float2*>(ys + ((2 * g) * C::NYPL + yq) * 2) = float2{y0[0], y0[1]};
+    *reinterpret_cast<float2*>(ys + ((2 * g + 1) * C::NYPL + yq) * 2) = float2{y0[2], y0[3]};
+    if (g == 0) *reinterpret_cast<float2*>(ys + (8 * C::NYPL + yq) * 2) = float2{y1[0], y1[1]};
+  }
+}
+
+// A fragments of the tap-major Y product (row-block, k-step) for this lane.
+template <class C>
+__device__ __forceinline__ void load_yfrag(const char* lds, int lane, u4 (&ay)[2][C::KY]) {
+  const u4* f = reinterpret_cast<const u4*>(lds + Layout<C>::FRY) + lane;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int ks = 0; ks < C::KY; ++ks) ay[rb][ks] = f[(rb * C::KY + ks) * 64];
 }
 
 // True for a canvas pixel of the tile interior (an output pixel of the tile).
@@ -654,7 +751,10 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     const int q = tid + C::NT * k;
     const int ty = q / C::TW, tx = q % C::TW;
     const bool inq = q < C::TH * C::TW;
-    op[k] = C::PADF + (inq ? (C::NL + ty) * C::CWT + (C::NL + tx) : C::NL * C::CWT + C::NL);
+    // LDS canvas pixel (VALU output layer), or the pixel's index in the Y
+    // planes (tap-major output layer; idle lanes take output pixel 0)
+    if constexpr (C::OTAP) op[k] = (C::NL - C::NH + (inq ? ty : 0)) * C::YRW + C::YC0 + (inq ? tx : 0);
+    else op[k] = C::PADF + (inq ? (C::NL + ty) * C::CWT + (C::NL + tx) : C::NL * C::CWT + C::NL);
     const int gy = tl.ty0 + ty, gx = tl.tx0 + tx;
     ovm |= ((inq && gy < H && gx < W) ? 1u : 0u) << k;
   }
@@ -682,7 +782,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
 #pragma unroll
       for (int co = 0; co < 2; ++co)
-        if (co < cout) so[k][co] = vin[(size_t)(choffo + co) * HW + pix];
+        if (co < cout) so[k][co] = vin[(size_t)(choffo + co) * HW + pix] * (C::OTAP ? sc3 : 1.f);
     }
   }
 
@@ -827,6 +927,15 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     }
   }
 
+  // tap-major output layer: the last hidden layer's epilogue forms Y (layer
+  // 1 of two-layer nets, layer 2 of three-layer ones); a block lane stores
+  // at its region pixel, tail lanes at the junk slot NYP
+  constexpr bool Y1 = C::OTAP && C::NH == 1, Y2 = C::OTAP && C::NH == 2;
+  static_assert(!Y2 || C::BO, "tap-major three-layer nets run layer 2 block by block");
+  auto yidx = [&](int b) __attribute__((always_inline)) {
+    const int q = 16 * b + j;
+    return q < C::NYP ? q : C::NYP;
+  };
   const int nseg = ca.ckpt_every > 0 ? cdiv(T, ca.ckpt_every) : 0;
   const TraceBox tb{ca.tb_y0, ca.tb_x0, ca.tb_h, ca.tb_w};
   auto write_state = [&](float* dst) __attribute__((always_inline)) {
@@ -839,7 +948,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
 #pragma unroll
         for (int co = 0; co < 2; ++co)
-          if (co < cout) dst[(size_t)(choffo + co) * HW + pix] = so[k][co];
+          if (co < cout) dst[(size_t)(choffo + co) * HW + pix] = so[k][co] * (C::OTAP ? isc3 : 1.f);
       }
     }
 #pragma unroll
@@ -893,6 +1002,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       for (int i = 0; i < C::NB1; ++i)
 #pragma unroll
         for (int m = 0; m < C::MB; ++m) st1[i][m] *= leak;
+      u4 ay[2][C::KY];
+      if constexpr (Y1) load_yfrag<C>(lds, lane, ay);
       if constexpr (C::XSPLIT) {
         // bf16 MFMA over the split records: per block, the 9 fragment
         // products (parts h, m, l interleaved per k-step) accumulate onto
@@ -936,8 +1047,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             }
           }
           if (i > 0)
-            hidden_epilogue<C>(st1[i - 1], lds, 0, e1[i - 1], (vm1 >> (i - 1)) & 1u, g, theta, alpha, relaxed, trace_t,
-                               1.f, c1, 0, gy0, gx0, tb);
+            hidden_epilogue<C, Y1>(st1[i - 1], lds, 0, e1[i - 1], (vm1 >> (i - 1)) & 1u, g, theta, alpha, relaxed,
+                                   trace_t, 1.f, c1, 0, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)));
         }
       } else if constexpr (!C::BF16) {
         // f32 MFMA; the operands of k-step q+1 load while those of q multiply
@@ -997,8 +1108,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       if constexpr (!C::XSPLIT) {
 #pragma unroll
         for (int i = 0; i < C::NB1; ++i)
-          hidden_epilogue<C>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, 1.f, c1, 0,
-                             gy0, gx0, tb);
+          hidden_epilogue<C, Y1>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, 1.f, c1,
+                                 0, gy0, gx0, tb, ay, yidx(wave + C::NW * i));
       }
       lds_barrier();                                   // B1: s1 visible, x buffer (t & 1) free
       if constexpr (C::XDMA) {
@@ -1029,6 +1140,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         for (int kb = 0; kb < C::KB; ++kb)
 #pragma unroll
           for (int p = 0; p < C::NSP; ++p) aw[kb][p] = fr2[(kb * C::NSP + p) * 64];
+        u4 ay[2][C::KY];
+        if constexpr (Y2) load_yfrag<C>(lds, lane, ay);
         u4 bq[2][C::KB];
         auto ldb2 = [&](int i, int sl) __attribute__((always_inline)) {
 #pragma unroll
@@ -1051,8 +1164,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           }
           if (STAGE_IN_L2 && i < C::XPP && t + 1 < T) store_group(i);
           if (i > 0)
-            hidden_epilogue<C>(st2[i - 1], lds, C::S2OFF, e2[i - 1], (vm2 >> (i - 1)) & 1u, g, theta2, alpha, relaxed,
-                               trace_t, isc2, c2, choff2, gy0, gx0, tb);
+            hidden_epilogue<C, Y2>(st2[i - 1], lds, C::S2OFF, e2[i - 1], (vm2 >> (i - 1)) & 1u, g, theta2, alpha,
+                                   relaxed, trace_t, isc2, c2, choff2, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)));
         }
         if constexpr (STAGE_IN_L2) {
 #pragma unroll
@@ -1112,7 +1225,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           }
         }
       }
-      if constexpr (!C::SEP) lds_barrier();            // B2: all reads of s1 done
+      if constexpr (!C::SEP && !C::OTAP) lds_barrier();   // B2: all reads of s1 done
       if constexpr (!C::BO) {
 #pragma unroll
         for (int i = 0; i < C::NB2; ++i)
@@ -1208,6 +1321,42 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
         for (int i = 0; i < C::NBO; ++i) out_epilogue(i, acc[i]);
       }
+    } else if constexpr (C::OTAP) {
+      // ================= tap-major output layer: u = sum over the 9 taps of
+      // the neighbour's Y (fixed order), h = leak v + u, BiLIF; lane = one
+      // output pixel, both channels; potentials in the output conv's weight
+      // scale (threshold theta3), traces and state unscaled
+      const float* const ys = reinterpret_cast<const float*>(lds + Lo::YS);
+      int8_t* const s8 = reinterpret_cast<int8_t*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
+      float* const s32 = reinterpret_cast<float*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
+#pragma unroll
+      for (int k = 0; k < C::NOUT; ++k) {
+        float u0 = 0.f, u1 = 0.f;
+#pragma unroll
+        for (int tau = 0; tau < 9; ++tau) {
+          const int o = op[k] + (tau / 3 - 1) * C::YRW + (tau % 3 - 1);
+          const float2 y = *reinterpret_cast<const float2*>(ys + (tau * C::NYPL + o) * 2);
+          u0 += y.x;
+          u1 += y.y;
+        }
+        const bool ok = (ovm >> k) & 1u;
+        const int q = tid + C::NT * k;
+        const int gy = tl.ty0 + q / C::TW, gx = tl.tx0 + q % C::TW;
+        const size_t pix = (size_t)gy * W + gx;
+#pragma unroll
+        for (int co = 0; co < 2; ++co) {
+          const float h = leak * so[k][co] + (co == 0 ? u0 : u1);
+          if (C::FULL && ok && co < cout && trace_t && tb.has(gy, gx))
+            trace_t[(size_t)(choffo + co) * tb.plane() + tb.idx(gy, gx)] = h * isc3;
+          float v = h;
+          const float sp = bilif(v, theta3, alpha, false);
+          so[k][co] = v;
+          if (ok && co < cout && ca.s_out) {
+            if (C::FULL && ca.s_fp32) s32[(size_t)co * HW + pix] = sp;
+            else s8[(size_t)co * HW + pix] = (int8_t)sp;
+          }
+        }
+      }
     } else {
       // ================= output layer (VALU), weights broadcast from LDS
       float u[C::NOUT][2];
@@ -1271,9 +1420,10 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       if (t + 1 < T) store_x();
       if (t + 2 < T) load_x(t + 2);
     }
-    // B4: spikes / xs consumed before the next frame overwrites them (the
-    // separate layer-2 buffer makes B3 of the next frame the guard)
-    if constexpr (!C::SEP) lds_barrier();
+    // B4: spikes / xs / Y consumed before the next frame overwrites them (the
+    // separate layer-2 buffer, or in three-layer tap-major nets the Y planes
+    // written only by layer 2, make B1 or B3 of the next frame the guard)
+    if constexpr (!C::SEP && !(C::OTAP && C::NH == 2)) lds_barrier();
   }
   if constexpr (C::XDMA) __builtin_amdgcn_s_waitcnt(0);
   if (ca.v_out) write_state(ca.v_out + (size_t)tl.n * sumc * HW);
@@ -1423,6 +1573,8 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
           &launch_batched<EVS_CFG(NL, CIN, CH, 0, TH, TW, NW, 0)>}
 
 // Tile variants per network shape; the first one of a shape is its default.
+// (Three-layer 16-wide nets have no 30x32 / 30x40 tiles: with the Y planes
+// of the tap-major output layer they need more than 160 KB of LDS.)
 const Variant kVariants[] = {
     // single-layer nets (input -> output), f32
     EVS_VARIANT_RX(1, 16, 32, 32, 8, "L1 cin1 f32 32x32 w8"),
@@ -1446,9 +1598,7 @@ const Variant kVariants[] = {
     EVS_VARIANT_RB(3, 3, 16, 24, 32, 8, "L3 h16 f32 24x32 w8"),
     EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
     EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
-    EVS_VARIANT(3, 3, 16, 0, 30, 32, 8, "L3 h16 f32 30x32 w8"),
     EVS_VARIANT(3, 3, 16, 1, 24, 32, 8, "L3 h16 bf16 24x32 w8"),
-    EVS_VARIANT(3, 3, 16, 1, 30, 40, 8, "L3 h16 bf16 30x40 w8"),
     EVS_VARIANT(3, 3, 16, 1, 16, 32, 4, "L3 h16 bf16 16x32 w4"),
     EVS_VARIANT(3, 3, 32, 1, 24, 32, 8, "L3 h32 bf16 24x32 w8"),
 };
