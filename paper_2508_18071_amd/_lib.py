@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libevs.so")
+# EVS_LIB_PATH selects another build of the same library (the host-sanitized
+# one of the CPU tests); the default is the in-tree libevs.so
+LIB_PATH = os.environ.get("EVS_LIB_PATH") or os.path.join(_HERE, "libevs.so")
 
 EVS_OK, EVS_EINVAL, EVS_EUNSUPPORTED, EVS_EWORKSPACE, EVS_EHIP, EVS_EOVERFLOW = range(6)
 EVS_FP32, EVS_BF16 = 0, 1

@@ -67,5 +67,53 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host-side sanitizers: the C++ files of the boundary (argument validation,
+# workspace sizing, tile cache, entry points) built with AddressSanitizer and
+# UndefinedBehaviorSanitizer on their host compilation only, linked with the
+# kernel objects of the normal build into _build/libevs_sanitized.so.  Load it
+# with EVS_LIB_PATH and the ASan runtime preloaded (see
+# tests/test_abi_host_sanitized.py).
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+SAN_OUT = os.path.join(BUILD, "libevs_sanitized.so")
+
+
+def asan_runtime() -> str:
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        for root in ("/opt/rocm/llvm/lib/clang",):
+            for dirpath, _, files in os.walk(root):
+                if "libclang_rt.asan-x86_64.so" in files:
+                    return os.path.join(dirpath, "libclang_rt.asan-x86_64.so")
+        raise RuntimeError("ASan runtime not found")
+    return path
+
+
+def build_sanitized() -> str:
+    if not os.path.exists(OUT):
+        build()
+    os.makedirs(os.path.join(BUILD, "san"), exist_ok=True)
+    objs = []
+    for src in sources():
+        if src.endswith(".cpp"):
+            obj = os.path.join(BUILD, "san", os.path.basename(src) + ".o")
+            cmd = [HIPCC, *COMMON, *SAN_HOST, "-x", "hip", "-c", src, "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compile failed: {src}\n{r.stdout}{r.stderr}")
+        else:
+            obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+        objs.append(obj)
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *SAN_HOST, "-shared-libsan", "-o", SAN_OUT, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed\n" + r.stdout + r.stderr)
+    return SAN_OUT
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitized" in sys.argv:
+        print(build_sanitized())
+    else:
+        print(build(verbose="-v" in sys.argv))
