@@ -85,14 +85,14 @@ std::tuple<int, int, int, int, int, int, int, int> shape_key(const evs_net& n, i
 }
 }  // namespace
 
-int choose_tile(const evs_net& net, int H, int W) {
+int choose_tile(const evs_net& net, int H, int W, int N) {
   load_tile_cache_once();
   std::lock_guard<std::mutex> lk(g_tile_mu);
   auto f = g_forced.find(net_key(net));
   if (f != g_forced.end() && f->second >= 0) return f->second;
   auto t = g_tuned.find(shape_key(net, H, W));
   if (t != g_tuned.end()) return t->second;
-  return forward_default_tile(net, H, W);
+  return forward_default_tile(net, H, W, N);
 }
 
 void remember_tile(const evs_net& net, int H, int W, int tile) {
@@ -271,7 +271,7 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
   };
 
   if (n_clips == 1) {
-    const int tile = choose_tile(*net, clips[0].H, clips[0].W);
+    const int tile = choose_tile(*net, clips[0].H, clips[0].W, clips[0].N);
     FwdClipArgs ca;
     if ((st = clip_args(clips[0], tile, ca))) return st;
     ca.ckpt = ckpt;

@@ -891,7 +891,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
                        net.ch[l], net.ch[l - 1], CI, CO, bf ? 1 : 0, wT + accofs[l - 1]);
     EVS_HIP(hipGetLastError());
   }
-  const int tile = choose_tile(net, H, W);
+  const int tile = choose_tile(net, H, W, N);
   int th = 0, tw = 0;
   forward_tile_dims(net, tile, &th, &tw);
   if (th == 0) return fail(EVS_EUNSUPPORTED, "backward: no forward kernel for this network");

@@ -39,6 +39,8 @@
 //     spike buffers and the f32 MFMA / VALU paths.)
 //   * Only the HBM traffic of the algorithm remains: x in (12 B/px/frame)
 //     and the output spikes (int8).
+#include <cmath>
+
 #include "evs_internal.hpp"
 #include "evs_device.hpp"
 
@@ -1521,6 +1523,9 @@ struct Variant {
   void (*batched)(const FwdNetArgs&, const BatchTable&, int32_t*, int ncu, hipStream_t, hipError_t*);
   // RGB-input kernels of one-channel nets: inference, training/debug, relaxed
   void (*logx[3])(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
+  // 1: one of the shape's default candidates, which differ only in how
+  // their tile count fills the CUs (see forward_default_tile)
+  int dflt;
 };
 
 template <class C>
@@ -1571,6 +1576,13 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
   Variant{NL, CIN, CH, 0, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, 0, TH, TW, NW),   \
           &launch_single<EVS_CFG(NL, CIN, CH, 0, TH, TW, NW, 2)>,                    \
           &launch_batched<EVS_CFG(NL, CIN, CH, 0, TH, TW, NW, 0)>}
+// default candidates (one workgroup per CU each)
+#define EVS_VARIANT_RB_D(NL, CIN, CH, TH, TW, NW, NAME)                              \
+  Variant{NL, CIN, CH, 0, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, 0, TH, TW, NW),   \
+          &launch_single<EVS_CFG(NL, CIN, CH, 0, TH, TW, NW, 2)>,                    \
+          &launch_batched<EVS_CFG(NL, CIN, CH, 0, TH, TW, NW, 0)>, {}, 1}
+#define EVS_VARIANT_D(NL, CIN, CH, BF, TH, TW, NW, NAME) \
+  Variant{NL, CIN, CH, BF, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, BF, TH, TW, NW), nullptr, nullptr, {}, 1}
 
 // Tile variants per network shape; the first one of a shape is its default.
 // (Three-layer 16-wide nets have no 30x32 / 30x40 tiles: with the Y planes
@@ -1595,7 +1607,8 @@ const Variant kVariants[] = {
     EVS_VARIANT(2, 3, 32, 1, 16, 32, 4, "L2 h32 bf16 16x32 w4"),
     EVS_VARIANT(2, 3, 32, 1, 20, 32, 4, "L2 h32 bf16 20x32 w4"),
     // three-layer nets
-    EVS_VARIANT_RB(3, 3, 16, 24, 32, 8, "L3 h16 f32 24x32 w8"),
+    EVS_VARIANT_RB_D(3, 3, 16, 24, 32, 8, "L3 h16 f32 24x32 w8"),
+    EVS_VARIANT_D(3, 3, 16, 0, 23, 32, 8, "L3 h16 f32 23x32 w8"),
     EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
     EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
     EVS_VARIANT(3, 3, 16, 1, 24, 32, 8, "L3 h16 bf16 24x32 w8"),
@@ -1653,9 +1666,37 @@ int forward_batched_tile(const evs_net& net, int preferred) {
   return -1;
 }
 
-int forward_default_tile(const evs_net& net, int H, int W) {
-  (void)H; (void)W;
-  return forward_tile_count(net) > 0 ? 0 : -1;
+// Default tile: the first compiled variant of the shape, or, among its
+// default candidates (whole-CU workgroups that differ only in tile height),
+// the one with the least estimated time: whole rounds of workgroups over the
+// CUs, ceil(tiles / CUs), times the canvas pixels of one tile.  A 720p frame
+// has 1200 tiles of 24x32 (4.69 rounds on 256 CUs, run as 5) but 1280 of
+// 23x32 (5 full rounds of a 3% smaller canvas).
+int forward_default_tile(const evs_net& net, int H, int W, int N) {
+  if (forward_tile_count(net) <= 0) return -1;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0, n = 0;
+    ncu = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) ? n : 256;
+  }
+  int best = 0, k = 0;
+  double best_cost = -1.0;
+  for (int i = 0; i < kNumVariants; ++i) {
+    const Variant& v = kVariants[i];
+    if (!matches(v, net)) continue;
+    if (v.dflt) {
+      const int L = net.n_layers;
+      const double tiles = (double)((H + v.th - 1) / v.th) * ((W + v.tw - 1) / v.tw) * (N > 0 ? N : 1);
+      const double cost = std::ceil(tiles / ncu) * (v.th + 2 * L) * (v.tw + 2 * L);
+      if (best_cost < 0.0 || cost < best_cost) {
+        best_cost = cost;
+        best = k;
+      }
+    }
+    ++k;
+  }
+  return best;
 }
 
 int launch_forward(const evs_net& net, const FwdNetArgs& na, const FwdClipArgs& ca, int tile_id,

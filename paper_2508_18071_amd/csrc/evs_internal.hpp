@@ -100,7 +100,7 @@ int launch_forward_batched(const evs_net& net, const FwdNetArgs& na, const Batch
 int forward_tile_count(const evs_net& net);
 const char* forward_tile_name(const evs_net& net, int tile_id);
 void forward_tile_dims(const evs_net& net, int tile_id, int* th, int* tw);
-int forward_default_tile(const evs_net& net, int H, int W);
+int forward_default_tile(const evs_net& net, int H, int W, int N);
 int forward_batched_tile(const evs_net& net, int preferred);   // -1: none compiled
 
 }  // namespace evs

@@ -42,7 +42,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
 
 // tile selection (evs_api.cpp); the autotuner (evs_autotune.cpp)
 void load_tile_cache_once();
-int choose_tile(const evs_net& net, int H, int W);
+int choose_tile(const evs_net& net, int H, int W, int N = 1);
 void remember_tile(const evs_net& net, int H, int W, int tile);
 FwdNetArgs make_net_args(const evs_net& net, const void* packed);
 
