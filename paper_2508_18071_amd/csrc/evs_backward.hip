@@ -113,7 +113,7 @@ __global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int
   constexpr int kTile = COUTP * (TT + 2) * (TT + 2);
   constexpr int kStage = (kTile + NTH - 1) / NTH;
   __shared__ float ghs[COUTP][TT + 2][TT + 2];
-  const int tile = blockIdx.x, n = blockIdx.y;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
   const int HW = H * W;
   const int ty = threadIdx.x / TT, tx = threadIdx.x % TT;
@@ -222,7 +222,7 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
   static_assert(COG % 4 == 0, "co slots come in lane groups of 4");
   static_assert(E * E > NTH && E * E <= 2 * NTH, "a tile plane is staged in two passes");
   __shared__ float ghs[COUTP * PS];
-  const int tile = blockIdx.x, n = blockIdx.y;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
   const int HW = H * W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -418,7 +418,7 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
     }
     __syncthreads();
     if (wave == 0) {
-      float* o = dw_partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (16 * COUTP * 9);
+      float* o = dw_partial + ((size_t)blockIdx.y * gridDim.x + tile) * (16 * COUTP * 9);
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) {
         const int idx = 16 * nt + j, co = idx / 9, tap = idx % 9;
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
   __shared__ float ghs[COUTP][TT * TT];
   __shared__ float ss[CINP][TT + 2][TT + 2];
   __shared__ float red[TPP > 1 ? NTH * 9 : 1];
-  const int tile = blockIdx.x, n = blockIdx.y;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
   const int HW = H * W;
   float acc[PPT][9];
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
       }
     }
   }
-  float* out = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * P * 9;
+  float* out = partial + ((size_t)blockIdx.y * gridDim.x + tile) * P * 9;
   if constexpr (TPP > 1) {
     __syncthreads();
 #pragma unroll
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, i
   __shared__ __attribute__((aligned(16))) char lds[kGspBytes + kSsbBytes];
   uint16_t* const gsp = reinterpret_cast<uint16_t*>(lds);
   uint16_t* const ssb = reinterpret_cast<uint16_t*>(lds + kGspBytes);
-  const int tile = blockIdx.x, n = blockIdx.y;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
   const int HW = H * W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, i
   }
   __syncthreads();
   if (wave == 0) {
-    float* out = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 256 * 9;
+    float* out = partial + ((size_t)blockIdx.y * gridDim.x + tile) * 256 * 9;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap)
 #pragma unroll

@@ -19,6 +19,19 @@ __device__ inline float linlog_lum(float r, float g, float b, float scale, float
   return L >= knee ? logf(L) : __fmul_rn(toe, L);
 }
 
+// XCD-aware tile order: the hardware deals workgroups round-robin over the
+// 8 XCDs; give each XCD a contiguous run of the n tiles so that the halo
+// rows and the cache lines that neighbouring tiles share are fetched into the
+// same L2 (a 16-pixel tile row is half a 128-byte line).  b is the block
+// index in a grid dimension of n blocks, the dimension the hardware walks
+// first; any n is a bijection.
+__device__ inline int xcd_remap(int b, int n) {
+  const int x = b & 7, k = b >> 3;
+  const int q = n >> 3, r = n & 7;
+  const int start = x * q + (x < r ? x : r);
+  return start + k;
+}
+
 // Smooth step of the surrogate (Sec. 3.3, Eq. 4) and its slope.
 //   kind 0: logistic sigmoid 1 / (1 + exp(-alpha z))
 //   kind 1: arctangent 1/2 + arctan(pi/2 alpha z) / pi

@@ -1439,16 +1439,6 @@ __device__ __forceinline__ void init_lds(const FwdNetArgs& na, char* lds) {
   load_weights<C>(na, lds);
 }
 
-// XCD-aware tile order: the hardware deals workgroups round-robin over the
-// 8 XCDs; give each XCD a contiguous run of tiles so that the halos that
-// neighbouring tiles share are fetched into the same L2.
-__device__ inline int xcd_remap(int b, int n) {
-  const int x = b & 7, k = b >> 3;
-  const int q = n >> 3, r = n & 7;
-  const int start = x * q + (x < r ? x : r);
-  return start + k;
-}
-
 template <class C>
 __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void fwd_kernel(FwdNetArgs na, FwdClipArgs ca) {
   __shared__ __attribute__((aligned(16))) char lds[Layout<C>::TOTAL];
