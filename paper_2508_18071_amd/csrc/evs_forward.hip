@@ -86,6 +86,12 @@ struct Cfg {
   static constexpr int nblk(int l) { return cdiv(rgh(l) * rgw(l), 16); }
   static constexpr int NB1 = NH >= 1 ? cdiv(nblk(1), NW) : 1;
   static constexpr int NB2 = NH >= 2 ? cdiv(nblk(2), NW) : 1;
+  // waves per SIMD the register budget is cut for: four (<= 128 VGPRs) for
+  // the inference build of BF16 nets with one hidden layer whose layer-1
+  // state is at most 4 blocks per wave (the 8-wave 12x32 tile: two
+  // workgroups, 16 waves, per CU; its frame loop has no spill code at that
+  // budget, the traced build's has), else two (<= 256 VGPRs)
+  static constexpr int WPE = (BF16_ && NH == 1 && NB1 <= 4 && !FULL) ? 4 : 2;
   static constexpr bool S16 = !RELAX;                // hidden spikes stored as bf16
   // FP32 nets: spikes and the weights of the convs that read them in fp16,
   // each weight (scaled by a power of two per layer) as two fp16 parts
@@ -1440,7 +1446,7 @@ __device__ __forceinline__ void init_lds(const FwdNetArgs& na, char* lds) {
 }
 
 template <class C>
-__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void fwd_kernel(FwdNetArgs na, FwdClipArgs ca) {
+__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE))) void fwd_kernel(FwdNetArgs na, FwdClipArgs ca) {
   __shared__ __attribute__((aligned(16))) char lds[Layout<C>::TOTAL];
   init_lds<C>(na, lds);
   __syncthreads();
@@ -1475,7 +1481,7 @@ __device__ inline int pop_item(int32_t* counter, int n_items, int x) {
 // Persistent batched kernel: workgroups pop (clip, tile) items from the
 // per-XCD queues; items are ordered clip by clip, clips longest-first.
 template <class C>
-__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void fwd_batched_kernel(FwdNetArgs na, BatchTable bt, int32_t* counter) {
+__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE))) void fwd_batched_kernel(FwdNetArgs na, BatchTable bt, int32_t* counter) {
   __shared__ __attribute__((aligned(16))) char lds[Layout<C>::TOTAL];
   __shared__ int item_sh;
   init_lds<C>(na, lds);
@@ -1588,20 +1594,22 @@ const Variant kVariants[] = {
     EVS_VARIANT_RX(2, 16, 30, 40, 8, "L2 cin1 h16 f32 30x40 w8"),
     EVS_VARIANT(2, 3, 16, 1, 30, 40, 8, "L2 h16 bf16 30x40 w8"),
     // two-layer nets with hidden width <= 32
-    EVS_VARIANT(2, 3, 32, 0, 24, 32, 8, "L2 h32 f32 24x32 w8"),
+    EVS_VARIANT_D(2, 3, 32, 0, 24, 32, 8, "L2 h32 f32 24x32 w8"),
+    EVS_VARIANT_D(2, 3, 32, 0, 23, 32, 8, "L2 h32 f32 23x32 w8"),
     EVS_VARIANT_R(2, 3, 32, 22, 32, 8, "L2 h32 f32 22x32 w8"),
     EVS_VARIANT(2, 3, 32, 0, 16, 44, 8, "L2 h32 f32 16x44 w8"),
+    EVS_VARIANT_B(2, 3, 32, 1, 12, 32, 8, "L2 h32 bf16 12x32 w8"),
     EVS_VARIANT_B(2, 3, 32, 1, 12, 32, 4, "L2 h32 bf16 12x32 w4"),
     EVS_VARIANT_B(2, 3, 32, 1, 24, 32, 8, "L2 h32 bf16 24x32 w8"),
     EVS_VARIANT(2, 3, 32, 1, 30, 40, 8, "L2 h32 bf16 30x40 w8"),
     EVS_VARIANT(2, 3, 32, 1, 16, 32, 4, "L2 h32 bf16 16x32 w4"),
-    EVS_VARIANT(2, 3, 32, 1, 20, 32, 4, "L2 h32 bf16 20x32 w4"),
     // three-layer nets
     EVS_VARIANT_RB_D(3, 3, 16, 24, 32, 8, "L3 h16 f32 24x32 w8"),
     EVS_VARIANT_D(3, 3, 16, 0, 23, 32, 8, "L3 h16 f32 23x32 w8"),
     EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
     EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
-    EVS_VARIANT(3, 3, 16, 1, 24, 32, 8, "L3 h16 bf16 24x32 w8"),
+    EVS_VARIANT_D(3, 3, 16, 1, 24, 32, 8, "L3 h16 bf16 24x32 w8"),
+    EVS_VARIANT_D(3, 3, 16, 1, 23, 32, 8, "L3 h16 bf16 23x32 w8"),
     EVS_VARIANT(3, 3, 16, 1, 16, 32, 4, "L3 h16 bf16 16x32 w4"),
     EVS_VARIANT(3, 3, 32, 1, 24, 32, 8, "L3 h32 bf16 24x32 w8"),
 };
