@@ -41,11 +41,71 @@ __device__ inline float wq(const float* w, int idx, bool bf) {
   return bf ? round_bf16(v) : v;
 }
 
+// Storage of a segment's charged potentials h (written by the forward's
+// training build) and of the adjoints g_h between the gradient kernels.
+// FP32 nets: float both.  BF16 nets: h as fp16 rounded so that the stored
+// value gives the forward's spike (the forward's recompute build) and g_h as bf16
+// (round to nearest), the operand precision of their bf16 matrix products;
+// the adjoint recurrences, the surrogate and every sum stay FP32.
+template <bool B16> struct Store;
+template <> struct Store<false> { using H = float; using G = float; };
+template <> struct Store<true> { using H = _Float16; using G = __bf16; };
+
+__device__ inline float to_f32(float v) { return v; }
+__device__ inline float to_f32(_Float16 v) { return (float)v; }
+__device__ inline float to_f32(__bf16 v) { return __builtin_bit_cast(float, (unsigned)__builtin_bit_cast(unsigned short, v) << 16); }
+template <class T> __device__ inline T from_f32(float v) { return (T)v; }
+
+// Buffer load / store of one element of type T at a byte offset (offsets
+// past the resource read 0 and drop the store).
+template <class T>
+__device__ inline float ld_el(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    return to_f32(__builtin_bit_cast(T, b));
+  }
+}
+template <class T>
+__device__ inline void st_el(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, from_f32<T>(v)), r, voff, soff, 0);
+  }
+}
+// byte offset of element e of type T, or the dead offset (reads 0)
+constexpr unsigned kDeadOff = 0x80000000u;
+template <class T> __device__ inline unsigned el_off(bool live, unsigned e) { return live ? e * (unsigned)sizeof(T) : kDeadOff; }
+// four consecutive elements (8- or 16-byte aligned) in one buffer load
+template <class T>
+__device__ inline f4 ld4_el(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  } else {
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    const h4 q = __builtin_bit_cast(h4, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return f4{(float)q[0], (float)q[1], (float)q[2], (float)q[3]};
+  }
+}
+
+// Where the potentials of one layer sit in the segment trace the forward
+// wrote (pixel-major): frame (n, t) of the segment starts at plane
+// (n len + t) tpf, the layer at plane cpo of it, and pixel p's channel c is
+// element p cw + c of the layer's block (cw: the layer's width rounded up
+// to 4; the output layer's 4).
+struct HTrace {
+  int tpf, cpo, cw;
+  __device__ size_t base(int n, int len, int t, size_t HW) const { return ((size_t)(n * len + t) * tpf + cpo) * HW; }
+};
+
 // ---------------------------------------------------------------- adjoint scan
-__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ hseg, int sumc, int choff, int C,
+template <class HS, class GS>
+__global__ __launch_bounds__(256) void k_adjoint(const HS* __restrict__ hseg, HTrace ht, int sumc, int choff, int C,
                                                  int len, int N, int HW, const float* __restrict__ G,
                                                  long long G_nstride, long long G_tstride,
-                                                 float* __restrict__ gh, float* __restrict__ gv, float theta,
+                                                 GS* __restrict__ gh, float* __restrict__ gv, float theta,
                                                  float leak, float alpha, int surr, int detach,
                                                  int32_t* __restrict__ status) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -58,12 +118,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ hseg,
   float* gvp = gv + ((size_t)n * sumc + choff + c) * HW + p;
   float g_v = *gvp;
   for (int t = len - 1; t >= 0; --t) {
-    const float h = hseg[(((size_t)n * len + t) * sumc + choff + c) * HW + p];
+    const float h = to_f32(hseg[ht.base(n, len, t, HW) + (size_t)p * ht.cw + c]);
     const float Gv = G[(size_t)n * G_nstride + (size_t)t * G_tstride + (size_t)c * HW + p];
     nan += Gv != Gv ? 1 : 0;
     const float psi = surrogate(h, theta, alpha, surr);
     const float g_h = detach ? fmaf(Gv, psi, g_v) : fmaf(fmaf(-theta, g_v, Gv), psi, g_v);
-    gh[(((size_t)n * len + t) * C + c) * HW + p] = g_h;
+    gh[(((size_t)n * len + t) * C + c) * HW + p] = from_f32<GS>(g_h);
     g_v = leak * g_h;
   }
   *gvp = g_v;
@@ -103,11 +163,11 @@ __global__ void k_pack_wT(const float* __restrict__ w, int Cout, int Cin, int CI
 // written to out [n][t][Cin][H][W]; without ADJ G itself is written (grad_x).
 // The arithmetic and its order are those of a separate conv-transpose pass
 // followed by a separate scan.
-template <int CINP, int COUTP, bool ADJ>
-__global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+template <int CINP, int COUTP, bool ADJ, class HS, class GS>
+__global__ __launch_bounds__(NTH) void k_convT(const GS* __restrict__ gh, int Cout, int Cin, int len, int H,
                                                int W, int tiles_x, const float* __restrict__ wT,
-                                               float* __restrict__ out, long long out_nstride,
-                                               long long out_tstride, const float* __restrict__ hseg, int sumc,
+                                               void* __restrict__ outv, long long out_nstride,
+                                               long long out_tstride, const HS* __restrict__ hseg, HTrace ht, int sumc,
                                                int choff, float* __restrict__ gv, float theta, float leak,
                                                float alpha, int surr, int detach) {
   constexpr int kTile = COUTP * (TT + 2) * (TT + 2);
@@ -121,14 +181,14 @@ __global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int
   const bool own = y < H && x < W;
   float pre[kStage];
   auto fetch = [&](int t) __attribute__((always_inline)) {
-    const float* g = gh + ((size_t)n * len + t) * Cout * HW;
+    const GS* g = gh + ((size_t)n * len + t) * Cout * HW;
 #pragma unroll
     for (int k = 0; k < kStage; ++k) {
       const int e = threadIdx.x + NTH * k;
       const int co = e / ((TT + 2) * (TT + 2)), r = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
       const int yy = ty0 - 1 + r, xx = tx0 - 1 + cc;
       pre[k] = (e < kTile && co < Cout && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                   ? g[(size_t)co * HW + (size_t)yy * W + xx] : 0.f;
+                   ? to_f32(g[(size_t)co * HW + (size_t)yy * W + xx]) : 0.f;
     }
   };
   float g_v[CINP];
@@ -147,9 +207,9 @@ __global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int
     }
     float hv[CINP];
     if constexpr (ADJ) {
-      const float* hp = hseg + (((size_t)n * len + t) * sumc + choff) * HW + (size_t)y * W + x;
+      const HS* hp = hseg + ht.base(n, len, t, HW) + ((size_t)y * W + x) * ht.cw;
 #pragma unroll
-      for (int ci = 0; ci < CINP; ++ci) hv[ci] = (own && ci < Cin) ? hp[(size_t)ci * HW] : 0.f;
+      for (int ci = 0; ci < CINP; ++ci) hv[ci] = (own && ci < Cin) ? to_f32(hp[ci]) : 0.f;
     }
     if (t > 0) fetch(t - 1);                           // in flight while this frame is used
     __syncthreads();
@@ -169,18 +229,18 @@ __global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int
     }
     if (own) {
       if constexpr (ADJ) {
-        float* o = out + (((size_t)n * len + t) * Cin) * HW + (size_t)y * W + x;
+        GS* o = reinterpret_cast<GS*>(outv) + (((size_t)n * len + t) * Cin) * HW + (size_t)y * W + x;
 #pragma unroll
         for (int ci = 0; ci < CINP; ++ci) {
           if (ci < Cin) {
             const float psi = surrogate(hv[ci], theta, alpha, surr);
             const float g = detach ? fmaf(acc[ci], psi, g_v[ci]) : fmaf(fmaf(-theta, g_v[ci], acc[ci]), psi, g_v[ci]);
-            o[(size_t)ci * HW] = g;
+            o[(size_t)ci * HW] = from_f32<GS>(g);
             g_v[ci] = leak * g;
           }
         }
       } else {
-        float* o = out + (size_t)n * out_nstride + (size_t)t * out_tstride + (size_t)y * W + x;
+        float* o = reinterpret_cast<float*>(outv) + (size_t)n * out_nstride + (size_t)t * out_tstride + (size_t)y * W + x;
 #pragma unroll
         for (int ci = 0; ci < CINP; ++ci)
           if (ci < Cin) o[(size_t)ci * HW] = acc[ci];
@@ -197,50 +257,91 @@ __global__ __launch_bounds__(NTH) void k_convT(const float* __restrict__ gh, int
 }
 
 // The same conv-transpose + adjoint for a layer below with 5..16 channels,
-// on the FP32 matrix pipe.  Per 16-pixel tile row, G[ci][pixel] is a 16 x 16
-// product over K = (tap, co): v_mfma_f32_16x16x4_f32 with the weights as the
-// A operand (lane (ci, k) holds W[co][ci][tap], staged in LDS once per
-// workgroup) and the haloed g_h tile as B, read from LDS at an immediate
-// offset from a per-lane base (K is ordered tap-major, co in lane
-// groups of 4; output widths below 4 are padded with zero weights).  Lane
-// (pixel j, group g) receives G for channels 4g..4g+3 of pixel j and runs the
-// adjoint scan on them; wave w takes tile rows 4w..4w+3.  The g_h planes are
-// 336 floats apart (16 banks mod 64), so the four lane groups of a read hit
-// distinct banks.  FP32 products and sums, in the matrix pipe's own order.
-template <int COUTP>
+// on the matrix pipe.  Per 16-pixel tile row, G[ci][pixel] is a 16 x 16
+// product over K = (tap, co), the weights as the A operand and the haloed
+// g_h tile as B, read from LDS at an immediate offset from a per-lane base.
+// Lane (pixel j, group g) receives G for channels 4g..4g+3 of pixel j and
+// runs the adjoint scan on them; wave w takes tile rows 4w..4w+3.
+//   FP32 nets (and narrow layers above): v_mfma_f32_16x16x4_f32, lane
+//     (ci, k) of the A operand holds W[co][ci][tap] (staged in LDS once per
+//     workgroup), K tap-major with co in lane groups of 4 (output widths
+//     below 4 padded with zero weights); the g_h planes are 336 floats apart
+//     (16 banks mod 64), so the four lane groups of a read hit distinct
+//     banks.  FP32 products and sums, in the matrix pipe's own order.
+//   BF16 nets, 16-wide layer above (B16): v_mfma_f32_16x16x32_bf16 with
+//     the bf16 g_h the layer above stored and the bf16 weights the forward
+//     used (exact products, FP32 sums): K slots 8g..8g+7 of k-step s are tap
+//     2s + g/2 (tap 9: zero weights), channels 8 (g & 1) .. +7, so the B
+//     operand of a lane is one 16-byte read from a tile held as two planes
+//     of [pixel][8 channels] bf16 whose stride is a multiple of 256 bytes
+//     (the two channel halves of a tap then fill disjoint banks); 5 MFMAs
+//     per row instead of 36.
+template <int COUTP, bool B16>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3)))
-void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int Cin, int len, int H,
                                                     int W, int tiles_x, const float* __restrict__ wT,
-                                                    float* __restrict__ out, const float* __restrict__ hseg,
+                                                    typename Store<B16>::G* __restrict__ out,
+                                                    const typename Store<B16>::H* __restrict__ hseg, HTrace ht,
                                                     int sumc, int choff, float* __restrict__ gv, float theta,
                                                     float leak, float alpha, int surr, int detach, int relaxed,
                                                     float* __restrict__ dw_partial) {
+  using HS = typename Store<B16>::H;
+  using GS = typename Store<B16>::G;
+  constexpr unsigned ESH = sizeof(HS), ESG = sizeof(GS);
+  constexpr bool kBF = B16 && COUTP == 16;             // the bf16 product
   constexpr int E = TT + 2;                            // haloed tile edge
-  constexpr int PS = (E * E + 47) / 64 * 64 + 16;      // plane stride, 16 mod 64
+  constexpr int PS = (E * E + 47) / 64 * 64 + 16;      // plane stride (floats), 16 mod 64
+  constexpr int PSB = (E * E * 16 + 255) / 256 * 256;  // bf16 plane stride (bytes), multiple of 256
   constexpr int COG = COUTP < 4 ? 4 : COUTP;           // co slots per tap
-  constexpr int KS = 9 * COG / 4;                      // k-steps
+  constexpr int KS = 9 * COG / 4;                      // k-steps (f32 product)
+  constexpr int KSB = 5;                               // k-steps (bf16 product)
   static_assert(COG % 4 == 0, "co slots come in lane groups of 4");
   static_assert(E * E > NTH && E * E <= 2 * NTH, "a tile plane is staged in two passes");
-  __shared__ float ghs[COUTP * PS];
+  __shared__ __attribute__((aligned(16))) float ghs[kBF ? 2 * PSB / 4 : COUTP * PS];
   const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
   const int HW = H * W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
-  // weights: k-step s, lane group g -> tap s / (COG/4), co 4 (s % (COG/4)) + g;
-  // held in LDS as [s / 4][lane][s % 4], one 16-byte read per lane for four
-  // k-steps (the A operand would otherwise take 36-72 registers)
+  // weights (f32 product): k-step s, lane group g -> tap s / (COG/4), co
+  // 4 (s % (COG/4)) + g; held in LDS as [s / 4][lane][s % 4], one 16-byte
+  // read per lane for four k-steps (the A operand would otherwise take 36-72
+  // registers)
   constexpr int KS4 = (KS + 3) / 4;
-  __shared__ f4 wl[KS4 * 64];
-  for (int idx = threadIdx.x; idx < KS4 * 4 * 64; idx += NTH) {
-    const int s = idx / 64, l = idx % 64;
-    const int tap = s / (COG / 4), co = 4 * (s % (COG / 4)) + l / 16;
-    wl[(s / 4) * 64 + l][s % 4] = (s < KS && co < COUTP) ? wT[(tap * COUTP + co) * 16 + l % 16] : 0.f;
+  __shared__ f4 wl[kBF ? 1 : KS4 * 64];
+  u4 wb[kBF ? KSB : 1];
+  if constexpr (kBF) {
+    // bf16 A operand in registers: row ci = j, K slot 8g + e of k-step s
+#pragma unroll
+    for (int s = 0; s < KSB; ++s) {
+      const int tap = 2 * s + (g >> 1);
+      unsigned wd[4];
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        float ww[2];
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const int co = 8 * (g & 1) + 2 * e2 + h2;
+          ww[h2] = tap < 9 ? wT[(tap * COUTP + co) * 16 + j] : 0.f;
+        }
+        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+        const bf2 pr = {(__bf16)ww[0], (__bf16)ww[1]};
+        wd[e2] = __builtin_bit_cast(unsigned, pr);
+      }
+      wb[s] = u4{wd[0], wd[1], wd[2], wd[3]};
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < KS4 * 4 * 64; idx += NTH) {
+      const int s = idx / 64, l = idx % 64;
+      const int tap = s / (COG / 4), co = 4 * (s % (COG / 4)) + l / 16;
+      wl[(s / 4) * 64 + l][s % 4] = (s < KS && co < COUTP) ? wT[(tap * COUTP + co) * 16 + l % 16] : 0.f;
+    }
   }
   // B read of (row r, k-step s): base + r E + imm(s); planes past COUTP
   // (zero weights) read plane g % COUTP, whose values are finite
   const int plane = COUTP < 4 ? g % COUTP : g;
   const float* const bbase = ghs + plane * PS + 4 * wave * E + j;
+  const char* const bbase16 = reinterpret_cast<const char*>(ghs) + (g & 1) * PSB + (4 * wave * E + j) * 16;
   // Narrow layers (output widths <= 4) also form their own weight gradient
   // dW[co][ci][tap] = sum_q s[ci][q] g_h[co][q - tap] (s: the spikes of the
   // layer below, from the h this kernel reads anyway) as a 16 (ci) x 18
@@ -265,18 +366,24 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
   }
   // this lane's 16 neurons: rows 4 wave + r (uniform in the wave), column j,
   // channels 4g + i.  Their [ch][H][W] planes are read and written through
-  // buffer resources bounded to the layer's Cin planes: voff[i] + r W 4 is
-  // the byte offset of neuron (r, i); a lane past the image's right edge has
-  // offsets of 2^31 and up, and one past Cin offsets beyond the last plane,
-  // so their loads return 0 and their stores are dropped.  Rows past the
-  // bottom edge are skipped by a branch that is uniform in the wave.
-  constexpr unsigned kDead = 0x80000000u;
+  // buffer resources bounded to the layer's Cin planes: voff[i] + r W es is
+  // the byte offset of neuron (r, i) in a plane of es-byte elements; a lane
+  // past the image's right edge has offsets of 2^31 and up, and one past
+  // Cin offsets beyond the last plane, so their loads return 0 and their
+  // stores are dropped.  Rows past the bottom edge are skipped by a branch
+  // that is uniform in the wave.
   const int x = tx0 + j, y0 = ty0 + 4 * wave;
-  const unsigned bytes = (unsigned)Cin * (unsigned)HW * 4u;
-  unsigned voff[4];
+  const unsigned nel = (unsigned)Cin * (unsigned)HW;
+  unsigned voff[4], voffG[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    voff[i] = x < W ? 4u * ((unsigned)(4 * g + i) * (unsigned)HW + (unsigned)(y0 * W + x)) : kDead;
+  for (int i = 0; i < 4; ++i) {
+    const unsigned e = (unsigned)(4 * g + i) * (unsigned)HW + (unsigned)(y0 * W + x);
+    voff[i] = el_off<float>(x < W, e);
+    voffG[i] = el_off<GS>(x < W, e);
+  }
+  // h of the lane's four channels of a pixel: one load from the
+  // pixel-major trace (lanes past the layer's rounded width read 0)
+  const unsigned voffH = el_off<HS>(x < W && 4 * g < ht.cw, (unsigned)((y0 * W + x) * ht.cw + 4 * g));
   // staging: this thread loads haloed-tile entries q = tid and tid + 256 of
   // every g_h plane; entries outside the image read 0 the same way
   unsigned qoff[2];
@@ -284,17 +391,15 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
   for (int k = 0; k < 2; ++k) {
     const int q = threadIdx.x + NTH * k;
     const int yy = ty0 - 1 + q / E, xx = tx0 - 1 + q % E;
-    qoff[k] = (q < E * E && yy >= 0 && yy < H && xx >= 0 && xx < W) ? 4u * (unsigned)(yy * W + xx) : kDead;
+    qoff[k] = el_off<GS>(q < E * E && yy >= 0 && yy < H && xx >= 0 && xx < W, (unsigned)(yy * W + xx));
   }
   const __amdgpu_buffer_rsrc_t rv =
-      __builtin_amdgcn_make_buffer_rsrc(gv + ((size_t)n * sumc + choff) * HW, (short)0, (int)bytes, 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(gv + ((size_t)n * sumc + choff) * HW, (short)0, (int)(nel * 4u), 0x00020000);
   float g_v[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      g_v[r][i] = y0 + r < H ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, voff[i], r * W * 4, 0))
-                             : 0.f;
+    for (int i = 0; i < 4; ++i) g_v[r][i] = y0 + r < H ? ld_el<float>(rv, voff[i], r * W * 4) : 0.f;
   // a frame's loads: its haloed g_h tile (every load issued before the first
   // LDS store; planes past Cout fall outside the resource and read 0) and the
   // h of this lane's neurons.  Narrow layers above (memory-bound: the scan
@@ -303,25 +408,45 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
   float st0[COUTP], st1[COUTP], hn[4][4];
   auto load_tile = [&](int t) __attribute__((always_inline)) {
     const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0,
-        (int)((unsigned)Cout * (unsigned)HW * 4u), 0x00020000);
+        const_cast<GS*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)((unsigned)Cout * (unsigned)HW * ESG),
+        0x00020000);
 #pragma unroll
-    for (int co = 0; co < COUTP; ++co)
-      st0[co] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, qoff[0] + 4u * co * HW, 0, 0));
+    for (int co = 0; co < COUTP; ++co) st0[co] = ld_el<GS>(rg, qoff[0] + ESG * co * HW, 0);
     if (threadIdx.x < E * E - NTH) {
 #pragma unroll
-      for (int co = 0; co < COUTP; ++co)
-        st1[co] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, qoff[1] + 4u * co * HW, 0, 0));
+      for (int co = 0; co < COUTP; ++co) st1[co] = ld_el<GS>(rg, qoff[1] + ESG * co * HW, 0);
     }
   };
   auto load_h = [&](int t) __attribute__((always_inline)) {
     const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(hseg + (((size_t)n * len + t) * sumc + choff) * HW), (short)0, (int)bytes, 0x00020000);
+        const_cast<HS*>(hseg + ht.base(n, len, t, HW)), (short)0, (int)((unsigned)ht.cw * (unsigned)HW * ESH),
+        0x00020000);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
+      const f4 v = ld4_el<HS>(rh, voffH, r * W * ht.cw * ESH);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        hn[r][i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff[i], r * W * 4, 0));
+      for (int i = 0; i < 4; ++i) hn[r][i] = v[i];
+    }
+  };
+  // one staged tile entry (all channels) into LDS: float planes, or the two
+  // bf16 planes of [pixel][8 channels]
+  auto stage_entry = [&](const float (&v)[COUTP], int q) __attribute__((always_inline)) {
+    if constexpr (kBF) {
+      typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        unsigned wd[4];
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) {
+          const bf2 pr = {(__bf16)v[8 * hf + 2 * e2], (__bf16)v[8 * hf + 2 * e2 + 1]};
+          wd[e2] = __builtin_bit_cast(unsigned, pr);
+        }
+        *reinterpret_cast<u4*>(reinterpret_cast<char*>(ghs) + hf * PSB + q * 16) = u4{wd[0], wd[1], wd[2], wd[3]};
+      }
+    } else {
+#pragma unroll
+      for (int co = 0; co < COUTP; ++co) ghs[co * PS + q] = v[co];
+    }
   };
   if constexpr (kAhead) {
     load_tile(len - 1);
@@ -330,12 +455,8 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
   for (int t = len - 1; t >= 0; --t) {
     __syncthreads();                                   // the previous frame's tile is consumed
     if constexpr (!kAhead) load_tile(t);
-#pragma unroll
-    for (int co = 0; co < COUTP; ++co) ghs[co * PS + threadIdx.x] = st0[co];
-    if (threadIdx.x < E * E - NTH) {
-#pragma unroll
-      for (int co = 0; co < COUTP; ++co) ghs[co * PS + threadIdx.x + NTH] = st1[co];
-    }
+    stage_entry(st0, threadIdx.x);
+    if (threadIdx.x < E * E - NTH) stage_entry(st1, threadIdx.x + NTH);
     __syncthreads();
     if constexpr (!kAhead) load_h(t);
     float hv[4][4];
@@ -352,24 +473,39 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
     f4 acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (kBF) {
 #pragma unroll
-    for (int s4 = 0; s4 < KS4; ++s4) {
-      const f4 w = wl[s4 * 64 + lane];
+      for (int s = 0; s < KSB; ++s) {
+        const int tap = 2 * s + (g >> 1) > 8 ? 8 : 2 * s + (g >> 1);     // tap 9: zero weights
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int imm = ((1 - dy) * E + (1 - dx)) * 16;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int s = 4 * s4 + u;
-        if (s < KS) {
-          const int tap = s / (COG / 4), cq = s % (COG / 4);
-          const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-          const int imm = (COUTP < 4 ? 0 : 4 * cq * PS) + (1 - dy) * E + (1 - dx);
+        for (int r = 0; r < 4; ++r) {
+          const u4 b = *reinterpret_cast<const u4*>(bbase16 + r * E * 16 + imm);
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, wb[s]), __builtin_bit_cast(bf8, b),
+                                                           acc[r], 0, 0, 0);
+        }
+      }
+    } else {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[u], bbase[r * E + imm], acc[r], 0, 0, 0);
+      for (int s4 = 0; s4 < KS4; ++s4) {
+        const f4 w = wl[s4 * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int s = 4 * s4 + u;
+          if (s < KS) {
+            const int tap = s / (COG / 4), cq = s % (COG / 4);
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            const int imm = (COUTP < 4 ? 0 : 4 * cq * PS) + (1 - dy) * E + (1 - dx);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[u], bbase[r * E + imm], acc[r], 0, 0, 0);
+          }
         }
       }
     }
     const __amdgpu_buffer_rsrc_t ro =
-        __builtin_amdgcn_make_buffer_rsrc(out + ((size_t)n * len + t) * Cin * HW, (short)0, (int)bytes, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(out + ((size_t)n * len + t) * Cin * HW, (short)0, (int)(nel * ESG), 0x00020000);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (y0 + r < H) {
@@ -378,7 +514,7 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
           const float Gv = acc[r][i];
           const float psi = surrogate(hv[r][i], theta, alpha, surr);
           const float gn = detach ? fmaf(Gv, psi, g_v[r][i]) : fmaf(fmaf(-theta, g_v[r][i], Gv), psi, g_v[r][i]);
-          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, gn), ro, voff[i], r * W * 4, 0);
+          st_el<GS>(gn, ro, voffG[i], r * W * ESG);
           g_v[r][i] = leak * gn;
         }
       }
@@ -438,8 +574,7 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
   for (int r = 0; r < 4; ++r)
     if (y0 + r < H) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, g_v[r][i]), rv, voff[i], r * W * 4, 0);
+      for (int i = 0; i < 4; ++i) st_el<float>(g_v[r][i], rv, voff[i], r * W * 4);
     }
 }
 
@@ -447,10 +582,12 @@ void k_convT_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int 
 // Per (tile, clip) workgroup over all frames of the segment: partial
 // dW[co][ci][tap] in registers; s_in is x (layer 1) or the spikes of the
 // layer below recomputed from its h.
-template <int CINP, int COUTP>
-__global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
+// IS: element type of the input (x: float; h of the layer below: its
+// storage type); GS: that of g_h.
+template <int CINP, int COUTP, class IS, class GS>
+__global__ __launch_bounds__(NTH) void k_dw(const GS* __restrict__ gh, int Cout, int Cin, int len, int H,
                                             int W, int tiles_x, const float* __restrict__ x,
-                                            long long x_nstride, int bf_x, const float* __restrict__ hseg,
+                                            long long x_nstride, int bf_x, const IS* __restrict__ hseg, HTrace ht,
                                             int sumc, int choff_in, float theta, float alpha, int relaxed,
                                             float* __restrict__ partial) {
   constexpr int P = CINP * COUTP;                     // (co, ci) pairs
@@ -477,38 +614,39 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
   // 32-bit byte offsets fixed for the whole segment; entries outside the
   // image (or past the real channels) get offsets of 2^31 and up, which read
   // 0 -- and 0 stages as 0 (its spike and its bf16 rounding are 0).
-  constexpr unsigned kDead = 0x80000000u;
+  constexpr unsigned ESI = sizeof(IS);
   unsigned goff[kGt], soff[kSt];
 #pragma unroll
   for (int k = 0; k < kGt; ++k) {
     const int e = threadIdx.x + NTH * k;
     const int co = e / (TT * TT), r = (e / TT) % TT, cc = e % TT;
     const int y = ty0 + r, xx = tx0 + cc;
-    goff[k] = (e < kG && co < Cout && y < H && xx < W) ? 4u * ((unsigned)co * (unsigned)HW + (unsigned)(y * W + xx))
-                                                       : kDead;
+    goff[k] = el_off<GS>(e < kG && co < Cout && y < H && xx < W, (unsigned)co * (unsigned)HW + (unsigned)(y * W + xx));
   }
 #pragma unroll
   for (int k = 0; k < kSt; ++k) {
     const int e = threadIdx.x + NTH * k;
     const int ci = e / ((TT + 2) * (TT + 2)), r = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
     const int y = ty0 - 1 + r, xx = tx0 - 1 + cc;
-    soff[k] = (e < kS && ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W)
-                  ? 4u * ((unsigned)ci * (unsigned)HW + (unsigned)(y * W + xx)) : kDead;
+    const bool live = e < kS && ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W;
+    // x: planar [ci][H][W]; h of the layer below: the pixel-major trace
+    const unsigned el = hseg ? (unsigned)(y * W + xx) * (unsigned)ht.cw + (unsigned)ci
+                             : (unsigned)ci * (unsigned)HW + (unsigned)(y * W + xx);
+    soff[k] = live ? ESI * el : kDeadOff;
   }
   float gpre[kGt], spre[kSt];
   auto fetch = [&](int t) __attribute__((always_inline)) {
     const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)(4u * Cout * HW), 0x00020000);
-    const float* sb = hseg ? hseg + (((size_t)n * len + t) * sumc + choff_in) * HW
-                           : x + (size_t)n * x_nstride + (size_t)t * Cin * HW;
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(sb), (short)0, (int)(4u * Cin * HW), 0x00020000);
+        const_cast<GS*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)((unsigned)sizeof(GS) * Cout * HW),
+        0x00020000);
+    const void* sb = hseg ? static_cast<const void*>(hseg + ht.base(n, len, t, HW))
+                          : static_cast<const void*>(x + (size_t)n * x_nstride + (size_t)t * Cin * HW);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void*>(sb), (short)0, (int)(ESI * (hseg ? (unsigned)ht.cw : (unsigned)Cin) * HW), 0x00020000);
 #pragma unroll
-    for (int k = 0; k < kGt; ++k)
-      gpre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, goff[k], 0, 0));
+    for (int k = 0; k < kGt; ++k) gpre[k] = ld_el<GS>(rg, goff[k], 0);
 #pragma unroll
-    for (int k = 0; k < kSt; ++k)
-      spre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, soff[k], 0, 0));
+    for (int k = 0; k < kSt; ++k) spre[k] = ld_el<IS>(rs, soff[k], 0);
   };
   fetch(0);
   for (int t = 0; t < len; ++t) {
@@ -589,15 +727,23 @@ __global__ __launch_bounds__(NTH) void k_dw(const float* __restrict__ gh, int Co
 // the tap column (16-byte operand reads), are staged in LDS from registers
 // that were loaded during the previous frame's products; wave w takes pixel
 // rows 4w .. 4w+3, and the four waves' partials are added in wave order at
-// the end (fixed association: reproducible).
+// the end (fixed association: reproducible).  BF16 nets (B16) store g_h in
+// bf16 already: one part, a third of the products.
 constexpr int kGspBytes = 3 * 16 * TT * TT * 2;          // g_h parts [part][co][pixel]
 constexpr int kSsbBytes = 3 * 16 * (TT + 2) * TT * 2;    // spikes [dx][ci][row][col]
-constexpr int kSsPerThread = (16 * (TT + 2) * (TT + 2) + NTH - 1) / NTH;
+// spike staging: (haloed pixel, 8-channel half) vectors of the pixel-major trace
+constexpr int kSsVec = 2 * (TT + 2) * (TT + 2);
+constexpr int kSsPerThread = (kSsVec + NTH - 1) / NTH;
 __device__ inline uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 
-__global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, int Cout, int Cin, int len, int H,
-                                                 int W, int tiles_x, const float* __restrict__ hseg, int sumc,
-                                                 int choff_in, float theta, float* __restrict__ partial) {
+template <bool B16>
+__global__ __launch_bounds__(NTH) void k_dw_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int Cin,
+                                                 int len, int H, int W, int tiles_x,
+                                                 const typename Store<B16>::H* __restrict__ hseg, HTrace ht,
+                                                 int sumc, int choff_in, float theta, float* __restrict__ partial) {
+  using HS = typename Store<B16>::H;
+  using GS = typename Store<B16>::G;
+  constexpr int NP = B16 ? 1 : 3;                      // bf16 parts of g_h
   __shared__ __attribute__((aligned(16))) char lds[kGspBytes + kSsbBytes];
   uint16_t* const gsp = reinterpret_cast<uint16_t*>(lds);
   uint16_t* const ssb = reinterpret_cast<uint16_t*>(lds + kGspBytes);
@@ -611,30 +757,41 @@ __global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, i
   // loads through buffer resources bounded to the frame's planes, at 32-bit
   // byte offsets fixed for the segment; entries outside the image or past
   // the real channels sit at 2^31 and up and read 0 (whose spike is 0)
-  constexpr unsigned kDead = 0x80000000u;
-  const unsigned goff = (gy < H && gx < W) ? 4u * (unsigned)(gy * W + gx) : kDead;
-  unsigned soff[kSsPerThread];
+  constexpr unsigned ESG = sizeof(GS), ESH = sizeof(HS);
+  const unsigned goff = el_off<GS>(gy < H && gx < W, (unsigned)(gy * W + gx));
+  // vector v: haloed pixel v / 2, channels 8 (v & 1) .. +7 as two loads
+  // of four (consecutive lanes read consecutive memory); channels at or past
+  // the trace block's width cw (a multiple of 4, at most 16) read 0.
+  unsigned soff[kSsPerThread][2];
 #pragma unroll
   for (int k = 0; k < kSsPerThread; ++k) {
-    const int e = threadIdx.x + NTH * k;
-    const int ci = e / ((TT + 2) * (TT + 2)), rr = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+    const int v = threadIdx.x + NTH * k, q = v >> 1;
+    const int rr = q / (TT + 2), cc = q % (TT + 2);
     const int y = ty0 - 1 + rr, xx = tx0 - 1 + cc;
-    soff[k] = (e < 16 * (TT + 2) * (TT + 2) && ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W)
-                  ? 4u * ((unsigned)ci * (unsigned)HW + (unsigned)(y * W + xx)) : kDead;
+    const bool in = v < kSsVec && y >= 0 && y < H && xx >= 0 && xx < W;
+#pragma unroll
+    for (int hq = 0; hq < 2; ++hq) {
+      const int c0 = 8 * (v & 1) + 4 * hq;
+      soff[k][hq] = el_off<HS>(in && c0 < ht.cw, (unsigned)(y * W + xx) * (unsigned)ht.cw + (unsigned)c0);
+    }
   }
-  float gr[16], hr[kSsPerThread];
+  float gr[16], hr[kSsPerThread][8];
   auto fetch = [&](int t) __attribute__((always_inline)) {
     const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)(4u * Cout * HW), 0x00020000);
+        const_cast<GS*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)(ESG * Cout * HW), 0x00020000);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(hseg + (((size_t)n * len + t) * sumc + choff_in) * HW), (short)0, (int)(4u * Cin * HW),
-        0x00020000);
+        const_cast<HS*>(hseg + ht.base(n, len, t, HW)), (short)0, (int)(ESH * (unsigned)ht.cw * HW), 0x00020000);
 #pragma unroll
-    for (int co = 0; co < 16; ++co)
-      gr[co] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, goff + 4u * co * HW, 0, 0));
+    for (int co = 0; co < 16; ++co) gr[co] = ld_el<GS>(rg, goff + ESG * co * HW, 0);
 #pragma unroll
-    for (int k = 0; k < kSsPerThread; ++k)
-      hr[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, soff[k], 0, 0));
+    for (int k = 0; k < kSsPerThread; ++k) {
+      const f4 a = ld4_el<HS>(rs, soff[k][0], 0), b = ld4_el<HS>(rs, soff[k][1], 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        hr[k][i] = a[i];
+        hr[k][4 + i] = b[i];
+      }
+    }
   };
   f4 acc[9];
 #pragma unroll
@@ -645,21 +802,29 @@ __global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, i
 #pragma unroll
     for (int co = 0; co < 16; ++co) {
       const float v = gr[co];
-      const float h = (float)(__bf16)v, r = v - h, m = (float)(__bf16)r;
-      gsp[(0 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(h);
-      gsp[(1 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(m);
-      gsp[(2 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(r - m);
+      if constexpr (B16) {
+        gsp[co * TT * TT + threadIdx.x] = bf16_bits(v);        // exact: v is a bf16 value
+      } else {
+        const float h = (float)(__bf16)v, r = v - h, m = (float)(__bf16)r;
+        gsp[(0 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(h);
+        gsp[(1 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(m);
+        gsp[(2 * 16 + co) * TT * TT + threadIdx.x] = bf16_bits(r - m);
+      }
     }
 #pragma unroll
     for (int k = 0; k < kSsPerThread; ++k) {
-      const int e = threadIdx.x + NTH * k;
-      if (e < 16 * (TT + 2) * (TT + 2)) {
-        const int ci = e / ((TT + 2) * (TT + 2)), rr = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
-        const uint16_t b = bf16_bits(spike_of(hr[k], theta, 0.f, 0));
+      const int v = threadIdx.x + NTH * k, q = v >> 1;
+      if (v < kSsVec) {
+        const int rr = q / (TT + 2), cc = q % (TT + 2);
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          const int c2 = cc - dx;
-          if (c2 >= 0 && c2 < TT) ssb[((dx * 16 + ci) * (TT + 2) + rr) * TT + c2] = b;
+        for (int i = 0; i < 8; ++i) {
+          const int ci = 8 * (v & 1) + i;
+          const uint16_t b = bf16_bits(spike_of(hr[k][i], theta, 0.f, 0));
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            const int c2 = cc - dx;
+            if (c2 >= 0 && c2 < TT) ssb[((dx * 16 + ci) * (TT + 2) + rr) * TT + c2] = b;
+          }
         }
       }
     }
@@ -670,15 +835,15 @@ __global__ __launch_bounds__(NTH) void k_dw_mfma(const float* __restrict__ gh, i
       // k-step: pixel rows 4 wave + 2q, +1; lane group g takes 8 pixels of
       // row 4 wave + 2q + g/2 starting at column 8 (g & 1)
       const int row = 4 * wave + 2 * q + (g >> 1), c0 = 8 * (g & 1);
-      u4 a[3];
+      u4 a[NP];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) a[b] = *reinterpret_cast<const u4*>(gsp + (b * 16 + j) * TT * TT + row * TT + c0);
+      for (int b = 0; b < NP; ++b) a[b] = *reinterpret_cast<const u4*>(gsp + (b * 16 + j) * TT * TT + row * TT + c0);
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap % 3;
         const u4 bv = *reinterpret_cast<const u4*>(ssb + ((dx * 16 + j) * (TT + 2) + row + dy) * TT + c0);
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+        for (int b = 0; b < NP; ++b)
           acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[b]), __builtin_bit_cast(bf8, bv),
                                                             acc[tap], 0, 0, 0);
       }
@@ -743,45 +908,58 @@ __global__ void k_dw_out(const float* __restrict__ acc, int Cout, int Cin, int C
 }
 
 struct ConvTArgs {
-  const float* gh; int Cout, Cin, len, H, W, tiles_x; const float* wT;
-  float* out; long long ons, ots;
-  const float* hseg; int sumc, choff; float* gv; float theta, leak, alpha; int surr, detach;
+  const void* gh; int Cout, Cin, len, H, W, tiles_x; const float* wT;
+  void* out; long long ons, ots;
+  const void* hseg; HTrace ht; int sumc, choff; float* gv; float theta, leak, alpha; int surr, detach;
   int relaxed; float* dw_partial;     // the fused weight gradient of narrow layers
 };
-template <int CINP, int COUTP>
+template <int CINP, int COUTP, bool B16>
 void launch_convT(dim3 g, hipStream_t st, bool adj, const ConvTArgs& a) {
+  using HS = typename Store<B16>::H;
+  using GS = typename Store<B16>::G;
+  const GS* gh = static_cast<const GS*>(a.gh);
+  const HS* hseg = static_cast<const HS*>(a.hseg);
   // hidden layers have equal widths, so the matrix-pipe kernel serves 16-wide
   // hidden layers below a 16-wide layer or the output layer
   if constexpr (CINP == 16 && COUTP <= 16) {
     if (adj) {
-      hipLaunchKernelGGL((k_convT_mfma<COUTP>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
-                         a.tiles_x, a.wT, a.out, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha, a.surr,
-                         a.detach, a.relaxed, a.dw_partial);
+      hipLaunchKernelGGL((k_convT_mfma<COUTP, B16>), g, dim3(NTH), 0, st, gh, a.Cout, a.Cin, a.len, a.H, a.W,
+                         a.tiles_x, a.wT, static_cast<GS*>(a.out), hseg, a.ht, a.sumc, a.choff, a.gv, a.theta, a.leak,
+                         a.alpha, a.surr, a.detach, a.relaxed, a.dw_partial);
       return;
     }
   } else {
     if (adj) {
-      hipLaunchKernelGGL((k_convT<CINP, COUTP, true>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
-                         a.tiles_x, a.wT, a.out, a.ons, a.ots, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak,
+      hipLaunchKernelGGL((k_convT<CINP, COUTP, true, HS, GS>), g, dim3(NTH), 0, st, gh, a.Cout, a.Cin, a.len, a.H,
+                         a.W, a.tiles_x, a.wT, a.out, a.ons, a.ots, hseg, a.ht, a.sumc, a.choff, a.gv, a.theta, a.leak,
                          a.alpha, a.surr, a.detach);
       return;
     }
   }
-  hipLaunchKernelGGL((k_convT<CINP, COUTP, false>), g, dim3(NTH), 0, st, a.gh, a.Cout, a.Cin, a.len, a.H, a.W,
-                       a.tiles_x, a.wT, a.out, a.ons, a.ots, a.hseg, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha,
-                       a.surr, a.detach);
+  hipLaunchKernelGGL((k_convT<CINP, COUTP, false, HS, GS>), g, dim3(NTH), 0, st, gh, a.Cout, a.Cin, a.len, a.H, a.W,
+                     a.tiles_x, a.wT, a.out, a.ons, a.ots, hseg, a.ht, a.sumc, a.choff, a.gv, a.theta, a.leak, a.alpha,
+                     a.surr, a.detach);
 }
-template <int CINP, int COUTP>
-void launch_dw(dim3 g, hipStream_t st, const float* gh, int Cout, int Cin, int len, int H, int W, int tx,
-               const float* x, long long xns, int bfx, const float* hseg, int sumc, int choff_in, float theta,
+template <int CINP, int COUTP, bool B16>
+void launch_dw(dim3 g, hipStream_t st, const void* ghv, int Cout, int Cin, int len, int H, int W, int tx,
+               const float* x, long long xns, int bfx, const void* hsegv, HTrace ht, int sumc, int choff_in, float theta,
                float alpha, int relaxed, float* partial) {
+  using HS = typename Store<B16>::H;
+  using GS = typename Store<B16>::G;
+  const GS* gh = static_cast<const GS*>(ghv);
+  const HS* hseg = static_cast<const HS*>(hsegv);
   if (CINP == 16 && COUTP == 16 && hseg && !relaxed) {   // hard spikes in: bf16 matrix pipe
-    hipLaunchKernelGGL(k_dw_mfma, g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, hseg, sumc, choff_in, theta,
-                       partial);
+    hipLaunchKernelGGL(k_dw_mfma<B16>, g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, hseg, ht, sumc, choff_in,
+                       theta, partial);
     return;
   }
-  hipLaunchKernelGGL((k_dw<CINP, COUTP>), g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, x, xns, bfx, hseg,
-                     sumc, choff_in, theta, alpha, relaxed, partial);
+  if (hseg) {
+    hipLaunchKernelGGL((k_dw<CINP, COUTP, HS, GS>), g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, x, xns, bfx,
+                       hseg, ht, sumc, choff_in, theta, alpha, relaxed, partial);
+  } else {
+    hipLaunchKernelGGL((k_dw<CINP, COUTP, float, GS>), g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, x, xns,
+                       bfx, static_cast<const float*>(nullptr), ht, sumc, choff_in, theta, alpha, relaxed, partial);
+  }
 }
 
 #define EVS_DISPATCH_PAD(CI, CO, CALL)                                   \
@@ -797,6 +975,14 @@ void launch_dw(dim3 g, hipStream_t st, const float* gh, int Cout, int Cin, int l
     else CALL(32, 32);                                                   \
   } while (0)
 
+// Planes per frame of the pixel-major segment trace: every hidden layer's
+// width rounded up to a multiple of 4, and 4 for the output layer.
+int trace_planes(const evs_net& net) {
+  int tp = 4;
+  for (int l = 1; l < net.n_layers; ++l) tp += (net.ch[l] + 3) & ~3;
+  return tp;
+}
+
 struct BwdLayout {
   size_t hseg, gv, gh, gh2, partial, acc, wT, total;
   int k, nseg, cmax, tiles_x, tiles_y;
@@ -807,6 +993,7 @@ BwdLayout layout(const evs_net& net, const evs_clip& c, int k) {
   const size_t HW = (size_t)c.H * c.W;
   const int sumc = real_sum_channels(net);
   int cmax = 0, accsum = 0;
+  const int tp = trace_planes(net);
   for (int l = 1; l <= net.n_layers; ++l) {
     cmax = net.ch[l] > cmax ? net.ch[l] : cmax;
     const int e = pad_in(net.ch[l - 1]) * pad_out(net.ch[l]) * 9;
@@ -818,11 +1005,13 @@ BwdLayout layout(const evs_net& net, const evs_clip& c, int k) {
   L.tiles_x = (c.W + TT - 1) / TT;
   L.tiles_y = (c.H + TT - 1) / TT;
   const size_t nblk = (size_t)L.tiles_x * L.tiles_y * c.N;
+  // segment potentials and adjoints: fp16 / bf16 for BF16 nets, else float
+  const size_t es = net.precision == EVS_BF16 ? 2 : 4;
   size_t o = 0;
-  L.hseg = o; o += align256((size_t)c.N * k * sumc * HW * 4);
+  L.hseg = o; o += align256((size_t)c.N * k * tp * HW * es);
   L.gv = o; o += align256((size_t)c.N * sumc * HW * 4);
-  L.gh = o; o += align256((size_t)c.N * k * cmax * HW * 4);
-  L.gh2 = o; o += align256((size_t)c.N * k * cmax * HW * 4);
+  L.gh = o; o += align256((size_t)c.N * k * cmax * HW * es);
+  L.gh2 = o; o += align256((size_t)c.N * k * cmax * HW * es);
   L.partial = o; o += align256(nblk * accsum * 4);
   L.acc = o; o += align256((size_t)accsum * 4);
   L.wT = o; o += align256((size_t)accsum * 4);
@@ -837,33 +1026,20 @@ size_t backward_workspace_bytes(const evs_net& net, const evs_clip& clip, int ck
   return layout(net, clip, ckpt_every < clip.T ? ckpt_every : clip.T).total;
 }
 
-int backward(const evs_net& net, const void* packed, const evs_clip& clip, const float* ckpt, int ckpt_every,
-             const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v, void* ws, size_t ws_bytes,
-             int32_t* status, hipStream_t st) {
-  int rc = validate_net(&net);
-  if (rc) return rc;
-  if (net.input != EVS_INPUT_DIRECT)
-    return fail(EVS_EUNSUPPORTED, "backward: direct input only (pass the output of evs_logdiff)");
-  if ((rc = validate_clip(net, clip, true))) return rc;
-  if (!packed || !ckpt || !grad_s || !grad_w) return fail(EVS_EINVAL, "backward: NULL argument");
-  if (ckpt_every < 1) return fail(EVS_EINVAL, "backward: ckpt_every must be >= 1");
-  if ((reinterpret_cast<uintptr_t>(status) & 3u) != 0) return fail(EVS_EINVAL, "backward: dev_status must be 4-byte aligned");
-  for (int l = 0; l < net.n_layers; ++l)
-    if (!grad_w[l]) return fail(EVS_EINVAL, "backward: NULL grad_w entry");
-  // the gradient kernels address a frame's planes of one layer with 32-bit
-  // byte offsets
-  if ((size_t)32 * clip.H * clip.W * 4 >= ((size_t)1 << 31))
-    return fail(EVS_EUNSUPPORTED, "backward: frame too large (32 x H x W x 4 bytes must stay below 2 GiB)");
-  const int k = ckpt_every < clip.T ? ckpt_every : clip.T;
-  const BwdLayout Lo = layout(net, clip, k);
-  if (!ws || ws_bytes < Lo.total) return fail(EVS_EWORKSPACE, "backward: workspace too small");
-  // the checkpoints were written with ceil(T / ckpt_every) segments
-  const int nseg_ck = (clip.T + ckpt_every - 1) / ckpt_every;
+// The segment loop of the backward (see the top of this file); B16: the
+// storage of BF16 nets (Store<true>).
+template <bool B16>
+int run_backward(const evs_net& net, const void* packed, const evs_clip& clip, const float* ckpt, int ckpt_every,
+                 int k, const BwdLayout& Lo, int nseg_ck, const float* grad_s, float* const* grad_w, float* grad_x,
+                 float* grad_v, void* ws, int32_t* status, hipStream_t st) {
+  using HS = typename Store<B16>::H;
+  using GS = typename Store<B16>::G;
+  int rc = 0;
   char* w8 = reinterpret_cast<char*>(ws);
-  float* hseg = reinterpret_cast<float*>(w8 + Lo.hseg);
+  HS* hseg = reinterpret_cast<HS*>(w8 + Lo.hseg);
   float* gv = reinterpret_cast<float*>(w8 + Lo.gv);
   // g_h of layer l and of the layer below, swapped after each layer
-  float* ghb[2] = {reinterpret_cast<float*>(w8 + Lo.gh), reinterpret_cast<float*>(w8 + Lo.gh2)};
+  GS* ghb[2] = {reinterpret_cast<GS*>(w8 + Lo.gh), reinterpret_cast<GS*>(w8 + Lo.gh2)};
   float* partial = reinterpret_cast<float*>(w8 + Lo.partial);
   float* acc = reinterpret_cast<float*>(w8 + Lo.acc);
   float* wT = reinterpret_cast<float*>(w8 + Lo.wT);
@@ -876,6 +1052,14 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
   const float* wbase = reinterpret_cast<const float*>(packed);
   int choff[4] = {0, 0, 0, 0};
   for (int l = 1; l < L; ++l) choff[l] = choff[l - 1] + net.ch[l];   // choff[l-1] = offset of layer l
+  // the layers' blocks in the pixel-major segment trace: ht[l - 1] is layer l
+  const int tpf = trace_planes(net);
+  HTrace ht[4];
+  for (int l = 1, o = 0; l <= L; ++l) {
+    const int cw = l == L ? 4 : (net.ch[l] + 3) & ~3;
+    ht[l - 1] = HTrace{tpf, o, cw};
+    o += cw;
+  }
   int accofs[4] = {0, 0, 0, 0};
   for (int l = 1; l <= L; ++l) accofs[l] = accofs[l - 1] + pad_in(net.ch[l - 1]) * pad_out(net.ch[l]) * 9;
 
@@ -907,8 +1091,10 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
     if (t0 % ckpt_every != 0) return fail(EVS_EINVAL, "backward: segment start is not a checkpoint");
     ca.v_in = ckpt + (size_t)(t0 / ckpt_every) * sumc * HW;
     ca.vin_nstride = (long long)nseg_ck * sumc * HW;
-    ca.h_trace = hseg;
-    ca.trace_nstride = (long long)len * sumc * HW;
+    ca.h_trace = reinterpret_cast<float*>(hseg);
+    ca.trace_f16 = B16 ? 1 : 0;
+    ca.trace_pm = 1;
+    ca.trace_nstride = (long long)len * tpf * HW;
     ca.tb_y0 = 0; ca.tb_x0 = 0; ca.tb_h = H; ca.tb_w = W;
     ca.N = N; ca.T = len; ca.H = H; ca.W = W;
     ca.tiles_x = (W + tw - 1) / tw;
@@ -920,7 +1106,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
     {
       const int C = net.ch[L];
       const long long tot = (long long)N * C * HW;
-      hipLaunchKernelGGL(k_adjoint, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, hseg, sumc,
+      hipLaunchKernelGGL((k_adjoint<HS, GS>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, hseg, ht[L - 1], sumc,
                          choff[L - 1], C, len, N, (int)HW, grad_s + (size_t)t0 * cout * HW, (long long)T * cout * HW,
                          (long long)cout * HW, ghb[0], gv, net.theta, net.leak, net.surr_alpha, net.surrogate,
                          net.detach_reset, status);
@@ -929,7 +1115,7 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
     int cur = 0;
     for (int l = L; l >= 1; --l) {
       const int C = net.ch[l], Cin = net.ch[l - 1];
-      float* gh = ghb[cur];
+      GS* gh = ghb[cur];
       // weight gradient partials for this segment (a narrow layer above a
       // 16-wide one forms them inside its conv-transpose), then the
       // fixed-order reduction; then the g_h of the layer below (the
@@ -938,11 +1124,11 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
       const bool fused_dw = l >= 2 && CI == 16 && CO <= 4;
       const dim3 gdw((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)N);
       if (!fused_dw) {
-        const float* hin = l >= 2 ? hseg : nullptr;
+        const HS* hin = l >= 2 ? hseg : nullptr;
         const int choff_in = l >= 2 ? choff[l - 2] : 0;
 #define EVS_CALL_DW(A, B)                                                                              \
-  launch_dw<A, B>(gdw, st, gh, C, Cin, len, H, W, Lo.tiles_x, clip.x + (size_t)t0 * cin0 * HW,          \
-                  (long long)T * cin0 * HW, bf ? 1 : 0, hin, sumc, choff_in, net.theta, net.surr_alpha, \
+  launch_dw<A, B, B16>(gdw, st, gh, C, Cin, len, H, W, Lo.tiles_x, clip.x + (size_t)t0 * cin0 * HW,          \
+                  (long long)T * cin0 * HW, bf ? 1 : 0, hin, ht[l >= 2 ? l - 2 : 0], sumc, choff_in, net.theta, net.surr_alpha, \
                   net.relaxed ? 1 + net.surrogate : 0, partial + nblk * accofs[l - 1])
         EVS_DISPATCH_PAD(CI, CO, EVS_CALL_DW);
 #undef EVS_CALL_DW
@@ -959,14 +1145,14 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
         a.dw_partial = partial + nblk * accofs[l - 1];
         if (l >= 2) {
           a.out = ghb[cur ^ 1];
-          a.hseg = hseg; a.choff = choff[l - 2]; a.gv = gv;
+          a.hseg = hseg; a.ht = ht[l - 2]; a.choff = choff[l - 2]; a.gv = gv;
         } else {
           a.out = grad_x + (size_t)t0 * cin0 * HW;
           a.ons = (long long)T * cin0 * HW;
           a.ots = (long long)cin0 * HW;
         }
         const dim3 gct((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)N);
-#define EVS_CALL_CT(A, B) launch_convT<A, B>(gct, st, l >= 2, a)
+#define EVS_CALL_CT(A, B) launch_convT<A, B, B16>(gct, st, l >= 2, a)
         EVS_DISPATCH_PAD(CI, CO, EVS_CALL_CT);
 #undef EVS_CALL_CT
         EVS_HIP(hipGetLastError());
@@ -993,6 +1179,35 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
     if ((rc = copy_f32(grad_v, gv, (size_t)N * sumc * HW, st))) return rc;
   }
   return EVS_OK;
+}
+
+int backward(const evs_net& net, const void* packed, const evs_clip& clip, const float* ckpt, int ckpt_every,
+             const float* grad_s, float* const* grad_w, float* grad_x, float* grad_v, void* ws, size_t ws_bytes,
+             int32_t* status, hipStream_t st) {
+  int rc = validate_net(&net);
+  if (rc) return rc;
+  if (net.input != EVS_INPUT_DIRECT)
+    return fail(EVS_EUNSUPPORTED, "backward: direct input only (pass the output of evs_logdiff)");
+  if ((rc = validate_clip(net, clip, true))) return rc;
+  if (!packed || !ckpt || !grad_s || !grad_w) return fail(EVS_EINVAL, "backward: NULL argument");
+  if (ckpt_every < 1) return fail(EVS_EINVAL, "backward: ckpt_every must be >= 1");
+  if ((reinterpret_cast<uintptr_t>(status) & 3u) != 0) return fail(EVS_EINVAL, "backward: dev_status must be 4-byte aligned");
+  for (int l = 0; l < net.n_layers; ++l)
+    if (!grad_w[l]) return fail(EVS_EINVAL, "backward: NULL grad_w entry");
+  // the gradient kernels address a frame's planes of one layer with 32-bit
+  // byte offsets
+  if ((size_t)32 * clip.H * clip.W * 4 >= ((size_t)1 << 31))
+    return fail(EVS_EUNSUPPORTED, "backward: frame too large (32 x H x W x 4 bytes must stay below 2 GiB)");
+  const int k = ckpt_every < clip.T ? ckpt_every : clip.T;
+  const BwdLayout Lo = layout(net, clip, k);
+  if (!ws || ws_bytes < Lo.total) return fail(EVS_EWORKSPACE, "backward: workspace too small");
+  // the checkpoints were written with ceil(T / ckpt_every) segments
+  const int nseg_ck = (clip.T + ckpt_every - 1) / ckpt_every;
+  if (net.precision == EVS_BF16)
+    return run_backward<true>(net, packed, clip, ckpt, ckpt_every, k, Lo, nseg_ck, grad_s, grad_w, grad_x, grad_v, ws,
+                              status, st);
+  return run_backward<false>(net, packed, clip, ckpt, ckpt_every, k, Lo, nseg_ck, grad_s, grad_w, grad_x, grad_v, ws,
+                             status, st);
 }
 
 }  // namespace evs

@@ -56,7 +56,9 @@ constexpr int align16(int b) { return (b + 15) & ~15; }
 
 // MODE_: 0 = inference; 1 = training/debug features (h traces, membrane
 // checkpoints, FP32 spike output); 2 = relaxed (smooth) spikes with the
-// features of mode 1.  Only mode 0 leaves the feature code out of the loop.
+// features of mode 1; 3 = the backward's segment recompute (the charged
+// potentials of every layer into its pixel-major trace, nothing else).
+// Only mode 0 leaves the feature code out of the loop.
 // MODE_ + 4 (one-channel FP32 nets): x holds RGB frames and the input of
 // Eq. (1) is formed while staging.
 template <int NL_, int CIN_, int CH_, bool BF16_, int TH_, int TW_, int NW_, int MODE_>
@@ -64,7 +66,10 @@ struct Cfg {
   static constexpr int NL = NL_, CIN = CIN_, CH = CH_, TH = TH_, TW = TW_, NW = NW_, MODE = MODE_;
   static constexpr int BMODE = MODE_ & 3;
   static constexpr bool LOGX = MODE_ >= 4;
-  static constexpr bool BF16 = BF16_, FULL = BMODE == 1 || BMODE == 2, RELAX = BMODE == 2;
+  static constexpr bool BF16 = BF16_, FULL = BMODE != 0, RELAX = BMODE == 2, REC = BMODE == 3;
+  // checkpoints and FP32 spike output (training / debug builds)
+  static constexpr bool CKS = FULL && !REC;
+  static_assert(!(REC && MODE_ >= 4), "recompute builds take direct input");
   static_assert(!LOGX || (CIN_ == 1 && !BF16_), "RGB input: one-channel FP32 nets");
   static_assert(!(BF16_ && MODE_ == 2), "relaxed spikes are FP32 only");
   static constexpr int CO = 2;                       // output channels (max)
@@ -540,6 +545,32 @@ struct TraceBox {
   __device__ size_t plane() const { return (size_t)h * w; }
 };
 
+// One frame of the potential trace.  Training / debug builds: float,
+// planar [sumC][h][w] over the window; relaxed builds: that, or (pm, the
+// backward's traces) pixel-major: layer li at off[li] planes of the frame,
+// cw[li] values per pixel.  p == nullptr: no trace.  Layer index li: 0, 1
+// the hidden layers, 2 the output layer.  Recompute builds use rs / t16
+// (rec_store*).
+struct TraceFrame {
+  char* p;
+  int pm;
+  float theta;        // unscaled threshold
+  int off[3], cw[3];
+  // recompute builds: the frame's layer blocks as buffer resources (hidden
+  // 1, hidden 2, output), stores at 32-bit byte offsets; t16 the bits of the
+  // smallest fp16 value >= theta (fp16 traces)
+  __amdgpu_buffer_rsrc_t rs[3];
+  unsigned t16;
+  // element index; PM: pixel-major layouts are possible (relaxed builds)
+  template <bool PM>
+  __device__ size_t idx(int li, int choff, int co, size_t pix, size_t plane) const {
+    return (PM && pm) ? (size_t)off[li] * plane + pix * cw[li] + co : (size_t)(choff + co) * plane + pix;
+  }
+  __device__ void put(size_t e, float h) const { reinterpret_cast<float*>(p)[e] = h; }
+  // four consecutive values at e (a multiple of 4): one 16-byte store
+  __device__ void put4(size_t e, f4 v) const { *reinterpret_cast<f4*>(reinterpret_cast<float*>(p) + e) = v; }
+};
+
 // LDS plane index (front pad included) of pixel 16b + j of layer l's region,
 // and whether that neuron is a real one (inside the region and the image).
 template <class C>
@@ -556,6 +587,64 @@ __device__ __forceinline__ int block_pixel(int l, int b, int j, int gy0, int gx0
   return C::PADF + row * C::CWT + col;
 }
 
+// Trace stores of the recompute builds.  fp16 (BF16 nets): round toward
+// zero, then a firing neuron whose magnitude fell below the threshold is
+// raised to t16, the smallest fp16 value >= theta (it is the fp16 neighbour
+// above), so the stored value gives the forward's spike; sp holds the
+// pair's spikes as 16-bit +-1 / 0 (bf16 or fp16 bits), any nonzero half
+// firing.  NaN stays NaN.
+__device__ inline unsigned rec_f16_pair(float h0, float h1, unsigned sp, unsigned t16) {
+  typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+  const unsigned q = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(h0, h1));
+  const us2 fire = __builtin_bit_cast(us2, sp & 0x7fff7fffu) >> (unsigned short)13;   // 1 per firing half
+  const us2 lo = fire * (unsigned short)t16;
+  const us2 mag = __builtin_bit_cast(us2, q & 0x7fff7fffu);
+  const us2 m2 = mag > lo ? mag : lo;
+  return (__builtin_bit_cast(unsigned, m2)) | (q & 0x80008000u);
+}
+// A recompute build's store of a lane's four (hidden) or two (output)
+// channel values of one pixel at element offset e of a layer block.
+template <class C>
+__device__ inline void rec_store4(const TraceFrame& tr, int li, unsigned e, f4 h, uint2 sp) {
+  if constexpr (C::BF16) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 v = {rec_f16_pair(h[0], h[1], sp.x, tr.t16), rec_f16_pair(h[2], h[3], sp.y, tr.t16)};
+    __builtin_amdgcn_raw_buffer_store_b64(v, tr.rs[li], e * 2u, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, h), tr.rs[li], e * 4u, 0, 0);
+  }
+}
+template <class C>
+__device__ inline void rec_store2(const TraceFrame& tr, unsigned e, float h0, float h1, float s0, float s1) {
+  if constexpr (C::BF16) {
+    __builtin_amdgcn_raw_buffer_store_b32(rec_f16_pair(h0, h1, pack_f16x2(s0, s1), tr.t16), tr.rs[2], e * 2u, 0, 0);
+  } else {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 v = {__builtin_bit_cast(unsigned, h0), __builtin_bit_cast(unsigned, h1)};
+    __builtin_amdgcn_raw_buffer_store_b64(v, tr.rs[2], e * 4u, 0, 0);
+  }
+}
+template <class C>
+__device__ inline void rec_store1(const TraceFrame& tr, unsigned e, float h, float s) {
+  if constexpr (C::BF16) {
+    const unsigned v = rec_f16_pair(h, 0.f, pack_f16x2(s, 0.f), tr.t16);
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, tr.rs[2], e * 2u, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), tr.rs[2], e * 4u, 0, 0);
+  }
+}
+// Element offset of an output or hidden pixel of the tile interior in the
+// recompute trace (pixel-major), or the dead offset past the block when the
+// canvas pixel p is not an interior pixel inside the image.
+template <class C>
+__device__ inline unsigned rec_pix(int p, bool valid, int gy0, int gx0, int H, int W, int cw) {
+  const int q = p - C::PADF, row = q / C::CWT, col = q - row * C::CWT;
+  const int gy = gy0 + row, gx = gx0 + col;
+  const bool in = valid && (unsigned)(row - C::NL) < (unsigned)C::TH && (unsigned)(col - C::NL) < (unsigned)C::TW &&
+                  gy < H && gx < W;
+  return in ? (unsigned)(gy * W + gx) * (unsigned)cw : 0x20000000u;   // (x 2 or 4 bytes: past the block)
+}
+
 // Hidden-layer epilogue for one 16-pixel block: st holds the charged
 // potentials h of MB x 4 (channel, pixel) pairs of this lane; fire, reset,
 // write spikes to LDS and, optionally, h to the trace.  TOY (the last hidden
@@ -564,21 +653,34 @@ __device__ __forceinline__ int block_pixel(int l, int b, int j, int gy0, int gx0
 // stored to the Y planes at region pixel yq.
 template <class C, bool TOY = false>
 __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int sp_off, int p, bool valid, int g,
-                                                float theta, float alpha, int relaxed, float* trace_t, float tscale,
+                                                float theta, float alpha, int relaxed, const TraceFrame& tr, float tscale,
                                                 int cl, int choff, int gy0, int gx0, const TraceBox& tb,
-                                                const u4 (*ay)[C::KY] = nullptr, int yq = 0) {
-  if (C::FULL && trace_t && valid) {
+                                                const u4 (*ay)[C::KY] = nullptr, int yq = 0, int li = 0) {
+  f4 hsave[C::REC ? C::MB : 1];
+  if constexpr (C::REC) {
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m) hsave[m] = st[m] * tscale;
+  }
+  if (C::FULL && !C::REC && tr.p && valid) {
     const int row = (p - C::PADF) / C::CWT, col = (p - C::PADF) % C::CWT;
     const int gy = gy0 + row, gx = gx0 + col;
     if (row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW && tb.has(gy, gx)) {
       const size_t pix = tb.idx(gy, gx);
 #pragma unroll
-      for (int m = 0; m < C::MB; ++m)
+      for (int m = 0; m < C::MB; ++m) {
+        if (C::RELAX && tr.pm) {
+          // the lane's four channels 16m + 4g .. +3 of the pixel (padding
+          // channels of the layer hold 0 and are stored too)
+          if (16 * m + 4 * g < tr.cw[li])
+            tr.put4(tr.template idx<true>(li, choff, 16 * m + 4 * g, pix, tb.plane()), st[m] * tscale);
+        } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int co = 16 * m + 4 * g + r;
-          if (co < cl) trace_t[(size_t)(choff + co) * tb.plane() + pix] = st[m][r] * tscale;
+          for (int r = 0; r < 4; ++r) {
+            const int co = 16 * m + 4 * g + r;
+            if (co < cl) tr.put(tr.template idx<false>(li, choff, co, pix, tb.plane()), st[m][r] * tscale);
+          }
         }
+      }
     }
   }
   uint2 sw[C::MB];
@@ -600,6 +702,12 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
     if constexpr (C::S16) {
       sw[m] = C::SF16 ? uint2{pack_f16x2(s[0], s[1]), pack_f16x2(s[2], s[3])}
                       : uint2{pack_bf16x2(s[0], s[1]), pack_bf16x2(s[2], s[3])};
+      if constexpr (C::REC) {
+        // the lane's channels 16m + 4g .. +3 of the pixel (the layer's
+        // padding channels hold 0 and are stored too)
+        const unsigned e = rec_pix<C>(p, valid && 16 * m + 4 * g < tr.cw[li], gy0, gx0, tb.h, tb.w, tr.cw[li]);
+        rec_store4<C>(tr, li, e + 16 * m + 4 * g, hsave[m], sw[m]);
+      }
       // channels 16m + 4g .. +3: plane 2m + g/2, half (g & 1) of the pixel's 16 bytes
       if constexpr (!TOY)
         *reinterpret_cast<uint2*>(lds + Layout<C>::SP + sp_off + (2 * m + (g >> 1)) * C::SPL + p * 16 + 8 * (g & 1)) =
@@ -723,6 +831,16 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   const int c1 = na.ch[1], c2 = na.ch[2];
   const int cout = na.ch[na.n_layers];
   const int choff2 = c1, choffo = (C::NH == 0) ? 0 : (C::NH == 1 ? c1 : c1 + c2);
+  // pixel-major trace: widths rounded up to 4, layer offsets (in planes)
+  const int cp1 = (c1 + 3) & ~3, cp2 = (c2 + 3) & ~3;
+  const int tp1 = cp1, tpo = (C::NH == 0) ? 0 : (C::NH == 1 ? cp1 : cp1 + cp2), tpsum = tpo + 4;
+  // recompute builds of BF16 nets: bits of the smallest fp16 value >= theta
+  unsigned t16 = 0;
+  if constexpr (C::REC && C::BF16) {
+    const _Float16 q = (_Float16)theta;
+    const unsigned b = __builtin_bit_cast(unsigned short, q);
+    t16 = (float)q < theta ? b + 1 : b;
+  }
   const int gy0 = tl.ty0 - C::NL, gx0 = tl.tx0 - C::NL;   // image coords of canvas (0,0)
 
   // ---- LDS pixel of every block lane of every layer, and which neurons are real
@@ -996,12 +1114,23 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     const int (&e1)[C::NB1] = a1;
     const int (&e2)[C::NB2] = a2;
     const int (&eo)[C::NBO] = ao;
-    float* trace_t = nullptr;
-    if constexpr (C::FULL) {
+    TraceFrame trace_t{nullptr, ca.trace_pm, theta, {0, tp1, tpo}, {cp1, cp2, 4}, {}, t16};
+    if constexpr (C::CKS) {
       if (ca.ckpt && (t % ca.ckpt_every) == 0)
         write_state(ca.ckpt + ((size_t)tl.n * nseg + t / ca.ckpt_every) * sumc * HW);
-      trace_t = ca.h_trace ? ca.h_trace + (size_t)tl.n * ca.trace_nstride + (size_t)t * sumc * tb.plane()
-                           : nullptr;
+    }
+    if constexpr (C::REC) {
+      // the frame's three layer blocks of the pixel-major trace
+      constexpr unsigned es = C::BF16 ? 2 : 4;
+      char* const fb = reinterpret_cast<char*>(ca.h_trace) + ((size_t)tl.n * ca.trace_nstride + (size_t)t * tpsum * HW) * es;
+#pragma unroll
+      for (int li = 0; li < 3; ++li)
+        trace_t.rs[li] = __builtin_amdgcn_make_buffer_rsrc(fb + (size_t)trace_t.off[li] * HW * es, (short)0,
+                                                           (int)((unsigned)trace_t.cw[li] * (unsigned)HW * es), 0x00020000);
+    } else if constexpr (C::FULL) {
+      if (ca.h_trace)
+        trace_t.p = reinterpret_cast<char*>(ca.h_trace) +
+                    ((size_t)tl.n * ca.trace_nstride + (size_t)t * ((C::RELAX && ca.trace_pm) ? tpsum : sumc) * tb.plane()) * 4;
     }
 
     if constexpr (C::NH >= 1) {
@@ -1173,7 +1302,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           if (STAGE_IN_L2 && i < C::XPP && t + 1 < T) store_group(i);
           if (i > 0)
             hidden_epilogue<C, Y2>(st2[i - 1], lds, C::S2OFF, e2[i - 1], (vm2 >> (i - 1)) & 1u, g, theta2, alpha,
-                                   relaxed, trace_t, isc2, c2, choff2, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)));
+                                   relaxed, trace_t, isc2, c2, choff2, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)),
+                                   1);
         }
         if constexpr (STAGE_IN_L2) {
 #pragma unroll
@@ -1238,7 +1368,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
         for (int i = 0; i < C::NB2; ++i)
           hidden_epilogue<C>(st2[i], lds, C::S2OFF, e2[i], (vm2 >> i) & 1u, g, theta2, alpha, relaxed, trace_t, isc2,
-                             c2, choff2, gy0, gx0, tb);
+                             c2, choff2, gy0, gx0, tb, nullptr, 0, 1);
       }
       if constexpr (C::XDMA) {
         if (t + 2 < T) issue_x(t + 2, t & 1);
@@ -1263,17 +1393,19 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       auto out_epilogue = [&](int i, const f4& acc) __attribute__((always_inline)) {
         if (g < 2) {
           const float h = C::NSP == 2 ? acc[0] + acc[1] : acc[0];
-          if (C::FULL && oo[i] >= 0 && trace_t) {
+          if (C::FULL && !C::REC && oo[i] >= 0 && trace_t.p) {
             const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
             const int gy = gy0 + row, gx = gx0 + col;
-            if (tb.has(gy, gx)) trace_t[(size_t)(choffo + g) * tb.plane() + tb.idx(gy, gx)] = h * isc3;
+            if (tb.has(gy, gx)) trace_t.put(trace_t.template idx<C::RELAX>(2, choffo, g, tb.idx(gy, gx), tb.plane()), h * isc3);
           }
           float v = h;
           const float sp = bilif(v, theta3, alpha, false);
+          if constexpr (C::REC)
+            rec_store1<C>(trace_t, rec_pix<C>(ao[i], oo[i] >= 0, gy0, gx0, H, W, 4) + g, h * isc3, sp);
           asm volatile("" : "+v"(v));
           vo[i] = v;
           if (oo[i] >= 0 && ca.s_out) {
-            if (C::FULL && ca.s_fp32) s32[oo[i]] = sp;
+            if (C::CKS && ca.s_fp32) s32[oo[i]] = sp;
             else s8[oo[i]] = (int8_t)sp;
           }
         }
@@ -1351,19 +1483,25 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         const int q = tid + C::NT * k;
         const int gy = tl.ty0 + q / C::TW, gx = tl.tx0 + q % C::TW;
         const size_t pix = (size_t)gy * W + gx;
+        float hs[2], ss[2];
 #pragma unroll
         for (int co = 0; co < 2; ++co) {
           const float h = leak * so[k][co] + (co == 0 ? u0 : u1);
-          if (C::FULL && ok && co < cout && trace_t && tb.has(gy, gx))
-            trace_t[(size_t)(choffo + co) * tb.plane() + tb.idx(gy, gx)] = h * isc3;
+          if (C::FULL && !C::REC && ok && co < cout && trace_t.p && tb.has(gy, gx))
+            trace_t.put(trace_t.template idx<C::RELAX>(2, choffo, co, tb.idx(gy, gx), tb.plane()), h * isc3);
           float v = h;
           const float sp = bilif(v, theta3, alpha, false);
           so[k][co] = v;
+          hs[co] = h * isc3;
+          ss[co] = sp;
           if (ok && co < cout && ca.s_out) {
-            if (C::FULL && ca.s_fp32) s32[(size_t)co * HW + pix] = sp;
+            if (C::CKS && ca.s_fp32) s32[(size_t)co * HW + pix] = sp;
             else s8[(size_t)co * HW + pix] = (int8_t)sp;
           }
         }
+        // both channels of the pixel (a second channel of a one-channel net
+        // has no weights and stays 0)
+        if constexpr (C::REC) rec_store2<C>(trace_t, ok ? (unsigned)pix * 4u : 0x20000000u, hs[0], hs[1], ss[0], ss[1]);
       }
     } else {
       // ================= output layer (VALU), weights broadcast from LDS
@@ -1408,16 +1546,17 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
 #pragma unroll
         for (int co = 0; co < 2; ++co) {
-          if (C::FULL && ok && co < cout && trace_t) {
+          if (C::FULL && !C::REC && ok && co < cout && trace_t.p) {
             const int gy = tl.ty0 + q / C::TW, gx = tl.tx0 + q % C::TW;
-            if (tb.has(gy, gx)) trace_t[(size_t)(choffo + co) * tb.plane() + tb.idx(gy, gx)] = u[k][co];
+            if (tb.has(gy, gx)) trace_t.put(trace_t.template idx<C::RELAX>(2, choffo, co, tb.idx(gy, gx), tb.plane()), u[k][co]);
           }
           float v = u[k][co];
           const float s = bilif(v, theta, alpha, C::RELAX ? relaxed : 0);
+          if constexpr (C::REC) rec_store1<C>(trace_t, ok ? (unsigned)pix * 4u + co : 0x20000000u, u[k][co], s);
           so[k][co] = v;
           if (ok && co < cout && ca.s_out) {
             const size_t o = (((size_t)tl.n * T + t) * cout + co) * HW + pix;
-            if (C::FULL && ca.s_fp32) reinterpret_cast<float*>(ca.s_out)[o] = s;
+            if (C::CKS && ca.s_fp32) reinterpret_cast<float*>(ca.s_out)[o] = s;
             else reinterpret_cast<int8_t*>(ca.s_out)[o] = (int8_t)s;
           }
         }
@@ -1515,6 +1654,8 @@ struct Variant {
   const char* name;
   void (*single_fast)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*single_full)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
+  // the backward's segment recompute (pixel-major trace only)
+  void (*single_rec)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*single_relaxed)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*batched)(const FwdNetArgs&, const BatchTable&, int32_t*, int ncu, hipStream_t, hipError_t*);
   // RGB-input kernels of one-channel nets: inference, training/debug, relaxed
@@ -1550,9 +1691,11 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
 
 #define EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, MODE) Cfg<NL, CIN, CH, (bool)BF, TH, TW, NW, MODE>
 #define EVS_FAST_FULL(NL, CIN, CH, BF, TH, TW, NW)                                                   \
-  &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 0)>, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 1)>
-// a tile variant: inference kernel + training/debug kernel; _R adds the
-// relaxed-spike kernel (one tile per FP32 shape), _B the batched one
+  &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 0)>, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 1)>, \
+      &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 3)>
+// a tile variant: inference kernel + training/debug kernel + the backward's
+// recompute kernel; _R adds the relaxed-spike kernel (one tile per FP32
+// shape), _B the batched one
 #define EVS_VARIANT(NL, CIN, CH, BF, TH, TW, NW, NAME) \
   Variant{NL, CIN, CH, BF, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, BF, TH, TW, NW), nullptr, nullptr}
 #define EVS_VARIANT_R(NL, CIN, CH, TH, TW, NW, NAME)                                 \
@@ -1715,6 +1858,11 @@ int launch_forward(const evs_net& net, const FwdNetArgs& na, const FwdClipArgs& 
     for (int t = 0; t < n && !v->single_relaxed; ++t) v = find_variant(net, t);
     if (!v->single_relaxed) return fail(EVS_EUNSUPPORTED, "no relaxed-spike kernel compiled for this network shape");
     v->single_relaxed(na, ca, stream, &e);
+  } else if (ca.trace_pm) {
+    // the backward's segment recompute: the pixel-major trace, nothing else
+    if (ca.ckpt || ca.s_out || ca.v_out || (ca.trace_f16 != 0) != (net.precision == EVS_BF16))
+      return fail(EVS_EINVAL, "recompute launch: trace only, fp16 exactly for BF16 nets");
+    v->single_rec(na, ca, stream, &e);
   } else {
     (full ? v->single_full : v->single_fast)(na, ca, stream, &e);
   }

@@ -67,6 +67,15 @@ struct FwdClipArgs {
   int64_t x_nstride, vin_nstride, trace_nstride;
   // image window recorded in h_trace (the whole frame by default)
   int32_t tb_y0, tb_x0, tb_h, tb_w;
+  // h_trace holds fp16 values (the backward's segment potentials of BF16
+  // nets, rounded so that each stored value gives the forward's spike), else
+  // float
+  int32_t trace_f16;
+  // h_trace is pixel-major (the backward's segment potentials): per frame,
+  // layer after layer, each layer [H][W][CP] with CP its width rounded up to
+  // a multiple of 4 (the output layer: 4), so that a lane's four channels of
+  // a pixel are one store and one load; else [sumC][h][w] over the window
+  int32_t trace_pm;
 };
 
 struct FwdNetArgs {

@@ -2,7 +2,8 @@
 
 * Hard spikes: weight/input/initial-state gradients against the FP64 oracle
   BPTT on trajectories whose spikes match the oracle's exactly (the test
-  checks that first), rel. error <= 1e-4.
+  checks that first), rel. error <= 1e-4 (FP32 nets) or the BF16 gradient
+  gate of tests/_helpers.py (BF16 nets: bf16 adjoints between kernels).
 * Relaxed spikes (smooth, FP32): against the oracle's relaxed BPTT and
   against central finite differences of the GPU's own relaxed forward on an
   8x8x4 crop, rel. error <= 1e-2.
@@ -17,7 +18,7 @@ import torch
 pytestmark = pytest.mark.gpu
 
 from oracle import evsnet, emd  # noqa: E402
-from tests._helpers import f32, make_inputs, split_layers  # noqa: E402
+from tests._helpers import f32, grad_tol, make_inputs, split_layers  # noqa: E402
 
 THETA, LEAK = f32(0.5), f32(0.9)
 
@@ -86,14 +87,17 @@ def test_backward_matches_oracle(evs, channels, prec, detach, surr, k):
         g = evsnet.backward(xo[n], ows, THETA, LEAK, G[n], detach_reset=detach, alpha=SURR_ALPHA[surr], surr=surr)
         for l in range(len(ws)):
             dW_ref[l] += g["dW"][l]
-        assert _rel(dx[n].cpu().numpy(), g["dx"]) < 1e-4
+        tol = grad_tol(prec)
+        rx = _rel(dx[n].cpu().numpy(), g["dx"])
+        print(f"  clip {n} dx rel err {rx:.2e}", flush=True)
+        assert rx < tol
         dvl = split_layers(dv[n].cpu().numpy()[None], channels)
         for a, b in zip(dvl, g["dv_init"]):
-            assert _rel(a[0], b) < 1e-4
+            assert _rel(a[0], b) < tol
     for l in range(len(ws)):
         r = _rel(gws[l].cpu().numpy(), dW_ref[l])
         print(f"  layer {l + 1} dW rel err {r:.2e}", flush=True)
-        assert r < 1e-4
+        assert r < grad_tol(prec)
 
 
 def test_checkpoint_interval_and_determinism(evs):

@@ -9,12 +9,16 @@ host time per precision) and to properties that hold at any size:
 * they do not depend on the checkpoint interval (every 16 vs every 64
   frames: rel. 1e-5);
 * for hard spikes the backward is linear in the incoming gradient:
-  dW(G1 + 2 G2) = dW(G1) + 2 dW(G2) to rel. 1e-5;
+  dW(G1 + 2 G2) = dW(G1) + 2 dW(G2) to rel. 1e-5 (FP32; BF16 nets round
+  their adjoints to bf16 between kernels, which holds linearity to the BF16
+  gradient gate);
 * they are finite, and the input-layer gradient is not zero.
 """
 
 import pytest
 import torch
+
+from tests._helpers import grad_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -81,7 +85,7 @@ def test_train_size_backward_properties(evs, batch, prec):
     for l in range(len(a_w)):
         r = _rel(e_w[l], a_w[l] + 2 * d_w[l])
         print(f"  layer {l + 1} dW linearity in grad_s: rel {r:.2e}", flush=True)
-        assert r < 1e-5
+        assert r < (1e-5 if prec == "fp32" else grad_tol(prec))
 
 
 @pytest.mark.slow
@@ -98,7 +102,8 @@ def test_train_size_backward_matches_oracle(evs, batch, prec):
     FP32 sum lands on the other side of a threshold than FP64 would then does
     not make the two gradients incomparable.  BF16 nets are held to the
     oracle with BF16-rounded x and W (the operands the forward multiplied).
-    Gate: dW, dx and the initial-state gradient within 1e-4 relative."""
+    Gate: dW, dx and the initial-state gradient within 1e-4 relative (FP32)
+    or the BF16 gradient gate (bf16 adjoints between kernels)."""
     import numpy as np
     from oracle import evsnet
     from tests._helpers import split_layers
@@ -135,11 +140,11 @@ def test_train_size_backward_matches_oracle(evs, batch, prec):
         dvl = split_layers(dvh[n][None], wl.channels)
         rv = max(_np_rel(a[0], b) for a, b in zip(dvl, ref["dv_init"]))
         print(f"  crop {n}: dx rel {rx:.2e}, dv_init rel {rv:.2e}", flush=True)
-        assert rx < 1e-4 and rv < 1e-4
+        assert rx < grad_tol(prec) and rv < grad_tol(prec)
     for l in range(len(ws)):
         r = _np_rel(gw[l].cpu().numpy(), dW_ref[l])
         print(f"  layer {l + 1} dW rel {r:.2e}", flush=True)
-        assert r < 1e-4
+        assert r < grad_tol(prec)
 
 
 def _np_rel(a, b):
