@@ -57,18 +57,23 @@ constexpr int align16(int b) { return (b + 15) & ~15; }
 // MODE_: 0 = inference; 1 = training/debug features (h traces, membrane
 // checkpoints, FP32 spike output); 2 = relaxed (smooth) spikes with the
 // features of mode 1; 3 = the backward's segment recompute (the charged
-// potentials of every layer into its pixel-major trace, nothing else).
-// Only mode 0 leaves the feature code out of the loop.
+// potentials of every layer into its pixel-major trace, nothing else);
+// 8 = the forward of a training step (checkpoints and FP32 spike output,
+// no trace).  Only mode 0 leaves the feature code out of the loop.
 // MODE_ + 4 (one-channel FP32 nets): x holds RGB frames and the input of
 // Eq. (1) is formed while staging.
 template <int NL_, int CIN_, int CH_, bool BF16_, int TH_, int TW_, int NW_, int MODE_>
 struct Cfg {
   static constexpr int NL = NL_, CIN = CIN_, CH = CH_, TH = TH_, TW = TW_, NW = NW_, MODE = MODE_;
-  static constexpr int BMODE = MODE_ & 3;
-  static constexpr bool LOGX = MODE_ >= 4;
-  static constexpr bool BF16 = BF16_, FULL = BMODE != 0, RELAX = BMODE == 2, REC = BMODE == 3;
-  // checkpoints and FP32 spike output (training / debug builds)
-  static constexpr bool CKS = FULL && !REC;
+  static constexpr int BMODE = MODE_ == 8 ? 8 : (MODE_ & 3);
+  static constexpr bool LOGX = MODE_ >= 4 && MODE_ < 8;
+  static constexpr bool BF16 = BF16_, RELAX = BMODE == 2, REC = BMODE == 3;
+  // the public trace (planar; relaxed builds also the backward's)
+  static constexpr bool TRC = BMODE == 1 || BMODE == 2;
+  // checkpoints and FP32 spike output
+  static constexpr bool CKS = BMODE == 1 || BMODE == 2 || BMODE == 8;
+  // any of the training / debug features (register budget)
+  static constexpr bool FULL = BMODE != 0;
   static_assert(!(REC && MODE_ >= 4), "recompute builds take direct input");
   static_assert(!LOGX || (CIN_ == 1 && !BF16_), "RGB input: one-channel FP32 nets");
   static_assert(!(BF16_ && MODE_ == 2), "relaxed spikes are FP32 only");
@@ -661,7 +666,7 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
 #pragma unroll
     for (int m = 0; m < C::MB; ++m) hsave[m] = st[m] * tscale;
   }
-  if (C::FULL && !C::REC && tr.p && valid) {
+  if (C::TRC && tr.p && valid) {
     const int row = (p - C::PADF) / C::CWT, col = (p - C::PADF) % C::CWT;
     const int gy = gy0 + row, gx = gx0 + col;
     if (row >= C::NL && row < C::NL + C::TH && col >= C::NL && col < C::NL + C::TW && tb.has(gy, gx)) {
@@ -1122,12 +1127,15 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     if constexpr (C::REC) {
       // the frame's three layer blocks of the pixel-major trace
       constexpr unsigned es = C::BF16 ? 2 : 4;
+      // (no trace: empty resources, every store dropped)
       char* const fb = reinterpret_cast<char*>(ca.h_trace) + ((size_t)tl.n * ca.trace_nstride + (size_t)t * tpsum * HW) * es;
+      const unsigned on = ca.h_trace ? 1u : 0u;
 #pragma unroll
       for (int li = 0; li < 3; ++li)
         trace_t.rs[li] = __builtin_amdgcn_make_buffer_rsrc(fb + (size_t)trace_t.off[li] * HW * es, (short)0,
-                                                           (int)((unsigned)trace_t.cw[li] * (unsigned)HW * es), 0x00020000);
-    } else if constexpr (C::FULL) {
+                                                           (int)(on * (unsigned)trace_t.cw[li] * (unsigned)HW * es),
+                                                           0x00020000);
+    } else if constexpr (C::TRC) {
       if (ca.h_trace)
         trace_t.p = reinterpret_cast<char*>(ca.h_trace) +
                     ((size_t)tl.n * ca.trace_nstride + (size_t)t * ((C::RELAX && ca.trace_pm) ? tpsum : sumc) * tb.plane()) * 4;
@@ -1393,7 +1401,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       auto out_epilogue = [&](int i, const f4& acc) __attribute__((always_inline)) {
         if (g < 2) {
           const float h = C::NSP == 2 ? acc[0] + acc[1] : acc[0];
-          if (C::FULL && !C::REC && oo[i] >= 0 && trace_t.p) {
+          if (C::TRC && oo[i] >= 0 && trace_t.p) {
             const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
             const int gy = gy0 + row, gx = gx0 + col;
             if (tb.has(gy, gx)) trace_t.put(trace_t.template idx<C::RELAX>(2, choffo, g, tb.idx(gy, gx), tb.plane()), h * isc3);
@@ -1487,7 +1495,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
         for (int co = 0; co < 2; ++co) {
           const float h = leak * so[k][co] + (co == 0 ? u0 : u1);
-          if (C::FULL && !C::REC && ok && co < cout && trace_t.p && tb.has(gy, gx))
+          if (C::TRC && ok && co < cout && trace_t.p && tb.has(gy, gx))
             trace_t.put(trace_t.template idx<C::RELAX>(2, choffo, co, tb.idx(gy, gx), tb.plane()), h * isc3);
           float v = h;
           const float sp = bilif(v, theta3, alpha, false);
@@ -1546,7 +1554,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         const size_t pix = (size_t)(tl.ty0 + q / C::TW) * W + (tl.tx0 + q % C::TW);
 #pragma unroll
         for (int co = 0; co < 2; ++co) {
-          if (C::FULL && !C::REC && ok && co < cout && trace_t.p) {
+          if (C::TRC && ok && co < cout && trace_t.p) {
             const int gy = tl.ty0 + q / C::TW, gx = tl.tx0 + q % C::TW;
             if (tb.has(gy, gx)) trace_t.put(trace_t.template idx<C::RELAX>(2, choffo, co, tb.idx(gy, gx), tb.plane()), u[k][co]);
           }
@@ -1656,6 +1664,8 @@ struct Variant {
   void (*single_full)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   // the backward's segment recompute (pixel-major trace only)
   void (*single_rec)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
+  // the forward of a training step (checkpoints, FP32 spikes, no trace)
+  void (*single_train)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*single_relaxed)(const FwdNetArgs&, const FwdClipArgs&, hipStream_t, hipError_t*);
   void (*batched)(const FwdNetArgs&, const BatchTable&, int32_t*, int ncu, hipStream_t, hipError_t*);
   // RGB-input kernels of one-channel nets: inference, training/debug, relaxed
@@ -1692,9 +1702,9 @@ void launch_batched(const FwdNetArgs& na, const BatchTable& bt, int32_t* counter
 #define EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, MODE) Cfg<NL, CIN, CH, (bool)BF, TH, TW, NW, MODE>
 #define EVS_FAST_FULL(NL, CIN, CH, BF, TH, TW, NW)                                                   \
   &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 0)>, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 1)>, \
-      &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 3)>
+      &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 3)>, &launch_single<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 8)>
 // a tile variant: inference kernel + training/debug kernel + the backward's
-// recompute kernel; _R adds the relaxed-spike kernel (one tile per FP32
+// recompute kernel + the training-step forward kernel; _R adds the relaxed-spike kernel (one tile per FP32
 // shape), _B the batched one
 #define EVS_VARIANT(NL, CIN, CH, BF, TH, TW, NW, NAME) \
   Variant{NL, CIN, CH, BF, TH, TW, NAME, EVS_FAST_FULL(NL, CIN, CH, BF, TH, TW, NW), nullptr, nullptr}
@@ -1859,10 +1869,14 @@ int launch_forward(const evs_net& net, const FwdNetArgs& na, const FwdClipArgs& 
     if (!v->single_relaxed) return fail(EVS_EUNSUPPORTED, "no relaxed-spike kernel compiled for this network shape");
     v->single_relaxed(na, ca, stream, &e);
   } else if (ca.trace_pm) {
-    // the backward's segment recompute: the pixel-major trace, nothing else
+    // the backward's segment recompute: its pixel-major trace (fp16 exactly
+    // for BF16 nets), nothing else
     if (ca.ckpt || ca.s_out || ca.v_out || (ca.trace_f16 != 0) != (net.precision == EVS_BF16))
       return fail(EVS_EINVAL, "recompute launch: trace only, fp16 exactly for BF16 nets");
     v->single_rec(na, ca, stream, &e);
+  } else if (full && !ca.h_trace) {
+    // checkpoints / FP32 spikes without a trace: the forward of a training step
+    v->single_train(na, ca, stream, &e);
   } else {
     (full ? v->single_full : v->single_fast)(na, ca, stream, &e);
   }
