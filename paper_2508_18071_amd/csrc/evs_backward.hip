@@ -276,6 +276,11 @@ __global__ __launch_bounds__(NTH) void k_convT(const GS* __restrict__ gh, int Co
 //     of [pixel][8 channels] bf16 whose stride is a multiple of 256 bytes
 //     (the two channel halves of a tap then fill disjoint banks); 5 MFMAs
 //     per row instead of 36.
+//   BF16 nets, output layer above (2 channels): the same bf16 product with
+//     K = 18 (tap, co) pairs in one k-step: lane group g holds taps 4g ..
+//     4g + 3 of both channels (tap 8 in group 2, zero weights past it), read
+//     from a table of [pixel][2 channels] bf16 pairs; 1 MFMA per row
+//     instead of 9.  (The fused weight gradient stays on the FP32 pipe.)
 template <int COUTP, bool B16>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3)))
 void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int Cin, int len, int H,
@@ -289,6 +294,7 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   using GS = typename Store<B16>::G;
   constexpr unsigned ESH = sizeof(HS), ESG = sizeof(GS);
   constexpr bool kBF = B16 && COUTP == 16;             // the bf16 product
+  constexpr bool kBF2 = B16 && COUTP == 2;             // its two-channel form
   constexpr int E = TT + 2;                            // haloed tile edge
   constexpr int PS = (E * E + 47) / 64 * 64 + 16;      // plane stride (floats), 16 mod 64
   constexpr int PSB = (E * E * 16 + 255) / 256 * 256;  // bf16 plane stride (bytes), multiple of 256
@@ -298,6 +304,7 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   static_assert(COG % 4 == 0, "co slots come in lane groups of 4");
   static_assert(E * E > NTH && E * E <= 2 * NTH, "a tile plane is staged in two passes");
   __shared__ __attribute__((aligned(16))) float ghs[kBF ? 2 * PSB / 4 : COUTP * PS];
+  __shared__ unsigned gp2[kBF2 ? E * E : 1];           // [pixel] (co 0, co 1) bf16 pairs
   const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
   const int HW = H * W;
@@ -310,6 +317,22 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   constexpr int KS4 = (KS + 3) / 4;
   __shared__ f4 wl[kBF ? 1 : KS4 * 64];
   u4 wb[kBF ? KSB : 1];
+  u4 wb2 = u4{0u, 0u, 0u, 0u};
+  if constexpr (kBF2) {
+    // row ci = j; K slot 8g + e: tap 4g + e / 2, channel e % 2
+    unsigned wd[4];
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+      const int tap = 4 * g + e2;
+      float ww[2];
+#pragma unroll
+      for (int co = 0; co < 2; ++co) ww[co] = tap < 9 ? wT[(tap * COUTP + co) * 16 + j] : 0.f;
+      typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+      const bf2 pr = {(__bf16)ww[0], (__bf16)ww[1]};
+      wd[e2] = __builtin_bit_cast(unsigned, pr);
+    }
+    wb2 = u4{wd[0], wd[1], wd[2], wd[3]};
+  }
   if constexpr (kBF) {
     // bf16 A operand in registers: row ci = j, K slot 8g + e of k-step s
 #pragma unroll
@@ -446,6 +469,11 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
     } else {
 #pragma unroll
       for (int co = 0; co < COUTP; ++co) ghs[co * PS + q] = v[co];
+      if constexpr (kBF2) {
+        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+        const bf2 pr = {(__bf16)v[0], (__bf16)v[1]};     // exact: bf16 values
+        gp2[q] = __builtin_bit_cast(unsigned, pr);
+      }
     }
   };
   if constexpr (kAhead) {
@@ -485,6 +513,20 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
           acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, wb[s]), __builtin_bit_cast(bf8, b),
                                                            acc[r], 0, 0, 0);
         }
+      }
+    } else if constexpr (kBF2) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        unsigned bw[4];
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) {
+          const int tap = 4 * g + e2 > 8 ? 8 : 4 * g + e2;  // taps past 8: zero weights
+          const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+          bw[e2] = gp2[(4 * wave + r + 1 - dy) * E + j + 1 - dx];
+        }
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, wb2),
+                                                         __builtin_bit_cast(bf8, u4{bw[0], bw[1], bw[2], bw[3]}), acc[r],
+                                                         0, 0, 0);
       }
     } else {
 #pragma unroll
@@ -873,6 +915,129 @@ __global__ __launch_bounds__(NTH) void k_dw_mfma(const typename Store<B16>::G* _
   }
 }
 
+// Weight gradient of the input layer of a BF16 net (x of at most 4
+// channels, 16 output channels) on the bf16 matrix pipe:
+// dW[co][ci][tap] = sum_p g_h[co][p] x[ci][p + tap] is a 16 (co) x 27
+// ((ci, tap), two 16-column tiles) product over pixels, g_h (bf16, as
+// stored) the A operand and the bf16-rounded x (the operand the forward
+// multiplied) the B operand, so every product is exact and the sums
+// accumulate in FP32.  Per frame the tile's g_h and its haloed x, in three
+// copies shifted by the tap column (16-byte operand reads), are staged in
+// LDS from registers loaded during the previous frame's products; wave w
+// takes pixel rows 4w .. 4w+3 and the four waves' partials are added in
+// wave order at the end.
+constexpr int kXsbBytes = 3 * 4 * (TT + 2) * TT * 2;     // x [dx][ci][row][col]
+constexpr int kXPerThread = (4 * (TT + 2) * (TT + 2) + NTH - 1) / NTH;
+__global__ __launch_bounds__(NTH) void k_dw1_mfma(const __bf16* __restrict__ gh, int Cout, int Cin, int len, int H,
+                                                  int W, int tiles_x, const float* __restrict__ x,
+                                                  long long x_nstride, float* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) char lds[16 * TT * TT * 2 + kXsbBytes];
+  uint16_t* const gsp = reinterpret_cast<uint16_t*>(lds);
+  uint16_t* const xsb = reinterpret_cast<uint16_t*>(lds + 16 * TT * TT * 2);
+  const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
+  const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
+  const int HW = H * W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int gy = ty0 + threadIdx.x / TT, gx = tx0 + threadIdx.x % TT;
+  const unsigned goff = el_off<__bf16>(gy < H && gx < W, (unsigned)(gy * W + gx));
+  unsigned xoff[kXPerThread];
+#pragma unroll
+  for (int k = 0; k < kXPerThread; ++k) {
+    const int e = threadIdx.x + NTH * k;
+    const int ci = e / ((TT + 2) * (TT + 2)), rr = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+    const int y = ty0 - 1 + rr, xx = tx0 - 1 + cc;
+    xoff[k] = el_off<float>(e < 4 * (TT + 2) * (TT + 2) && ci < Cin && y >= 0 && y < H && xx >= 0 && xx < W,
+                            (unsigned)ci * (unsigned)HW + (unsigned)(y * W + xx));
+  }
+  float gr[16], xr[kXPerThread];
+  auto fetch = [&](int t) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<__bf16*>(gh + ((size_t)n * len + t) * Cout * HW), (short)0, (int)(2u * Cout * HW), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(x + (size_t)n * x_nstride + (size_t)t * Cin * HW), (short)0, (int)(4u * Cin * HW),
+        0x00020000);
+#pragma unroll
+    for (int co = 0; co < 16; ++co) gr[co] = ld_el<__bf16>(rg, goff + 2u * co * HW, 0);
+#pragma unroll
+    for (int k = 0; k < kXPerThread; ++k) xr[k] = ld_el<float>(rx, xoff[k], 0);
+  };
+  // B column j of tile nt: (ci, tap) = ((16 nt + j) / 9, (16 nt + j) % 9);
+  // columns 27..31 multiply zeros
+  int boff[2];
+  bool bcol[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const int idx = 16 * nt + j, ci = idx / 9, tap = idx % 9;
+    bcol[nt] = idx < 27;
+    const int dy = tap / 3, dx = tap % 3;
+    boff[nt] = bcol[nt] ? ((dx * 4 + ci) * (TT + 2) + dy) * TT : 0;
+  }
+  f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+  fetch(0);
+  for (int t = 0; t < len; ++t) {
+    __syncthreads();                                   // the previous frame's operands are consumed
+#pragma unroll
+    for (int co = 0; co < 16; ++co) gsp[co * TT * TT + threadIdx.x] = bf16_bits(gr[co]);   // exact: bf16 values
+#pragma unroll
+    for (int k = 0; k < kXPerThread; ++k) {
+      const int e = threadIdx.x + NTH * k;
+      if (e < 4 * (TT + 2) * (TT + 2)) {
+        const int ci = e / ((TT + 2) * (TT + 2)), rr = (e / (TT + 2)) % (TT + 2), cc = e % (TT + 2);
+        const uint16_t b = bf16_bits(xr[k]);           // round to nearest: the forward's operand
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const int c2 = cc - dx;
+          if (c2 >= 0 && c2 < TT) xsb[((dx * 4 + ci) * (TT + 2) + rr) * TT + c2] = b;
+        }
+      }
+    }
+    if (t + 1 < len) fetch(t + 1);                     // in flight while this frame multiplies
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      // k-step: pixel rows 4 wave + 2q, +1; lane group g takes 8 pixels of
+      // row 4 wave + 2q + g/2 starting at column 8 (g & 1)
+      const int row = 4 * wave + 2 * q + (g >> 1), c0 = 8 * (g & 1);
+      const u4 a = *reinterpret_cast<const u4*>(gsp + j * TT * TT + row * TT + c0);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        u4 b = u4{0u, 0u, 0u, 0u};
+        if (bcol[nt]) b = *reinterpret_cast<const u4*>(xsb + boff[nt] + row * TT + c0);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b),
+                                                          acc[nt], 0, 0, 0);
+      }
+    }
+  }
+  // lane (column j, group g) holds dW[co = 4g + r][(ci, tap) = 16 nt + j]
+  __syncthreads();
+  float* rb = reinterpret_cast<float*>(lds);             // waves 1..3: [wave - 1][lane][8]
+  if (wave > 0) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rb[((wave - 1) * 64 + lane) * 8 + nt * 4 + r] = acc[nt][r];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    float* out = partial + ((size_t)blockIdx.y * gridDim.x + tile) * (4 * 16 * 9);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int idx = 16 * nt + j;
+      if (idx < 27) {
+        const int ci = idx / 9, tap = idx % 9;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = acc[nt][r];
+#pragma unroll
+          for (int w2 = 0; w2 < 3; ++w2) v += rb[(w2 * 64 + lane) * 8 + nt * 4 + r];
+          out[((4 * g + r) * 4 + ci) * 9 + tap] += v;     // [co][ci][tap] with 4 ci slots, as the VALU kernel
+        }
+      }
+    }
+  }
+}
+
 // acc[e] += sum_b partial[b][e] (e over padded pairs x 9).  A workgroup
 // takes 32 consecutive e; each of its 8 b-lanes sums the partials b = lane,
 // lane + 8, ... in order, then the 8 lane sums are added in lane order: a
@@ -952,6 +1117,12 @@ void launch_dw(dim3 g, hipStream_t st, const void* ghv, int Cout, int Cin, int l
     hipLaunchKernelGGL(k_dw_mfma<B16>, g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, hseg, ht, sumc, choff_in,
                        theta, partial);
     return;
+  }
+  if constexpr (B16 && CINP == 4 && COUTP == 16) {
+    if (!hseg) {                                         // input layer of a BF16 net: bf16 matrix pipe
+      hipLaunchKernelGGL(k_dw1_mfma, g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, x, xns, partial);
+      return;
+    }
   }
   if (hseg) {
     hipLaunchKernelGGL((k_dw<CINP, COUTP, HS, GS>), g, dim3(NTH), 0, st, gh, Cout, Cin, len, H, W, tx, x, xns, bfx,
