@@ -196,7 +196,16 @@ size_t evs_workspace_bytes(const evs_net* net, const evs_clip* clips, int32_t n_
 /* Size in bytes of the packed weight buffer for `net`.                   */
 size_t evs_packed_weights_bytes(const evs_net* net);
 
-/* Pack the per-layer weights into one device buffer read by the kernels.
+/* Pack the per-layer weights into one device buffer read by the kernels
+ * (the weights of the 3x3 convolutions of Sec. 3.3).  The buffer holds the
+ * FP32 weights layer after layer and, 256-byte aligned after them, the
+ * forward kernels' matrix-core operand fragments (BF16-rounded weights, or
+ * the two-part splits of FP32 nets with their power-of-two scales) built
+ * once here, which every forward workgroup copies instead of building; a
+ * kernel whose layout the block was not built for builds its own.  The
+ * buffer is tied to the channel counts and precision of `net`.  Enqueued
+ * on `stream` (a copy and one kernel); the sources must stay valid until it
+ * has run.
  *   w       host array of L device pointers; w[l] is float32
  *           [C_{l+1}][C_l][3][3] (torch Conv2d layout)
  *   packed  device buffer of evs_packed_weights_bytes(net) bytes        */

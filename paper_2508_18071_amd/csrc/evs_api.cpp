@@ -110,9 +110,18 @@ void set_tuned(const std::tuple<int, int, int, int, int, int, int, int>& k, int 
   g_tuned[k] = tile;
 }
 
-FwdNetArgs make_net_args(const evs_net& net, const void* packed) {
+size_t packed_floats(const evs_net& net);
+
+// Byte offset of the prepacked fragment block in a packed weight buffer:
+// after the FP32 weights, 256-byte aligned.
+size_t frag_offset(const evs_net& net) { return align256(packed_floats(net) * sizeof(float)); }
+
+FwdNetArgs make_net_args(const evs_net& net, const void* packed, bool with_frag) {
   FwdNetArgs na{};
   na.w = reinterpret_cast<const float*>(packed);
+  na.frag = with_frag && forward_frag_bytes(net) > 0
+                ? reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(packed) + frag_offset(net))
+                : nullptr;
   na.n_layers = net.n_layers;
   int ofs = 0;
   for (int l = 0; l < 4; ++l) na.ch[l] = l <= net.n_layers ? net.ch[l] : 0;
@@ -162,19 +171,27 @@ const char* evs_version(void) { return "evs-mi355x 0.1 (gfx950)"; }
 
 size_t evs_packed_weights_bytes(const evs_net* net) {
   if (validate_net(net) != EVS_OK) return (size_t)-1;
-  return packed_floats(*net) * sizeof(float);
+  const size_t fb = forward_frag_bytes(*net);
+  return fb ? frag_offset(*net) + fb : packed_floats(*net) * sizeof(float);
 }
 
 int evs_pack_weights(const evs_net* net, const float* const* w, void* packed, void* stream) {
   int st = validate_net(net);
   if (st) return st;
   if (!w || !packed) return fail(EVS_EINVAL, "weights or packed buffer is NULL");
+  for (int l = 0; l < net->n_layers; ++l)
+    if (!w[l]) return fail(EVS_EINVAL, "a layer weight pointer is NULL");
   char* dst = reinterpret_cast<char*>(packed);
   for (int l = 0; l < net->n_layers; ++l) {
-    if (!w[l]) return fail(EVS_EINVAL, "a layer weight pointer is NULL");
     const size_t b = (size_t)net->ch[l + 1] * net->ch[l] * 9 * sizeof(float);
     EVS_HIP(hipMemcpyAsync(dst, w[l], b, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     dst += b;
+  }
+  // the MFMA fragments of the forward kernels, built once from the copy
+  if (forward_frag_bytes(*net) > 0) {
+    const FwdNetArgs na = make_net_args(*net, packed, false);
+    uint32_t* fb = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(packed) + frag_offset(*net));
+    if ((st = forward_prepack(*net, na, fb, (hipStream_t)stream))) return st;
   }
   return EVS_OK;
 }

@@ -112,7 +112,7 @@ int evs_autotune(const evs_net* net, int32_t H, int32_t W, int32_t T, int32_t* c
   if ((st = fill_uniform(x, xfl, 1u, 0.f, 2.f, s)) ||
       (st = fill_uniform(w, wfl, 2u, -0.5f, 0.5f, s))) goto done;
   {
-    const FwdNetArgs na = make_net_args(*net, w);
+    const FwdNetArgs na = make_net_args(*net, w, false);   // plain weights: no prepacked block
     FwdClipArgs ca{};
     ca.x = x;
     ca.s_out = out;

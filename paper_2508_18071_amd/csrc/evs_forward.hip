@@ -1584,12 +1584,82 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   if (ca.v_out) write_state(ca.v_out + (size_t)tl.n * sumc * HW);
 }
 
+// Signature of the weight area's layout (offsets relative to its start, the
+// shape parameters that decide its contents): kernels of one network shape
+// that share it can take the same prepacked image whatever their tile.
+template <class C>
+constexpr uint32_t frag_sig() {
+  using Lo = Layout<C>;
+  uint32_t h = 2166136261u;
+  const uint32_t v[] = {(uint32_t)(Lo::YS - Lo::WL), (uint32_t)(Lo::FR1 - Lo::WL), (uint32_t)(Lo::FR2 - Lo::WL),
+                        (uint32_t)(Lo::FR3 - Lo::WL), (uint32_t)(Lo::FRY - Lo::WL), (uint32_t)C::BF16,
+                        (uint32_t)C::CH, (uint32_t)C::NL, (uint32_t)C::CIN, (uint32_t)C::XSPLIT, (uint32_t)C::OTAP,
+                        (uint32_t)C::OMF, (uint32_t)C::SF16};
+  for (uint32_t x : v) h = (h ^ x) * 16777619u;
+  return h;
+}
+template <class C>
+constexpr bool takes_frag() { return !C::RELAX && !C::LOGX; }
+
 template <class C>
 __device__ __forceinline__ void init_lds(const FwdNetArgs& na, char* lds) {
+  using Lo = Layout<C>;
   // zero canvas and pads once: pads are read only by junk (masked) pixels
   unsigned* z = reinterpret_cast<unsigned*>(lds);
   for (int e = threadIdx.x; e < (C::XS_BYTES + C::SP_BYTES) / 4; e += C::NT) z[e] = 0u;
+  // the prepacked weight area when it was built for this layout and these
+  // channel counts (uniform branch), else built here from the weights
+  bool pre = false;
+  if constexpr (takes_frag<C>()) {
+    if (na.frag) {
+      const uint32_t* hd = na.frag;
+      const uint32_t chw = (uint32_t)na.ch[0] | ((uint32_t)na.ch[1] << 8) | ((uint32_t)na.ch[2] << 16) |
+                           ((uint32_t)na.ch[3] << 24);
+      pre = hd[0] == kFragMagic && hd[1] == frag_sig<C>() && hd[2] == chw && hd[3] == (uint32_t)na.n_layers &&
+            hd[6] == (uint32_t)(Lo::YS - Lo::WL);
+    }
+  }
+  if (pre) {
+    const u4* src = reinterpret_cast<const u4*>(na.frag + kFragHeaderWords);
+    u4* dst = reinterpret_cast<u4*>(lds + Lo::WL);
+    for (int e = threadIdx.x; e < (Lo::YS - Lo::WL) / 16; e += C::NT) dst[e] = src[e];
+    if (threadIdx.x < 2) reinterpret_cast<unsigned*>(lds + Lo::SCL)[threadIdx.x] = na.frag[4 + threadIdx.x];
+  } else {
+    load_weights<C>(na, lds);
+  }
+}
+
+// Prepack: build the weight area once (one workgroup) and store it with its
+// header for the kernels to copy.
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_prepack(FwdNetArgs na, uint32_t* dst) {
+  using Lo = Layout<C>;
+  __shared__ __attribute__((aligned(16))) char lds[Lo::TOTAL];
+  na.frag = nullptr;
   load_weights<C>(na, lds);
+  __syncthreads();
+  const u4* src = reinterpret_cast<const u4*>(lds + Lo::WL);
+  u4* out = reinterpret_cast<u4*>(dst + kFragHeaderWords);
+  for (int e = threadIdx.x; e < (Lo::YS - Lo::WL) / 16; e += C::NT) out[e] = src[e];
+  if (threadIdx.x == 0) {
+    dst[0] = kFragMagic;
+    dst[1] = frag_sig<C>();
+    dst[2] = (uint32_t)na.ch[0] | ((uint32_t)na.ch[1] << 8) | ((uint32_t)na.ch[2] << 16) | ((uint32_t)na.ch[3] << 24);
+    dst[3] = (uint32_t)na.n_layers;
+    dst[4] = reinterpret_cast<const unsigned*>(lds + Lo::SCL)[0];
+    dst[5] = reinterpret_cast<const unsigned*>(lds + Lo::SCL)[1];
+    dst[6] = (uint32_t)(Lo::YS - Lo::WL);
+    dst[7] = 0u;
+  }
+}
+template <class C>
+void launch_prepack(const FwdNetArgs& na, uint32_t* dst, hipStream_t st, hipError_t* err) {
+  hipLaunchKernelGGL(k_prepack<C>, dim3(1), dim3(C::NT), 0, st, na, dst);
+  *err = hipGetLastError();
+}
+template <class C>
+constexpr size_t frag_block_bytes() {
+  return (size_t)kFragHeaderWords * 4 + (size_t)(Layout<C>::YS - Layout<C>::WL);
 }
 
 template <class C>
@@ -1673,6 +1743,11 @@ struct Variant {
   // 1: one of the shape's default candidates, which differ only in how
   // their tile count fills the CUs (see forward_default_tile)
   int dflt;
+};
+// The prepack of a shape (its first variant's inference configuration).
+struct Prepack {
+  void (*launch)(const FwdNetArgs&, uint32_t*, hipStream_t, hipError_t*);
+  size_t bytes;
 };
 
 template <class C>
@@ -1768,6 +1843,24 @@ const Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
+// Prepack per network shape, built with the shape's first tile (the weight
+// area does not depend on the tile; a kernel whose layout signature differs
+// builds its own).
+struct ShapePrepack {
+  int nl, cin, ch, bf16;
+  Prepack pp;
+};
+#define EVS_PREPACK(NL, CIN, CH, BF, TH, TW, NW)                                       \
+  ShapePrepack{NL, CIN, CH, BF, Prepack{&launch_prepack<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 0)>, \
+                                        frag_block_bytes<EVS_CFG(NL, CIN, CH, BF, TH, TW, NW, 0)>()}}
+const ShapePrepack kPrepacks[] = {
+    EVS_PREPACK(1, 1, 16, 0, 32, 32, 8), EVS_PREPACK(1, 3, 16, 0, 32, 32, 8),
+    EVS_PREPACK(2, 3, 16, 0, 16, 32, 8), EVS_PREPACK(2, 1, 16, 0, 30, 40, 8),
+    EVS_PREPACK(2, 3, 16, 1, 30, 40, 8), EVS_PREPACK(2, 3, 32, 0, 24, 32, 8),
+    EVS_PREPACK(2, 3, 32, 1, 12, 32, 8), EVS_PREPACK(3, 3, 16, 0, 24, 32, 8),
+    EVS_PREPACK(3, 3, 16, 1, 24, 32, 8), EVS_PREPACK(3, 3, 32, 1, 24, 32, 8),
+};
+
 int padded_hidden(const evs_net& net) {
   int mx = 0;
   for (int l = 1; l < net.n_layers; ++l) mx = net.ch[l] > mx ? net.ch[l] : mx;
@@ -1777,6 +1870,14 @@ int padded_hidden(const evs_net& net) {
 bool matches(const Variant& v, const evs_net& net) {
   return v.nl == net.n_layers && v.cin == net.ch[0] && v.bf16 == (net.precision == EVS_BF16) &&
          (net.n_layers == 1 || v.ch == padded_hidden(net));
+}
+
+const ShapePrepack* find_prepack(const evs_net& net) {
+  for (const ShapePrepack& p : kPrepacks)
+    if (p.nl == net.n_layers && p.cin == net.ch[0] && p.bf16 == (net.precision == EVS_BF16) &&
+        (net.n_layers == 1 || p.ch == padded_hidden(net)))
+      return &p;
+  return nullptr;
 }
 
 const Variant* find_variant(const evs_net& net, int tile_id) {
@@ -1790,6 +1891,20 @@ const Variant* find_variant(const evs_net& net, int tile_id) {
 }
 
 }  // namespace
+
+size_t forward_frag_bytes(const evs_net& net) {
+  const ShapePrepack* p = find_prepack(net);
+  return p ? (p->pp.bytes + 255) / 256 * 256 : 0;
+}
+
+int forward_prepack(const evs_net& net, const FwdNetArgs& na, uint32_t* dst, hipStream_t stream) {
+  const ShapePrepack* p = find_prepack(net);
+  if (!p) return EVS_OK;
+  hipError_t e = hipSuccess;
+  p->pp.launch(na, dst, stream, &e);
+  if (e != hipSuccess) return hip_check(e, "weight prepack launch");
+  return EVS_OK;
+}
 
 int forward_tile_count(const evs_net& net) {
   int k = 0;

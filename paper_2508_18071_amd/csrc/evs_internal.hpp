@@ -90,7 +90,16 @@ struct FwdNetArgs {
   // difference (Eq. 1): scale, knee and toe slope ln(knee) / knee
   int32_t x_rgb;
   float lum_scale, knee, toe;
+  // the prepacked MFMA fragments of the packed weight buffer (a header of
+  // kFragHeaderWords words, then the LDS image of the weight area), or null
+  const uint32_t* frag;
 };
+
+// Header of the prepacked fragments: magic, layout signature of the kernel
+// configuration they were built for, the real channel counts (8 bits each),
+// the layer count, the two weight-scale words of FP32 nets, image bytes.
+constexpr int kFragHeaderWords = 8;
+constexpr uint32_t kFragMagic = 0x45565346u;
 
 // Batched (persistent) launch: a clip table passed by value.
 constexpr int kMaxBatchClips = 24;
@@ -111,5 +120,9 @@ const char* forward_tile_name(const evs_net& net, int tile_id);
 void forward_tile_dims(const evs_net& net, int tile_id, int* th, int* tw);
 int forward_default_tile(const evs_net& net, int H, int W, int N);
 int forward_batched_tile(const evs_net& net, int preferred);   // -1: none compiled
+// Prepacked fragments: bytes of the block (header + image) for `net`, 0
+// when no kernel of the net takes them; forward_prepack writes the block.
+size_t forward_frag_bytes(const evs_net& net);
+int forward_prepack(const evs_net& net, const FwdNetArgs& na, uint32_t* dst, hipStream_t stream);
 
 }  // namespace evs

@@ -44,6 +44,8 @@ int backward(const evs_net& net, const void* packed, const evs_clip& clip, const
 void load_tile_cache_once();
 int choose_tile(const evs_net& net, int H, int W, int N = 1);
 void remember_tile(const evs_net& net, int H, int W, int tile);
-FwdNetArgs make_net_args(const evs_net& net, const void* packed);
+// with_frag: the packed buffer carries the prepacked fragments
+// (evs_pack_weights wrote it)
+FwdNetArgs make_net_args(const evs_net& net, const void* packed, bool with_frag = true);
 
 }  // namespace evs

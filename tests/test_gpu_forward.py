@@ -263,3 +263,35 @@ def test_every_tile_inference_kernel_equals_traced_kernel(evs, channels, prec, T
         evs.set_tile(net, -1)
     print(f"  {channels} {prec} T={T}: {n} tiles, differing: {bad}", flush=True)
     assert not bad
+
+
+@pytest.mark.parametrize("channels,prec", [((3, 16, 16, 2), "fp32"), ((3, 16, 16, 2), "bf16"),
+                                           ((3, 32, 2), "fp32"), ((3, 32, 2), "bf16"), ((3, 8, 2), "fp32"),
+                                           ((3, 10, 10, 2), "fp32"), ((3, 32, 32, 2), "bf16")])
+def test_prepacked_fragments_equal_built_ones(evs, channels, prec):
+    """evs_pack_weights stores the MFMA fragments of the forward kernels
+    (built once); a kernel whose packed block is not valid builds its own
+    from the FP32 weights.  Both give the same spikes, potentials and
+    checkpoints bit for bit (inference, traced and training-step builds)."""
+    import ctypes
+    from paper_2508_18071_amd import _lib
+    print(f"case prepack {channels} {prec}", flush=True)
+    T, H, W = 7, 45, 70
+    x, ws = make_inputs(channels, T, H, W, seed=5)
+    net = evs.Net(channels, theta=THETA, leak=LEAK, precision=prec)
+    packed = evs.pack_weights(net, [torch.from_numpy(w).cuda() for w in ws])
+    nfl = sum(ci * co * 9 for ci, co in zip(channels[:-1], channels[1:]))
+    off = (nfl * 4 + 255) // 256 * 256
+    assert packed.numel() > off, "the packed buffer carries a fragment block"
+    plain = packed.clone()
+    plain[off:] = 0                                    # no valid header: kernels build their own
+    xg = x.cuda()
+    outs = []
+    for p in (packed, plain):
+        a = evs.forward(net, p, xg)
+        b = evs.forward(net, p, xg, trace=True)
+        c = evs.forward(net, p, xg, s_fp32=True, ckpt_every=3)
+        torch.cuda.synchronize()
+        outs.append((a["s"], b["s"], b["h"], c["s"], c["ckpt"]))
+    for u, v in zip(*outs):
+        assert torch.equal(u, v)
