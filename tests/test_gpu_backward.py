@@ -100,6 +100,42 @@ def test_backward_matches_oracle(evs, channels, prec, detach, surr, k):
         assert r < grad_tol(prec)
 
 
+@pytest.mark.parametrize("channels,prec", [((3, 16, 16, 2), "fp32"), ((3, 32, 2), "bf16")])
+@pytest.mark.parametrize("N,T,H,W,k", [(1, 1, 1, 1, 1), (2, 3, 2, 37, 2), (1, 5, 19, 1, 5)])
+def test_backward_degenerate_shapes(evs, channels, prec, N, T, H, W, k):
+    """One pixel and one frame, two rows across several gradient tiles, one
+    column: gradients along the device's trajectory against the oracle."""
+    print(f"case backward {channels} {prec} N={N} T={T} H={H} W={W} k={k}", flush=True)
+    x, ws, net, packed = _setup(evs, channels, prec, T, H, W, N=N, seed=9)
+    xg = x.cuda()
+    out = evs.forward(net, packed, xg, trace=True, ckpt_every=k)
+    G = np.random.default_rng(2).normal(size=(N, T, channels[-1], H, W)).astype(np.float32)
+    gws, dx, dv = evs.backward(net, packed, xg, out["ckpt"], k, torch.from_numpy(G).cuda(), want_dx=True,
+                               want_dv=True)
+    torch.cuda.synchronize()
+    if prec == "bf16":
+        ows = [evsnet.bf16_round(w) for w in ws]
+        xo = evsnet.bf16_round(x.numpy())
+    else:
+        ows = [w.astype(np.float64) for w in ws]
+        xo = x.numpy().astype(np.float64)
+    h = out["h"].cpu().numpy()
+    dW_ref = [np.zeros_like(w) for w in ows]
+    tol = grad_tol(prec)
+    for n in range(N):
+        g = evsnet.backward_along(xo[n], ows, THETA, LEAK, G[n], split_layers(h[n], channels))
+        for l in range(len(ws)):
+            dW_ref[l] += g["dW"][l]
+        assert _rel(dx[n].cpu().numpy(), g["dx"]) < tol
+        dvl = split_layers(dv[n].cpu().numpy()[None], channels)
+        for a, b in zip(dvl, g["dv_init"]):
+            assert _rel(a[0], b) < tol
+    for l in range(len(ws)):
+        r = _rel(gws[l].cpu().numpy(), dW_ref[l])
+        print(f"  layer {l + 1} dW rel err {r:.2e}", flush=True)
+        assert r < tol
+
+
 def test_checkpoint_interval_and_determinism(evs):
     channels = (3, 16, 16, 2)
     T, H, W = 12, 19, 23
