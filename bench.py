@@ -40,8 +40,8 @@ def mfma_peak(channels, prec):
     BF16 nets run every conv on the bf16 pipe.  FP32 nets run every conv
     that reads spikes on the fp16 pipe (same rate as bf16) with each weight
     split into two fp16 parts (half the rate); their first conv runs on the
-    bf16 pipe with x and W both split into three parts, six part products
-    kept (a sixth of the rate) when x has three channels and a hidden layer
+    fp16 pipe with x and W both split into two parts, all four part products
+    kept (a quarter of the rate) when x has three channels and a hidden layer
     follows, and on the f32 pipe otherwise.  Harmonic mean over the layers'
     flops."""
     layers = list(zip(channels[:-1], channels[1:]))
@@ -52,7 +52,7 @@ def mfma_peak(channels, prec):
             peak = BF16_MFMA_PEAK
         elif l == 0:
             split_l1 = ci == 3 and len(layers) >= 2
-            peak = BF16_MFMA_PEAK / 6 if split_l1 else FP32_MFMA_PEAK
+            peak = BF16_MFMA_PEAK / 4 if split_l1 else FP32_MFMA_PEAK
         else:
             peak = BF16_MFMA_PEAK / 2
         t += f / peak
@@ -629,8 +629,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_MFMA_PEAK,
                      "unit": "TFLOP/s", "frac": round(achieved / BF16_MFMA_PEAK, 4),
                      "peak_note": "published dense bf16/fp16 matrix-core peak: every conv of this FP32 net runs "
-                                  "on the 16-bit pipes (FP32 accuracy from operand splits: conv 1 x and W in 3 "
-                                  "bf16 parts, 6 part products; the spike convs 2 fp16 weight parts)",
+                                  "on the 16-bit pipes (FP32 accuracy from operand splits: conv 1 x and W in 2 "
+                                  "fp16 parts, 4 part products; the spike convs 2 fp16 weight parts)",
                      "hbm_achieved_GBps": round(alg_bytes / (fwd_avg / 1e3) / 1e9, 1),
                      "hbm_frac": round(alg_bytes / (fwd_avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                      "fp32_peak_ratio": round(achieved / FP32_MFMA_PEAK, 3),

@@ -73,8 +73,14 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
  *              used by evs_backward and by relaxed forwards (Eq. 4)
  *   precision  EVS_FP32: FP32 convolutions: sums accumulate in FP32 and
  *              every product is carried to within 2^-22 of its value
- *              (operands split into bf16 or fp16 parts on the matrix cores,
- *              or f32 MFMA), i.e. below the rounding of the FP32 sum;
+ *              (operands split into fp16 parts on the matrix cores, or f32
+ *              MFMA), except in the input layer of nets with three input
+ *              channels and hidden layers (hard spikes), where x and W are
+ *              split into two fp16 parts each: there every product is within
+ *              2^-21 |w x| (plus absolute terms below 2^-35 |w|max at the
+ *              fp16 subnormal spacing), and x must satisfy
+ *              |x| < 65520 (larger or infinite values give NaN potentials;
+ *              the status word flags them, EVS_FLAG_X_RANGE);
  *              EVS_BF16: x and W rounded to bfloat16 (round-to-nearest-even)
  *              and multiplied on BF16 MFMA with FP32 accumulation.
  *              Membrane state, threshold compare and reset are FP32 in both.
@@ -172,12 +178,17 @@ typedef struct evs_clip {
  *   [EVS_STATUS_FLAGS]    EVS_FLAG_EVENT_OVERFLOW: evs_compact_events found
  *                         more events than `capacity` (the list was cut; the
  *                         dense spikes and `count` stay exact).
+ *                         EVS_FLAG_X_RANGE: evs_forward of an FP32 net whose
+ *                         input layer splits x into fp16 parts (see
+ *                         `precision`) read a value with |x| >= 65520 or an
+ *                         infinity (same pass as the NaN count).
  *   [3]                   reserved (left unchanged).                       */
 #define EVS_STATUS_WORDS 4
 #define EVS_STATUS_NAN_X 0
 #define EVS_STATUS_NAN_GRAD 1
 #define EVS_STATUS_FLAGS 2
 #define EVS_FLAG_EVENT_OVERFLOW 1
+#define EVS_FLAG_X_RANGE 2
 
 /* Operation selector for evs_workspace_bytes. */
 typedef enum {
@@ -221,7 +232,8 @@ int evs_pack_weights(const evs_net* net, const float* const* w, void* packed, vo
  *           (k = ckpt_every), as needed by evs_backward.
  *   tile    tiles are chosen by the autotuner cache (evs_autotune) or a
  *           built-in default; results do not depend on the tile choice.
- *   dev_status  NULL or the device status word (counts NaN inputs).     */
+ *   dev_status  NULL or the device status word (counts NaN inputs, flags
+ *               inputs outside the fp16 range where `precision` says so). */
 int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, int32_t n_clips,
                 float* ckpt, int32_t ckpt_every, void* ws, size_t ws_bytes, int32_t* dev_status,
                 void* stream);

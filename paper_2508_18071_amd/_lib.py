@@ -22,6 +22,7 @@ EVS_OP_FORWARD, EVS_OP_BACKWARD, EVS_OP_EMD, EVS_OP_COMPACT = range(4)
 # device status word: EVS_STATUS_WORDS int32 values
 EVS_STATUS_WORDS, EVS_STATUS_NAN_X, EVS_STATUS_NAN_GRAD, EVS_STATUS_FLAGS = 4, 0, 1, 2
 EVS_FLAG_EVENT_OVERFLOW = 1
+EVS_FLAG_X_RANGE = 2
 
 
 class EvsNet(ctypes.Structure):

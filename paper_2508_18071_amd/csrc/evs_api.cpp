@@ -238,13 +238,18 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
   const size_t need = evs_workspace_bytes(net, clips, n_clips, ckpt_every, EVS_OP_FORWARD);
   if (need > 0 && (!ws || ws_bytes < need)) return fail(EVS_EWORKSPACE, "forward workspace too small");
   hipStream_t s = (hipStream_t)stream;
-  // NaN inputs: one streaming pass over each clip's x, only when asked for
+  // NaN inputs: one streaming pass over each clip's x, only when asked for;
+  // for nets whose input layer splits x into fp16 parts (FP32, three input
+  // channels, hidden layers, hard spikes) the same pass flags |x| >= 65520
   if (dev_status) {
+    const bool fp16_split = net->precision == EVS_FP32 && net->input == EVS_INPUT_DIRECT && net->ch[0] == 3 &&
+                            net->n_layers >= 2 && !net->relaxed;
     for (int i = 0; i < n_clips; ++i) {
       const evs_clip& c = clips[i];
       const size_t frames = net->input == EVS_INPUT_RGB_LOGDIFF ? (size_t)c.T + 1 : (size_t)c.T;
       const size_t chans = net->input == EVS_INPUT_RGB_LOGDIFF ? 3 : (size_t)net->ch[0];
-      if ((st = count_nan(c.x, (size_t)c.N * frames * chans * c.H * c.W, dev_status + EVS_STATUS_NAN_X, s)))
+      if ((st = count_nan(c.x, (size_t)c.N * frames * chans * c.H * c.W, dev_status + EVS_STATUS_NAN_X, s,
+                          fp16_split ? 65520.f : 0.f, dev_status + EVS_STATUS_FLAGS, EVS_FLAG_X_RANGE)))
         return st;
     }
   }

@@ -24,10 +24,12 @@
 //     product within 2^-22, sums in FP32; the state behind the conv is kept
 //     in the scaled units, which is exact).  The spike fragment of a k-step
 //     is loaded once and multiplied by the parts.
-//   * The first layer of FP32 3 -> 16 nets splits both x and W into three
-//     bf16 parts (exact) and keeps six of the nine part products (the
-//     dropped ones are below 2^-23 |w x|); other FP32 nets use the f32 MFMA
-//     for it, BF16 nets the bf16 one with bf16-rounded input.
+//   * The first layer of FP32 nets with three input channels splits x and
+//     the (power-of-two scaled) W into two fp16 parts each and keeps all
+//     four part products (each product within 2^-21 |w x| up to absolute
+//     terms at the fp16 subnormal spacing, sums in FP32);
+//     other FP32 nets use the f32 MFMA for it, BF16 nets the bf16 one with
+//     bf16-rounded input.
 //   * The output layer (1-2 channels) puts its (channel, part) pairs on the
 //     MFMA rows: row 4c + p holds part p of channel c, and the potentials
 //     are the sums of the part rows.
@@ -136,16 +138,16 @@ struct Cfg {
   // FP32 nets with hidden layers fill them by direct global -> LDS loads of
   // 64-pixel chunks into two buffers (frame t+1 lands while t is read)
   // FP32 nets with three input channels (16 or 32 hidden channels) run layer 1
-  // on the bf16 pipe as well: each staged x value is split into three bf16
-  // parts (x = xh + xm + xl exactly) stored as per-pixel records of the three
-  // channels, one record plane per part (register staging, no raw x in LDS)
+  // on the fp16 pipe as well: each staged x value is split into two fp16
+  // parts, stored as 24 bytes per canvas pixel that hold the parts of the
+  // pixel and its right neighbour (register staging, no raw x in LDS)
   static constexpr bool XSPLIT = !BF16 && CIN == 3 && NH >= 1 && !RELAX && !LOGX;
   static constexpr bool XDMA = !BF16 && NH >= 1 && !RELAX && !LOGX && !XSPLIT;
   static constexpr int XPP = cdiv(NPIX, NT);         // canvas pixels staged per thread (XSPLIT)
   // 16-channel spike convs run block by block with all weight fragments in
   // registers, so that block i-1's epilogue overlaps block i's MFMAs
   static constexpr bool BO = CH == 16 && S16;
-  static constexpr int NFR1 = 9;                     // XSPLIT A fragments: part h 4 k-steps, m 3, l 2
+  static constexpr int NFR1 = 4;                     // XSPLIT A fragments: weight parts h, l x 2 k-steps
   static constexpr int XCK = CIN * CHT;              // x chunks: one canvas row of one plane
   static constexpr int XPW = cdiv(XCK, NW);          // chunk loads per wave and frame
   // x buffer: front pad, CIN planes and the zero plane back to back (plane
@@ -228,24 +230,26 @@ __device__ inline unsigned pack_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(unsigned, p);
 }
 
-// Split three FP32 values into bf16 parts x = h + m + l (round to nearest:
-// h = bf16(x), m = bf16(x - h), l = x - h - m, each exact) and pack them as
-// the records [x0 x1 x2 0] of parts h, m and l.
-__device__ inline void split3_records(float x0, float x1, float x2, uint2 (&rec)[3]) {
-  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-  float r0 = x0, r1 = x1, r2 = x2;
+// Split three FP32 values into two fp16 parts each, round to nearest:
+// h = fp16(x), and l = fp16(2^11 (x - h)) (x - h is exact), the low part
+// carried at 2^11 times its value so that it stays in the fp16 normal range
+// for |x| >= 2^-14 (the weights it meets are scaled by 2^-11, exactly).  The
+// fp16 matrix cores of gfx950 keep subnormal operands, so below that the
+// parts stay accurate to the subnormal spacing: |x - h - 2^-11 l| <=
+// 2^-22 |x| + 2^-36.  |x| must stay below 65520 (h overflows there).
+// Packed as V = [h0 h1 | h2 l0 | l1 l2].
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ inline void split2_parts(float x0, float x1, float x2, unsigned (&v)[3]) {
+  const float x[3] = {x0, x1, x2};
+  _Float16 hp[3], lp[3];
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const bf2 p01 = {(__bf16)r0, (__bf16)r1};
-    const bf2 p2z = {(__bf16)r2, (__bf16)0.f};
-    const unsigned u01 = __builtin_bit_cast(unsigned, p01), u2 = __builtin_bit_cast(unsigned, p2z);
-    rec[b] = uint2{u01, u2};
-    if (b < 2) {
-      r0 -= __builtin_bit_cast(float, u01 << 16);
-      r1 -= __builtin_bit_cast(float, u01 & 0xffff0000u);
-      r2 -= __builtin_bit_cast(float, u2 << 16);
-    }
+  for (int c = 0; c < 3; ++c) {
+    hp[c] = (_Float16)x[c];
+    lp[c] = (_Float16)((x[c] - (float)hp[c]) * 2048.f);
   }
+  v[0] = __builtin_bit_cast(unsigned, f16x2{hp[0], hp[1]});
+  v[1] = __builtin_bit_cast(unsigned, f16x2{hp[2], lp[0]});
+  v[2] = __builtin_bit_cast(unsigned, f16x2{lp[1], lp[2]});
 }
 
 // ------------------------------------------------------------------ weights
@@ -265,26 +269,33 @@ __device__ inline float wpart(float w, int p) {
   return p == 0 ? hi : (p == 1 ? mid : r1 - mid);
 }
 
-// Part p of the round-to-nearest split w = hi + mid + lo into bf16 values
-// (hi = bf16(w), mid = bf16(w - hi), lo = w - hi - mid, all exact): the split
-// of the layer-1 weights, whose x operand is split the same way.
-__device__ inline float wpart_rn(float w, int p) {
-  const float hi = round_bf16(w);
-  const float r1 = w - hi;
-  const float mid = round_bf16(r1);
-  return p == 0 ? hi : (p == 1 ? mid : r1 - mid);
+// Layer-1 operand order of the split FP32 nets.  The six parts V(P) of
+// canvas pixel P are stored twice, at bytes 24P - 12 and 24P of the x area,
+// so the five 8-byte records at 24P + {-24, -16, -8, 8, 16} hold
+//   V(P-1)[0..3] | V(P-1)[4..5] V(P)[0..1] | V(P)[2..5] | V(P)[4..5] V(P+1)[0..1] | V(P+1)[2..5]
+// : the 18 parts of one kernel row (taps dx = -1, 0, +1), the repeated
+// V(P)[4..5] aside.  A k-step gives lane group g records 2g and 2g + 1 of
+// its eight; record R = 8q + 2g + r of k-step q is record R % 5 of kernel
+// row R / 5, R = 15 is padding (read at P, zero weights).  Slot v of record
+// R holds (tap, channel c, part lo) when xslot returns true.
+__device__ __forceinline__ bool xslot(int R, int v, int& tap, int& c, int& lo) {
+  if (R >= 15) return false;
+  const int r = R % 5;
+  int dx, i;
+  if (r == 0) { dx = -1; i = v; }
+  else if (r == 1) { dx = v < 2 ? -1 : 0; i = v < 2 ? 4 + v : v - 2; }
+  else if (r == 2) { dx = 0; i = 2 + v; }
+  else if (r == 3) { if (v < 2) return false; dx = 1; i = v - 2; }
+  else { dx = 1; i = 2 + v; }
+  tap = 3 * (R / 5) + dx + 1;
+  c = i % 3;
+  lo = i / 3;
+  return true;
 }
-
-// Layer-1 operand order of the split FP32 nets.  A k-step gives each lane
-// group two 4-entry x records; record R = 8q + 2g + r of k-step q is part
-// b = R / 9 (h, m, l) of the three channels at tap R % 9 (entry 3 is empty;
-// R >= 27 is padding).  Fragment f multiplies weight part p over k-step q:
-// f = 0..3 part h, q = 0..3; f = 4..6 part m, q = 0..2; f = 7..8 part l,
-// q = 0..1.  Part pairs (weight, x) kept: (h, any), (m, h), (m, m), (l, h);
-// the dropped (m, l), (l, m), (l, l) are below 2^-23 |w x| together.
-__device__ __forceinline__ void split_frag(int f, int& p, int& q) {
-  p = f < 4 ? 0 : (f < 7 ? 1 : 2);
-  q = f < 4 ? f : (f < 7 ? f - 4 : f - 7);
+// Byte offset of record R from the 24P of its block pixel (row stride cwt).
+__device__ __forceinline__ int xrec_off(int R, int cwt) {
+  constexpr int kOff[5] = {-24, -16, -8, 8, 16};
+  return R >= 15 ? 0 : 24 * cwt * (R / 5 - 1) + kOff[R % 5];
 }
 
 // Power-of-two exponent s that brings the largest weight magnitude of a
@@ -339,15 +350,16 @@ struct Layout {
   static constexpr int FRY_BYTES = C::OTAP ? 2 * C::KY * 64 * 16 : 0;
   static constexpr int YS = FRY + FRY_BYTES;                    // Y planes [9][NYPL][2] f32
   static constexpr int XDUMMY = YS + C::YS_BYTES;               // target of the padding x loads
-  static constexpr int SCL = XDUMMY + (C::XDMA ? 256 : 0);      // |w|max bits of the spike convs (u32 x 2)
+  static constexpr int SCL = XDUMMY + (C::XDMA ? 256 : 0);      // |w|max bits of the fp16 convs (u32 x 3)
   static constexpr int TOTAL = SCL + 16;
   static_assert(TOTAL <= 160 * 1024, "tile does not fit in LDS");
 };
 
 // Fill the weight areas of LDS with the MFMA A-operand fragments in the
 // per-lane order the k-step loops read them (and the VALU output weights).
-// Scale 2^s of the spike-conv weights of FP32 nets: slot 0 the hidden ->
-// hidden conv, slot 1 the output conv (1 for other nets).
+// Scale 2^s of the fp16 weights of FP32 nets: slot 0 the hidden -> hidden
+// conv, slot 1 the output conv, slot 2 layer 1 of split nets (1 for other
+// nets).
 template <class C>
 __device__ __forceinline__ float spike_scale(const char* lds, int slot) {
   if constexpr (C::SF16) return __builtin_ldexpf(1.f, scale_exp(reinterpret_cast<const unsigned*>(lds + Layout<C>::SCL)[slot]));
@@ -363,15 +375,16 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
     unsigned* scl = reinterpret_cast<unsigned*>(lds + Lo::SCL);
     if (threadIdx.x < 4) scl[threadIdx.x] = 0u;
     __syncthreads();
-    for (int l = 1; l <= L; ++l) {
-      if (l < L && C::NH < 2) continue;
+    // (and of layer 1 of split nets, slot 2)
+    for (int l = C::XSPLIT ? 0 : 1; l <= L; ++l) {
+      if (l >= 1 && l < L && C::NH < 2) continue;
       const int n = na.ch[l + 1] * na.ch[l] * 9;
       unsigned m = 0u;
       for (int e = threadIdx.x; e < n; e += C::NT) {
         const unsigned b = __builtin_bit_cast(unsigned, na.w[na.wofs[l] + e]) & 0x7fffffffu;
         m = b > m ? b : m;
       }
-      atomicMax(scl + (l == L ? 1 : 0), m);
+      atomicMax(scl + (l == 0 ? 2 : (l == L ? 1 : 0)), m);
     }
     __syncthreads();
   }
@@ -386,23 +399,26 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
   }
   if constexpr (C::XSPLIT) {
     const int c1 = na.ch[1];
-    // entry (m, f, lane): row co = 16m + lane%16, lane group g = lane/16
+    const float sc = spike_scale<C>(lds, 2);
+    // entry (m, f, lane): weight part p = f / 2 over k-step q = f % 2, row
+    // co = 16m + lane%16, lane group g = lane/16; the slots of low x parts
+    // take the weight part times 2^-11 (rounded to nearest where that leaves
+    // the fp16 normal range)
     for (int e = threadIdx.x; e < C::MB * C::NFR1 * 64; e += C::NT) {
       const int lane = e % 64, f = (e / 64) % C::NFR1, m = e / (64 * C::NFR1);
       const int co = 16 * m + (lane & 15), g = lane >> 4;
-      int p, q;
-      split_frag(f, p, q);
+      const int p = f >> 1, q = f & 1;
       unsigned wd[4];
       for (int e2 = 0; e2 < 4; ++e2) {
         float ww[2];
         for (int h = 0; h < 2; ++h) {
           const int slot = 2 * e2 + h;
-          const int R = 8 * q + 2 * g + (slot >> 2), c = slot & 3;
-          const int b = R / 9, tap = R % 9;
-          const bool keep = R < 27 && c < 3 && co < c1 && (b == 0 || (b == 1 && p <= 1) || (b == 2 && p == 0));
-          ww[h] = keep ? wpart_rn(wget(na, 0, co, c, tap), p) : 0.f;
+          int tap = 0, c = 0, lo = 0;
+          const bool real = xslot(8 * q + 2 * g + (slot >> 2), slot & 3, tap, c, lo) && co < c1;
+          const float wp = real ? wpart16(wget(na, 0, co, c, tap), sc, p) : 0.f;
+          ww[h] = lo ? (float)(_Float16)(wp * 0x1p-11f) : wp;
         }
-        wd[e2] = pack_bf16x2(ww[0], ww[1]);
+        wd[e2] = pack_f16x2(ww[0], ww[1]);
       }
       reinterpret_cast<u4*>(lds + Lo::FR1)[e] = u4{wd[0], wd[1], wd[2], wd[3]};
     }
@@ -826,12 +842,14 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   const size_t HW = (size_t)H * W;
   const int sumc = na.sum_c;
   const float theta = na.theta, leak = na.leak, alpha = na.alpha;
-  // FP32 nets keep the state of the layers behind a spike conv in units of
-  // that conv's weight scale 2^s (exact): their threshold is theta 2^s, and
-  // traces, checkpoints and the final state are written unscaled
+  // FP32 nets keep the state of the layers behind an fp16 conv (those that
+  // read spikes, and layer 1 of split nets) in units of that conv's weight
+  // scale 2^s (exact): their threshold is theta 2^s, and traces, checkpoints
+  // and the final state are written unscaled
+  const float sc1 = C::XSPLIT ? spike_scale<C>(lds, 2) : 1.f;
   const float sc2 = spike_scale<C>(lds, 0), sc3 = spike_scale<C>(lds, 1);
-  const float isc2 = 1.f / sc2, isc3 = 1.f / sc3;
-  const float theta2 = theta * sc2, theta3 = theta * sc3;
+  const float isc1 = 1.f / sc1, isc2 = 1.f / sc2, isc3 = 1.f / sc3;
+  const float theta1 = theta * sc1, theta2 = theta * sc2, theta3 = theta * sc3;
   const int relaxed = na.relaxed;                   // 0 hard, 1 sigmoid, 2 arctangent step
   const int c1 = na.ch[1], c2 = na.ch[2];
   const int cout = na.ch[na.n_layers];
@@ -897,7 +915,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   float vo[C::NBO];         // output potential (MFMA form)
   const float* vin = ca.v_in ? ca.v_in + (size_t)tl.n * ca.vin_nstride : nullptr;
   const float fill = C::RELAX ? 0.f : __builtin_nanf("");
-  if constexpr (C::NH >= 1) read_hidden_state<C, C::NB1>(st1, vm1, a1, g, vin, c1, 0, gy0, gx0, W, HW, fill, 1.f);
+  if constexpr (C::NH >= 1) read_hidden_state<C, C::NB1>(st1, vm1, a1, g, vin, c1, 0, gy0, gx0, W, HW, fill, sc1);
   if constexpr (C::NH >= 2)
     read_hidden_state<C, C::NB2>(st2, vm2, a2, g, vin, c2, choff2, gy0, gx0, W, HW, fill, sc2);
 #pragma unroll
@@ -953,8 +971,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   // pixels (xl_prev), so input frame tt is X = L_log[tt + 1] - L_log[tt];
   // pixels outside the image load zeros and give X = 0 (the zero padding).
   // Split FP32 nets (XSPLIT) prefetch the three channels of canvas pixels
-  // tid + NT k and store them as records [ch0 ch1 ch2 0] of bf16 parts, one
-  // 8-byte record per pixel in each of the part planes h, m, l.
+  // tid + NT k and store their six fp16 parts V twice (see xslot).
   int xo[C::XSPLIT ? C::XPP : 1];
   if constexpr (C::XSPLIT) {
 #pragma unroll
@@ -1001,11 +1018,13 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     if constexpr (C::XSPLIT) {
       const int q = tid + C::NT * k;
       if (q < C::NPIX) {
-        uint2 rec[3];
-        split3_records(xpf[3 * k], xpf[3 * k + 1], xpf[3 * k + 2], rec);
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-          *reinterpret_cast<uint2*>(lds + Lo::XS + (b * C::NPIXL + C::PADF + q) * 8) = rec[b];
+        unsigned v[3];
+        split2_parts(xpf[3 * k], xpf[3 * k + 1], xpf[3 * k + 2], v);
+        char* const px = lds + Lo::XS + (C::PADF + q) * 24;
+        *reinterpret_cast<unsigned*>(px - 12) = v[0];
+        *reinterpret_cast<uint2*>(px - 8) = uint2{v[1], v[2]};
+        *reinterpret_cast<uint2*>(px) = uint2{v[0], v[1]};
+        *reinterpret_cast<unsigned*>(px + 8) = v[2];
       }
     }
   };
@@ -1036,16 +1055,12 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     }
   };
 
-  // split nets: byte offset (from a block pixel's record) of record r of
-  // k-step q for this lane's group; padding records re-read the centre tap
-  // (their weights are zero)
-  int ro[C::XSPLIT ? 8 : 1];
+  // split nets: byte offset (from 24 P of a block pixel P) of record r of
+  // k-step q for this lane's group, k = 2q + r
+  int ro[C::XSPLIT ? 4 : 1];
   if constexpr (C::XSPLIT) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int R = 8 * (k >> 1) + 2 * g + (k & 1);
-      ro[k] = R < 27 ? ((R / 9) * C::NPIXL + tap_off(R % 9, C::CWT)) * 8 : 0;
-    }
+    for (int k = 0; k < 4; ++k) ro[k] = xrec_off(8 * (k >> 1) + 2 * g + (k & 1), C::CWT);
   }
   // per-lane x-plane offsets of the layer-1 k-steps (FP32: K = 4q + g)
   int o1[C::BF16 || C::XSPLIT ? 1 : C::KS1];
@@ -1070,7 +1085,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   const int nseg = ca.ckpt_every > 0 ? cdiv(T, ca.ckpt_every) : 0;
   const TraceBox tb{ca.tb_y0, ca.tb_x0, ca.tb_h, ca.tb_w};
   auto write_state = [&](float* dst) __attribute__((always_inline)) {
-    if constexpr (C::NH >= 1) write_hidden_state<C, C::NB1>(st1, vm1, a1, g, dst, c1, 0, gy0, gx0, W, HW, 1.f);
+    if constexpr (C::NH >= 1) write_hidden_state<C, C::NB1>(st1, vm1, a1, g, dst, c1, 0, gy0, gx0, W, HW, isc1);
     if constexpr (C::NH >= 2) write_hidden_state<C, C::NB2>(st2, vm2, a2, g, dst, c2, choff2, gy0, gx0, W, HW, isc2);
 #pragma unroll
     for (int k = 0; k < C::NOUT; ++k) {
@@ -1150,11 +1165,11 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       u4 ay[2][C::KY];
       if constexpr (Y1) load_yfrag<C>(lds, lane, ay);
       if constexpr (C::XSPLIT) {
-        // bf16 MFMA over the split records: per block, the 9 fragment
-        // products (parts h, m, l interleaved per k-step) accumulate onto
-        // leak * v in one chain (dependent MFMAs issue back to back); the
-        // records of block i+1 load and the epilogue of block i-1 runs
-        // while block i multiplies
+        // fp16 MFMA over the split records: per block, the 4 fragment
+        // products (weight parts h, l per k-step) accumulate onto leak * v
+        // in one chain (dependent MFMAs issue back to back); the records of
+        // block i+1 load and the epilogue of block i-1 runs while block i
+        // multiplies
         const char* const xr = lds + Lo::XS;
         const u4* const fr = reinterpret_cast<const u4*>(lds + Lo::FR1) + lane;
         u4 af[C::MB][C::NFR1];
@@ -1162,12 +1177,12 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         for (int m = 0; m < C::MB; ++m)
 #pragma unroll
           for (int f = 0; f < C::NFR1; ++f) af[m][f] = fr[(m * C::NFR1 + f) * 64];
-        u4 bq[2][4];
+        u4 bq[2][2];
         auto ldb = [&](int i, int sl) __attribute__((always_inline)) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const uint2 lo = *reinterpret_cast<const uint2*>(xr + e1[i] * 8 + ro[2 * q]);
-            const uint2 hi = *reinterpret_cast<const uint2*>(xr + e1[i] * 8 + ro[2 * q + 1]);
+          for (int q = 0; q < 2; ++q) {
+            const uint2 lo = *reinterpret_cast<const uint2*>(xr + e1[i] * 24 + ro[2 * q]);
+            const uint2 hi = *reinterpret_cast<const uint2*>(xr + e1[i] * 24 + ro[2 * q + 1]);
             bq[sl][q] = u4{lo.x, lo.y, hi.x, hi.y};
           }
         };
@@ -1176,24 +1191,19 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         for (int i = 0; i <= C::NB1; ++i) {
           if (i < C::NB1) {
             if (i + 1 < C::NB1) ldb(i + 1, (i + 1) & 1);
-            const u4 (&b)[4] = bq[i & 1];
+            const u4 (&b)[2] = bq[i & 1];
 #pragma unroll
             for (int m = 0; m < C::MB; ++m) {
               f4& h = st1[i][m];
-              h = mfma_bf16(af[m][0], b[0], h);
-              h = mfma_bf16(af[m][4], b[0], h);
-              h = mfma_bf16(af[m][7], b[0], h);
-              h = mfma_bf16(af[m][1], b[1], h);
-              h = mfma_bf16(af[m][5], b[1], h);
-              h = mfma_bf16(af[m][8], b[1], h);
-              h = mfma_bf16(af[m][2], b[2], h);
-              h = mfma_bf16(af[m][6], b[2], h);
-              h = mfma_bf16(af[m][3], b[3], h);
+              h = mfma_f16(af[m][2], b[0], h);       // low weight parts first
+              h = mfma_f16(af[m][3], b[1], h);
+              h = mfma_f16(af[m][0], b[0], h);
+              h = mfma_f16(af[m][1], b[1], h);
             }
           }
           if (i > 0)
-            hidden_epilogue<C, Y1>(st1[i - 1], lds, 0, e1[i - 1], (vm1 >> (i - 1)) & 1u, g, theta, alpha, relaxed,
-                                   trace_t, 1.f, c1, 0, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)));
+            hidden_epilogue<C, Y1>(st1[i - 1], lds, 0, e1[i - 1], (vm1 >> (i - 1)) & 1u, g, theta1, alpha, relaxed,
+                                   trace_t, isc1, c1, 0, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)));
         }
       } else if constexpr (!C::BF16) {
         // f32 MFMA; the operands of k-step q+1 load while those of q multiply
@@ -1253,7 +1263,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       if constexpr (!C::XSPLIT) {
 #pragma unroll
         for (int i = 0; i < C::NB1; ++i)
-          hidden_epilogue<C, Y1>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta, alpha, relaxed, trace_t, 1.f, c1,
+          hidden_epilogue<C, Y1>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta1, alpha, relaxed, trace_t, isc1, c1,
                                  0, gy0, gx0, tb, ay, yidx(wave + C::NW * i));
       }
       lds_barrier();                                   // B1: s1 visible, x buffer (t & 1) free
@@ -1623,7 +1633,9 @@ __device__ __forceinline__ void init_lds(const FwdNetArgs& na, char* lds) {
     const u4* src = reinterpret_cast<const u4*>(na.frag + kFragHeaderWords);
     u4* dst = reinterpret_cast<u4*>(lds + Lo::WL);
     for (int e = threadIdx.x; e < (Lo::YS - Lo::WL) / 16; e += C::NT) dst[e] = src[e];
-    if (threadIdx.x < 2) reinterpret_cast<unsigned*>(lds + Lo::SCL)[threadIdx.x] = na.frag[4 + threadIdx.x];
+    // |w|max bits: slots 0, 1 in header words 4, 5, slot 2 in word 7
+    if (threadIdx.x < 3)
+      reinterpret_cast<unsigned*>(lds + Lo::SCL)[threadIdx.x] = na.frag[threadIdx.x == 2 ? 7 : 4 + threadIdx.x];
   } else {
     load_weights<C>(na, lds);
   }
@@ -1649,7 +1661,7 @@ __global__ __launch_bounds__(C::NT) void k_prepack(FwdNetArgs na, uint32_t* dst)
     dst[4] = reinterpret_cast<const unsigned*>(lds + Lo::SCL)[0];
     dst[5] = reinterpret_cast<const unsigned*>(lds + Lo::SCL)[1];
     dst[6] = (uint32_t)(Lo::YS - Lo::WL);
-    dst[7] = 0u;
+    dst[7] = reinterpret_cast<const unsigned*>(lds + Lo::SCL)[2];
   }
 }
 template <class C>

@@ -11,7 +11,10 @@ int zero_f32(float* p, size_t n, hipStream_t s);
 int copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
 int fill_uniform(float* p, size_t n, uint32_t seed, float lo, float hi, hipStream_t s);
 // adds the number of NaN values in p[0, n) to the status-word counter *word
-int count_nan(const float* p, size_t n, int32_t* word, hipStream_t s);
+// NaN count of p[0, n) added to *word; with range > 0, |v| >= range (or
+// infinite) anywhere sets bit `flag` of *flags.
+int count_nan(const float* p, size_t n, int32_t* word, hipStream_t s, float range = 0.f, int32_t* flags = nullptr,
+              int flag = 0);
 
 // EMD loss (evs_emd.hip)
 size_t emd_workspace_bytes(int N, int T, int C, int H, int W);

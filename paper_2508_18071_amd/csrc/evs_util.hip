@@ -72,10 +72,14 @@ __device__ inline void sat_add(int32_t* word, unsigned n) {
 }
 
 // NaN values among p[0, n): 16-byte loads over the aligned body (vec), one
-// count per workgroup added to *word.
+// count per workgroup added to *word.  With range > 0, any value with
+// |v| >= range (infinities included) also sets `flag` in *flags.
 __global__ __launch_bounds__(256) void k_count_nan(const float* __restrict__ p, size_t n, int vec,
-                                                   int32_t* __restrict__ word) {
-  unsigned c = 0;
+                                                   int32_t* __restrict__ word, float range,
+                                                   int32_t* __restrict__ flags, int flag) {
+  unsigned c = 0, big = 0;
+  const float lim = range > 0.f ? range : __builtin_inff();
+  auto out = [&](float v) __attribute__((always_inline)) { return __builtin_fabsf(v) >= lim ? 1u : 0u; };
   const size_t stride = (size_t)gridDim.x * 256;
   size_t i0 = blockIdx.x * (size_t)256 + threadIdx.x;
   size_t body = 0;
@@ -85,28 +89,37 @@ __global__ __launch_bounds__(256) void k_count_nan(const float* __restrict__ p, 
     for (size_t i = i0; i < body; i += stride) {
       const float4 v = q[i];
       c += (v.x != v.x) + (v.y != v.y) + (v.z != v.z) + (v.w != v.w);
+      big |= out(v.x) | out(v.y) | out(v.z) | out(v.w);
     }
     body *= 4;
   }
-  for (size_t i = body + i0; i < n; i += stride) c += p[i] != p[i];
+  for (size_t i = body + i0; i < n; i += stride) {
+    c += p[i] != p[i];
+    big |= out(p[i]);
+  }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
-  __shared__ unsigned part[4];
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  const bool any_big = __builtin_amdgcn_ballot_w64(big != 0u) != 0ull;
+  __shared__ unsigned part[4], bigw[4];
+  if ((threadIdx.x & 63) == 0) {
+    part[threadIdx.x >> 6] = c;
+    bigw[threadIdx.x >> 6] = any_big ? 1u : 0u;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned tot = part[0] + part[1] + part[2] + part[3];
     if (tot) sat_add(word, tot);
+    if (range > 0.f && (bigw[0] | bigw[1] | bigw[2] | bigw[3])) atomicOr(flags, flag);
   }
 }
 }  // namespace
 
-int count_nan(const float* p, size_t n, int32_t* word, hipStream_t s) {
+int count_nan(const float* p, size_t n, int32_t* word, hipStream_t s, float range, int32_t* flags, int flag) {
   if (n == 0) return EVS_OK;
   const int vec = (reinterpret_cast<uintptr_t>(p) & 15) == 0 ? 1 : 0;
   size_t g = (n + 256 * 16 - 1) / (256 * 16);
   g = g < 2048 ? (g ? g : 1) : 2048;
-  hipLaunchKernelGGL(k_count_nan, dim3((unsigned)g), dim3(256), 0, s, p, n, vec, word);
+  hipLaunchKernelGGL(k_count_nan, dim3((unsigned)g), dim3(256), 0, s, p, n, vec, word, range, flags, flag);
   EVS_HIP(hipGetLastError());
   return EVS_OK;
 }

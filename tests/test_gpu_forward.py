@@ -101,6 +101,25 @@ def test_forward_teacher_forced_parity(evs, channels, prec, N, T, H, W):
             assert mis <= 1e-3
 
 
+@pytest.mark.parametrize("channels", [(3, 16, 16, 2), (3, 32, 2)])
+@pytest.mark.parametrize("scale", [2.0 ** 13, 2.0 ** -16])
+def test_fp32_split_input_layer_over_the_input_range(evs, channels, scale):
+    """FP32 nets with three input channels split x into two fp16 parts in
+    their input layer.  The FP32 gate holds near the top of the accepted
+    range (max |x| about 4.3e4, below 65520) and where most values are fp16
+    subnormals (max |x| about 8e-5)."""
+    print(f"case split range channels={channels} scale={scale}", flush=True)
+    x, ws = make_inputs(channels, 4, 45, 61, seed=11, scale=scale)
+    _, _, out = _run(evs, channels, "fp32", x, ws)
+    hl = split_layers(out["h"][0].cpu().numpy(), channels)
+    rep = teacher_forced_report(x[0].numpy(), ws, THETA, LEAK, hl)
+    for l, r in enumerate(rep):
+        print(f"  layer {l + 1}: {r}", flush=True)
+        assert r["rel"] <= 1e-5, r
+        assert r["outside"] == 0, r
+        assert r["mism"] <= max(1, 1e-4 * r["n"]), r
+
+
 def test_zero_input_gives_no_spikes(evs):
     x = torch.zeros(1, 5, 3, 40, 50)
     _, ws = make_inputs((3, 16, 16, 2), 1, 4, 4)
@@ -113,7 +132,7 @@ def test_zero_input_gives_no_spikes(evs):
 def test_oddness_up_to_accumulator_rounding(evs, prec, bound):
     """Negating the input negates every potential and spike (the oracle's
     oddness pin).  The layers that read spikes run on the bf16 matrix core
-    (FP32 nets through the exact three-part weight split), whose FP32
+    (FP32 nets through fp16 weight parts), whose FP32
     accumulation on gfx950 is not exactly sign-symmetric: potentials agree
     to float32 rounding and spikes may differ only where the potential sits
     at a threshold."""

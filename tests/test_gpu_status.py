@@ -6,6 +6,8 @@
   NaN potentials that mask neurons outside the image are not counted, and
   passing the word changes no output.
 * evs_backward counts NaN values of grad_s.
+* evs_forward flags inputs beyond the fp16 split of FP32 nets with three
+  input channels (|x| >= 65520 or infinite), and only for those nets.
 * evs_compact_events flags a list cut at its capacity.
 * Counts accumulate over calls and over graph replays; NULL records nothing.
 """
@@ -76,6 +78,27 @@ def test_forward_counts_nan_inputs_once(evs, channels, prec, kw):
     if s_fp32:                                    # NaN spikes of the smooth form compare by their bits
         o1, o2 = o1.view(torch.int32), o2.view(torch.int32)
     assert torch.equal(o1, o2)
+
+
+@pytest.mark.parametrize("channels,prec,value,flagged", [
+    ((3, 16, 16, 2), "fp32", 65504.0, False),     # largest fp16 value: inside the split's range
+    ((3, 16, 16, 2), "fp32", -65519.0, False),    # rounds to -65504, still inside
+    ((3, 16, 16, 2), "fp32", 65520.0, True),      # would round to infinity
+    ((3, 32, 2), "fp32", float("-inf"), True),
+    ((3, 32, 2), "bf16", 1e9, False),             # BF16 nets do not split x
+    ((1, 16, 2), "fp32", 1e9, False),             # one-channel nets use the f32 matrix core
+    ((3, 2), "fp32", 1e9, False),                 # no hidden layer: no split
+])
+def test_forward_flags_inputs_beyond_the_fp16_split(evs, channels, prec, value, flagged):
+    print(f"case status range {channels} {prec} {value}", flush=True)
+    x, ws = make_inputs(channels, 3, 21, 27, seed=5)
+    x[0, 1, -1, 7, 11] = value
+    net = evs.Net(channels, theta=THETA, leak=LEAK, precision=prec)
+    packed = evs.pack_weights(net, [torch.from_numpy(w).cuda() for w in ws])
+    st = evs.status_word()
+    evs.forward(net, packed, x.cuda(), status=st)
+    torch.cuda.synchronize()
+    assert st.tolist() == [0, 0, evs._lib.EVS_FLAG_X_RANGE if flagged else 0, 0]
 
 
 def test_forward_rgb_input_counts_every_frame(evs):
