@@ -262,12 +262,19 @@ __global__ __launch_bounds__(NTH) void k_convT(const GS* __restrict__ gh, int Co
 // g_h tile as B, read from LDS at an immediate offset from a per-lane base.
 // Lane (pixel j, group g) receives G for channels 4g..4g+3 of pixel j and
 // runs the adjoint scan on them; wave w takes tile rows 4w..4w+3.
-//   FP32 nets (and narrow layers above): v_mfma_f32_16x16x4_f32, lane
-//     (ci, k) of the A operand holds W[co][ci][tap] (staged in LDS once per
+//   FP32 nets, narrow layer above: v_mfma_f32_16x16x4_f32, lane (ci, k) of
+//     the A operand holds W[co][ci][tap] (staged in LDS once per
 //     workgroup), K tap-major with co in lane groups of 4 (output widths
 //     below 4 padded with zero weights); the g_h planes are 336 floats apart
 //     (16 banks mod 64), so the four lane groups of a read hit distinct
 //     banks.  FP32 products and sums, in the matrix pipe's own order.
+//   FP32 nets, 16-wide layer above (kF3): the bf16 product below with g_h
+//     and W each split exactly into three bf16 parts (h = bf16(v),
+//     m = bf16(v - h), l = v - h - m) and six part products kept per
+//     k-step, (h,h) (h,m) (m,h) (h,l) (m,m) (l,h): the dropped ones are
+//     below 2^-23 |w g| together.  g_h is split while it is staged (three
+//     pairs of [pixel][8 channels] planes), the weight parts sit in LDS;
+//     30 MFMAs per row instead of 36 f32 ones at twice the issue time.
 //   BF16 nets, 16-wide layer above (B16): v_mfma_f32_16x16x32_bf16 with
 //     the bf16 g_h the layer above stored and the bf16 weights the forward
 //     used (exact products, FP32 sums): K slots 8g..8g+7 of k-step s are tap
@@ -281,6 +288,15 @@ __global__ __launch_bounds__(NTH) void k_convT(const GS* __restrict__ gh, int Co
 //     4g + 3 of both channels (tap 8 in group 2, zero weights past it), read
 //     from a table of [pixel][2 channels] bf16 pairs; 1 MFMA per row
 //     instead of 9.  (The fused weight gradient stays on the FP32 pipe.)
+// Part p of the exact split v = h + m + l into bf16 values (round to
+// nearest: h = bf16(v), m = bf16(v - h), l = v - h - m, each exact).
+__device__ inline float bf16_part(float v, int p) {
+  const float h = (float)(__bf16)v;
+  if (p == 0) return h;
+  const float r = v - h, m = (float)(__bf16)r;
+  return p == 1 ? m : r - m;
+}
+
 template <int COUTP, bool B16>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3)))
 void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int Cin, int len, int H,
@@ -295,6 +311,7 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   constexpr unsigned ESH = sizeof(HS), ESG = sizeof(GS);
   constexpr bool kBF = B16 && COUTP == 16;             // the bf16 product
   constexpr bool kBF2 = B16 && COUTP == 2;             // its two-channel form
+  constexpr bool kF3 = !B16 && COUTP == 16;            // the bf16 product on three-part splits
   constexpr int E = TT + 2;                            // haloed tile edge
   constexpr int PS = (E * E + 47) / 64 * 64 + 16;      // plane stride (floats), 16 mod 64
   constexpr int PSB = (E * E * 16 + 255) / 256 * 256;  // bf16 plane stride (bytes), multiple of 256
@@ -303,7 +320,7 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   constexpr int KSB = 5;                               // k-steps (bf16 product)
   static_assert(COG % 4 == 0, "co slots come in lane groups of 4");
   static_assert(E * E > NTH && E * E <= 2 * NTH, "a tile plane is staged in two passes");
-  __shared__ __attribute__((aligned(16))) float ghs[kBF ? 2 * PSB / 4 : COUTP * PS];
+  __shared__ __attribute__((aligned(16))) float ghs[kBF ? 2 * PSB / 4 : (kF3 ? 6 * PSB / 4 : COUTP * PS)];
   __shared__ unsigned gp2[kBF2 ? E * E : 1];           // [pixel] (co 0, co 1) bf16 pairs
   const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
@@ -315,8 +332,10 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   // read per lane for four k-steps (the A operand would otherwise take 36-72
   // registers)
   constexpr int KS4 = (KS + 3) / 4;
-  __shared__ f4 wl[kBF ? 1 : KS4 * 64];
+  __shared__ f4 wl[kBF || kF3 ? 1 : KS4 * 64];
   u4 wb[kBF ? KSB : 1];
+  // kF3: the A operand of part p, k-step s at [p][s][lane], laid out as wb
+  __shared__ u4 wl3[kF3 ? 3 * KSB * 64 : 1];
   u4 wb2 = u4{0u, 0u, 0u, 0u};
   if constexpr (kBF2) {
     // row ci = j; K slot 8g + e: tap 4g + e / 2, channel e % 2
@@ -352,6 +371,25 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
         wd[e2] = __builtin_bit_cast(unsigned, pr);
       }
       wb[s] = u4{wd[0], wd[1], wd[2], wd[3]};
+    }
+  } else if constexpr (kF3) {
+    for (int idx = threadIdx.x; idx < 3 * KSB * 64; idx += NTH) {
+      const int p = idx / (KSB * 64), sk = (idx / 64) % KSB, l = idx % 64;
+      const int tap = 2 * sk + (l >> 5);
+      unsigned wd[4];
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        float ww[2];
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const int co = 8 * ((l >> 4) & 1) + 2 * e2 + h2;
+          ww[h2] = tap < 9 ? bf16_part(wT[(tap * COUTP + co) * 16 + (l & 15)], p) : 0.f;
+        }
+        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+        const bf2 pr = {(__bf16)ww[0], (__bf16)ww[1]};   // exact: bf16 values
+        wd[e2] = __builtin_bit_cast(unsigned, pr);
+      }
+      wl3[idx] = u4{wd[0], wd[1], wd[2], wd[3]};
     }
   } else {
     for (int idx = threadIdx.x; idx < KS4 * 4 * 64; idx += NTH) {
@@ -452,9 +490,32 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
     }
   };
   // one staged tile entry (all channels) into LDS: float planes, or the two
-  // bf16 planes of [pixel][8 channels]
+  // bf16 planes of [pixel][8 channels] (three pairs of them, one per part,
+  // for kF3)
   auto stage_entry = [&](const float (&v)[COUTP], int q) __attribute__((always_inline)) {
-    if constexpr (kBF) {
+    if constexpr (kF3) {
+      typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+      float pt[3][COUTP];
+#pragma unroll
+      for (int c = 0; c < COUTP; ++c) {
+        pt[0][c] = bf16_part(v[c], 0);
+        const float r = v[c] - pt[0][c];
+        pt[1][c] = (float)(__bf16)r;
+        pt[2][c] = r - pt[1][c];
+      }
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+          unsigned wd[4];
+#pragma unroll
+          for (int e2 = 0; e2 < 4; ++e2) {
+            const bf2 pr = {(__bf16)pt[p][8 * hf + 2 * e2], (__bf16)pt[p][8 * hf + 2 * e2 + 1]};
+            wd[e2] = __builtin_bit_cast(unsigned, pr);
+          }
+          *reinterpret_cast<u4*>(reinterpret_cast<char*>(ghs) + (2 * p + hf) * PSB + q * 16) = u4{wd[0], wd[1], wd[2], wd[3]};
+        }
+    } else if constexpr (kBF) {
       typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 #pragma unroll
       for (int hf = 0; hf < 2; ++hf) {
@@ -501,7 +562,30 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
     f4 acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
-    if constexpr (kBF) {
+    if constexpr (kF3) {
+      const u4* const a3 = wl3 + lane;
+#pragma unroll
+      for (int s = 0; s < KSB; ++s) {
+        const bf8 ah = __builtin_bit_cast(bf8, a3[s * 64]), am = __builtin_bit_cast(bf8, a3[(KSB + s) * 64]),
+                  al = __builtin_bit_cast(bf8, a3[(2 * KSB + s) * 64]);
+        const int tap = 2 * s + (g >> 1) > 8 ? 8 : 2 * s + (g >> 1);     // tap 9: zero weights
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int imm = ((1 - dy) * E + (1 - dx)) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const char* const b = bbase16 + r * E * 16 + imm;
+          const bf8 bh = __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(b)),
+                    bm = __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(b + 2 * PSB)),
+                    bl = __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(b + 4 * PSB));
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[r], 0, 0, 0);   // small parts first
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[r], 0, 0, 0);
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[r], 0, 0, 0);
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[r], 0, 0, 0);
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[r], 0, 0, 0);
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[r], 0, 0, 0);
+        }
+      }
+    } else if constexpr (kBF) {
 #pragma unroll
       for (int s = 0; s < KSB; ++s) {
         const int tap = 2 * s + (g >> 1) > 8 ? 8 : 2 * s + (g >> 1);     // tap 9: zero weights

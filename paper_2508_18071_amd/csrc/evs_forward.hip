@@ -1848,8 +1848,11 @@ const Variant kVariants[] = {
     EVS_VARIANT_D(3, 3, 16, 0, 23, 32, 8, "L3 h16 f32 23x32 w8"),
     EVS_VARIANT_B(3, 3, 16, 0, 12, 32, 4, "L3 h16 f32 12x32 w4"),
     EVS_VARIANT(3, 3, 16, 0, 16, 24, 4, "L3 h16 f32 16x24 w4"),
+    // (16x32: the default of 256x256 crops in fours, 512 tiles in 2 full rounds)
+    EVS_VARIANT_D(3, 3, 16, 0, 16, 32, 8, "L3 h16 f32 16x32 w8"),
     EVS_VARIANT_D(3, 3, 16, 1, 24, 32, 8, "L3 h16 bf16 24x32 w8"),
     EVS_VARIANT_D(3, 3, 16, 1, 23, 32, 8, "L3 h16 bf16 23x32 w8"),
+    EVS_VARIANT_D(3, 3, 16, 1, 16, 32, 8, "L3 h16 bf16 16x32 w8"),
     EVS_VARIANT(3, 3, 16, 1, 16, 32, 4, "L3 h16 bf16 16x32 w4"),
     EVS_VARIANT(3, 3, 32, 1, 24, 32, 8, "L3 h32 bf16 24x32 w8"),
 };
