@@ -298,7 +298,7 @@ __device__ inline float bf16_part(float v, int p) {
 }
 
 template <int COUTP, bool B16>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(B16 && COUTP == 16 ? 4 : 3)))
 void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int Cin, int len, int H,
                                                     int W, int tiles_x, const float* __restrict__ wT,
                                                     typename Store<B16>::G* __restrict__ out,
