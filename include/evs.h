@@ -253,8 +253,12 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
  *   grad_x  NULL or [N][T][Cin][H][W] float32 dLoss/dx
  *   grad_v  NULL or [N][sum C][H][W] float32 dLoss/d(initial membrane)
  *   dev_status  NULL or the device status word (counts NaN values of grad_s)
- * Segments are recomputed from their checkpoints in reverse order; the
- * weight gradient is reduced deterministically (no float atomics).      */
+ * Segments are recomputed from their checkpoints in reverse order (with
+ * the forward's arithmetic, input range included); the weight gradient is
+ * reduced deterministically (no float atomics).  FP32 nets: every product
+ * of the gradient convolutions is carried to within 2^-23 of its value
+ * (exact three-part bf16 splits on the matrix cores, FP32 MFMA or VALU),
+ * sums and recurrences in FP32.                                         */
 int evs_backward(const evs_net* net, const void* packed, const evs_clip* clip,
                  const float* ckpt, int32_t ckpt_every, const float* grad_s,
                  float* const* grad_w, float* grad_x, float* grad_v,
