@@ -3,7 +3,8 @@
 //
 // The dense int8 array is cut into chunks of one (t, channel) plane each.
 // Pass 1 counts the non-zero spikes of every chunk; pass 2 turns the counts
-// into output offsets (exclusive scan in one workgroup); pass 3 re-reads the
+// into output offsets (exclusive scan in two levels: blocks of 1024 chunk
+// counts, then the block totals); pass 3 re-reads the
 // chunk and writes its events at that offset.  In pass 3 each lane loads 16
 // consecutive spikes per round; its exclusive offset inside the wave comes
 // from five ballots of the bit planes of its count (0..16) with mbcnt, the
@@ -20,6 +21,7 @@ constexpr int kSpl = 16;                         // spikes per lane and round (o
 constexpr int kRound = kThreads * kSpl;          // 4096 spikes per round
 constexpr int kRounds = 4;
 constexpr int kChunk = kRound * kRounds;         // 16384 spikes per workgroup
+constexpr int kScanB = 1024;                     // chunk counts per block of the offset scan
 
 __device__ inline unsigned lane_prefix(unsigned long long mask) {
   // number of lanes below this one whose bit is set in mask
@@ -66,6 +68,7 @@ __global__ __launch_bounds__(kThreads) void k_count(const int8_t* __restrict__ s
 __global__ __launch_bounds__(kThreads) void k_write(const int8_t* __restrict__ s, int HW, int W,
                                                     int chunks_per_plane, int C, int vec,
                                                     const long long* __restrict__ offsets,
+                                                    const long long* __restrict__ boff,
                                                     uint64_t* __restrict__ events, long long cap) {
   const int chunk = blockIdx.x;
   const long long plane = blockIdx.y;            // t * C + c
@@ -75,7 +78,8 @@ __global__ __launch_bounds__(kThreads) void k_write(const int8_t* __restrict__ s
   __shared__ uint2 stage[kRound];                // the round's events, dense order
   __shared__ int wave_tot[4];
   __shared__ int wave_off[5];
-  long long run = offsets[plane * chunks_per_plane + chunk];
+  const long long idx = plane * chunks_per_plane + chunk;
+  long long run = offsets[idx] + boff[idx / kScanB];
   for (int r = 0; r < kRounds; ++r) {
     const int p0 = chunk * kChunk + r * kRound + kSpl * threadIdx.x;
     const uint4 v = load16(base, p0, HW, vec != 0);
@@ -118,17 +122,44 @@ __global__ __launch_bounds__(kThreads) void k_write(const int8_t* __restrict__ s
   }
 }
 
-// Exclusive scan of the chunk counts in one workgroup (fixed order); the
-// grand total goes to *count, and a total above the capacity sets the
-// overflow flag of the status word (if given).
-__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ counts, long long n,
-                                               long long* __restrict__ offsets, int64_t* __restrict__ count,
-                                               long long cap, int32_t* __restrict__ status) {
+// Exclusive scan of the chunk counts in two levels (integer sums: the
+// result does not depend on the order).  Level 1: blocks of kScanB counts
+// scanned in one workgroup each (wave scans by shuffles, then the wave
+// totals), offsets relative to the block and the block totals.  Level 2:
+// the block totals scanned in place by one workgroup; the grand total goes
+// to *count, and a total above the capacity sets the overflow flag of the
+// status word (if given).  k_write adds the two levels.
+__global__ __launch_bounds__(kScanB) void k_scan_local(const int32_t* __restrict__ counts, long long n,
+                                                       long long* __restrict__ offsets, long long* __restrict__ btot) {
+  __shared__ int wsum[kScanB / 64];
+  const long long i = (long long)blockIdx.x * kScanB + threadIdx.x;
+  const int v = i < n ? counts[i] : 0;                 // <= kChunk: block sums fit in 32 bits
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(inc, off);
+    if (lane >= off) inc += u;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int r = 0;
+    for (int k = 0; k < kScanB / 64; ++k) { const int t = wsum[k]; wsum[k] = r; r += t; }
+    btot[blockIdx.x] = r;
+  }
+  __syncthreads();
+  if (i < n) offsets[i] = (long long)(wsum[wave] + inc - v);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(long long* __restrict__ btot, long long nb,
+                                                   int64_t* __restrict__ count, long long cap,
+                                                   int32_t* __restrict__ status) {
   __shared__ long long part[1024];
-  const long long per = (n + 1023) / 1024;
+  const long long per = (nb + 1023) / 1024;
   const long long b = threadIdx.x * per;
   long long acc = 0;
-  for (long long i = b; i < b + per && i < n; ++i) acc += counts[i];
+  for (long long k = b; k < b + per && k < nb; ++k) acc += btot[k];
   part[threadIdx.x] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -139,7 +170,11 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count
   }
   __syncthreads();
   long long run = part[threadIdx.x];
-  for (long long i = b; i < b + per && i < n; ++i) { offsets[i] = run; run += counts[i]; }
+  for (long long k = b; k < b + per && k < nb; ++k) {
+    const long long t = btot[k];
+    btot[k] = run;
+    run += t;
+  }
 }
 
 }  // namespace
@@ -148,7 +183,8 @@ size_t compact_workspace_bytes(int T, int C, int H, int W) {
   const long long HW = (long long)H * W;
   const long long cpp = (HW + kChunk - 1) / kChunk;
   const long long blocks = cpp * T * C;
-  return align256((size_t)blocks * 4) + align256((size_t)blocks * 8);
+  const long long nb = (blocks + kScanB - 1) / kScanB;
+  return align256((size_t)blocks * 4) + align256((size_t)blocks * 8) + align256((size_t)nb * 8);
 }
 
 int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events, int64_t cap,
@@ -166,6 +202,8 @@ int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events
   if (!ws || ws_bytes < need) return fail(EVS_EWORKSPACE, "compact_events: workspace too small");
   int32_t* counts = reinterpret_cast<int32_t*>(ws);
   long long* offsets = reinterpret_cast<long long*>(reinterpret_cast<char*>(ws) + align256((size_t)cpp * planes * 4));
+  const long long n = cpp * planes, nb = (n + kScanB - 1) / kScanB;
+  long long* boff = reinterpret_cast<long long*>(reinterpret_cast<char*>(offsets) + align256((size_t)n * 8));
   // grid.y holds the (t, c) planes; split across z only if the y limit is exceeded
   if (planes > 65535) return fail(EVS_EUNSUPPORTED, "compact_events: more than 65535 (t, c) planes per call");
   dim3 grid((unsigned)cpp, (unsigned)planes);
@@ -173,10 +211,11 @@ int compact_events(const int8_t* s, int T, int C, int H, int W, uint64_t* events
   const int vec = ((reinterpret_cast<uintptr_t>(s) & 15) == 0 && (HW & 15) == 0) ? 1 : 0;
   hipLaunchKernelGGL(k_count, grid, dim3(kThreads), 0, st, s, (int)HW, (int)cpp, vec, counts);
   EVS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, counts, cpp * planes, offsets, count, (long long)cap,
-                     status);
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanB), 0, st, counts, n, offsets, boff);
   EVS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_write, grid, dim3(kThreads), 0, st, s, (int)HW, W, (int)cpp, C, vec, offsets, events,
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, boff, nb, count, (long long)cap, status);
+  EVS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_write, grid, dim3(kThreads), 0, st, s, (int)HW, W, (int)cpp, C, vec, offsets, boff, events,
                      (long long)cap);
   EVS_HIP(hipGetLastError());
   return EVS_OK;
