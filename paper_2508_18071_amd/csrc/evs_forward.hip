@@ -982,6 +982,22 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       xo[k] = in ? (gy * W + gx) * 4 : (int)0x80000000u;
     }
   }
+  // Other register-staged nets: a 32-bit byte offset per staged element
+  // (channel plane and pixel of the frame, or of its red plane with RGB
+  // input), or one past the end for elements outside the canvas or the
+  // image, which reads zero
+  constexpr bool XGEN = !C::XSPLIT && !C::XDMA;
+  unsigned xog[XGEN ? C::XPF : 1];
+  if constexpr (XGEN) {
+#pragma unroll
+    for (int k = 0; k < C::XPF; ++k) {
+      const int e = tid + C::NT * k;
+      const int c = e / C::NPIX, rem = e % C::NPIX;
+      const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;
+      const bool in = e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      xog[k] = in ? (unsigned)((c * H + gy) * W + gx) * 4u : 0x80000000u;
+    }
+  }
   constexpr int XPR = C::LOGX ? 3 : 1;
   constexpr int NXPF = C::XDMA ? 1 : (C::XSPLIT ? 3 * C::XPP : C::XPF * XPR);
   float xpf[NXPF];
@@ -998,18 +1014,16 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
         for (int c = 0; c < 3; ++c)
           xpf[3 * k + c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, xo[k], c * (int)HW * 4, 0));
-    } else if constexpr (!C::XDMA) {
-      const float* xf = xclip + (size_t)frame * (C::LOGX ? 3 : C::CIN) * HW;
+    } else if constexpr (XGEN) {
+      // buffer loads (the colour plane of RGB input in soffset)
+      float* const xf = const_cast<float*>(xclip + (size_t)frame * (C::LOGX ? 3 : C::CIN) * HW);
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc(xf, (short)0, (int)((C::LOGX ? 3 : C::CIN) * HW * 4), 0x00020000);
 #pragma unroll
-      for (int k = 0; k < C::XPF; ++k) {
-        const int e = tid + C::NT * k;
-        const int c = e / C::NPIX, rem = e % C::NPIX;
-        const int gy = gy0 + rem / C::CWT, gx = gx0 + rem % C::CWT;
-        const bool in = e < C::XN && gy >= 0 && gy < H && gx >= 0 && gx < W;
-        const size_t o = (size_t)c * HW + (size_t)gy * W + gx;
+      for (int k = 0; k < C::XPF; ++k)
 #pragma unroll
-        for (int r = 0; r < XPR; ++r) xpf[k * XPR + r] = in ? xf[o + (size_t)r * HW] : 0.f;
-      }
+        for (int r = 0; r < XPR; ++r)
+          xpf[k * XPR + r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, xog[k], r * (int)HW * 4, 0));
     }
   };
   auto load_x = [&](int tt) __attribute__((always_inline)) { fetch_x(C::LOGX ? tt + 1 : tt); };
