@@ -79,7 +79,9 @@ def _expected_events(s):
 
 
 @pytest.mark.parametrize("T,C,H,W,dens", [(7, 2, 67, 131, 0.1), (3, 1, 128, 128, 0.5), (4, 2, 720, 1280, 0.05),
-                                         (2, 2, 5, 3, 0.9), (1, 1, 1, 1, 1.0)])
+                                         (2, 2, 5, 3, 0.9), (1, 1, 1, 1, 1.0),
+                                         # 1520 chunks: the offset scan's blocks of 1024 counts, two of them
+                                         (40, 2, 480, 640, 0.02)])
 def test_compaction_exact(evs, T, C, H, W, dens):
     rng = np.random.default_rng(T * 1000 + H)
     s = rng.choice(np.array([-1, 0, 1], np.int8), p=[dens / 2, 1 - dens, dens / 2], size=(T, C, H, W))
@@ -101,6 +103,19 @@ def test_compaction_empty_and_overflow(evs):
     s = rng.choice(np.array([-1, 0, 1], np.int8), p=[0.2, 0.6, 0.2], size=(3, 2, 40, 50))
     exp = _expected_events(s)
     cap = len(exp) // 3
+    ev, cnt = evs.compact_events(torch.from_numpy(s).cuda(), capacity=cap)
+    torch.cuda.synchronize()
+    assert int(cnt) == len(exp)
+    np.testing.assert_array_equal(ev[:cap].cpu().numpy().view(np.uint64), exp[:cap])
+
+
+def test_compaction_overflow_across_scan_blocks(evs):
+    """A capacity that cuts the list inside the second block of chunk counts
+    (3420 chunks: four blocks of the offset scan)."""
+    rng = np.random.default_rng(11)
+    s = rng.choice(np.array([-1, 0, 1], np.int8), p=[0.05, 0.9, 0.05], size=(30, 2, 720, 1280))
+    exp = _expected_events(s)
+    cap = (len(exp) * 3) // 8
     ev, cnt = evs.compact_events(torch.from_numpy(s).cuda(), capacity=cap)
     torch.cuda.synchronize()
     assert int(cnt) == len(exp)
