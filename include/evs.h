@@ -60,10 +60,16 @@ typedef enum {
 typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
 
 /* Network description (host struct, read during the call only).
- *   n_layers   L in 1..3
+ *   n_layers   L in 1..EVS_MAX_LAYERS (8)
  *   ch[0]      input channels Cin: 3 (RGB) or 1
- *   ch[1..L-1] hidden widths, each in 1..32 (all hidden layers equal);
- *              widths are padded internally to 16 or 32 with zero weights
+ *   ch[1..L-1] hidden widths, each in 1..32.  Nets of at most three layers
+ *              whose hidden layers have equal widths run the fused kernels
+ *              (all layers and frames of a tile in one launch; widths
+ *              padded internally to 16 or 32 with zero weights; the tile
+ *              calls below list them); other shapes run layer by layer
+ *              (one launch per frame and layer, FP32 VALU arithmetic on the
+ *              same operands, the same outputs and layouts; direct input
+ *              only).  Entries past ch[L] are ignored.
  *   ch[L]      output channels in 1..2.  With two outputs, channel 0 is the
  *              ON stream and channel 1 the OFF stream; each is a BiLIF unit
  *              that may itself fire with either sign.
@@ -109,9 +115,10 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
 #define EVS_SURR_ATAN 1
 #define EVS_INPUT_DIRECT 0
 #define EVS_INPUT_RGB_LOGDIFF 1
+#define EVS_MAX_LAYERS 8
 typedef struct evs_net {
   int32_t n_layers;
-  int32_t ch[4];
+  int32_t ch[EVS_MAX_LAYERS + 1];
   float theta;
   float leak;
   float surr_alpha;
@@ -363,11 +370,13 @@ int evs_tnet_forward(const evs_tnet* net, const float* weights, const float* x, 
  * fastest for later evs_forward calls with this (net, H, W).  If the
  * environment variable EVS_AUTOTUNE_CACHE names a file, the cache is
  * loaded from and saved to it.  `chosen` (host, may be NULL) receives the
- * chosen tile id.                                                        */
+ * chosen tile id, or -1 for a shape that runs layer by layer (no tiles to
+ * choose from; nothing is timed).                                        */
 int evs_autotune(const evs_net* net, int32_t H, int32_t W, int32_t T, int32_t* chosen, void* stream);
 
-/* Number of compiled tile variants for `net`, and a description of one
- * (host string, valid until the library is unloaded).                    */
+/* Number of compiled tile variants for `net` (0 for a shape that runs
+ * layer by layer), and a description of one (host string, valid until the
+ * library is unloaded).                                                  */
 int32_t evs_tile_count(const evs_net* net);
 const char* evs_tile_name(const evs_net* net, int32_t tile_id);
 

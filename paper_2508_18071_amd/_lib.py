@@ -23,12 +23,13 @@ EVS_OP_FORWARD, EVS_OP_BACKWARD, EVS_OP_EMD, EVS_OP_COMPACT = range(4)
 EVS_STATUS_WORDS, EVS_STATUS_NAN_X, EVS_STATUS_NAN_GRAD, EVS_STATUS_FLAGS = 4, 0, 1, 2
 EVS_FLAG_EVENT_OVERFLOW = 1
 EVS_FLAG_X_RANGE = 2
+EVS_MAX_LAYERS = 8
 
 
 class EvsNet(ctypes.Structure):
     _fields_ = [
         ("n_layers", ctypes.c_int32),
-        ("ch", ctypes.c_int32 * 4),
+        ("ch", ctypes.c_int32 * (EVS_MAX_LAYERS + 1)),
         ("theta", ctypes.c_float),
         ("leak", ctypes.c_float),
         ("surr_alpha", ctypes.c_float),

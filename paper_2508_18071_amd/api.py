@@ -36,7 +36,7 @@ class Net:
         n = EvsNet()
         L = len(self.channels) - 1
         n.n_layers = L
-        for i in range(4):
+        for i in range(_lib.EVS_MAX_LAYERS + 1):
             n.ch[i] = self.channels[i] if i <= L else 0
         n.theta = self.theta
         n.leak = self.leak

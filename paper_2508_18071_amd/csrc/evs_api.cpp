@@ -32,11 +32,10 @@ int hip_check(hipError_t e, const char* what) {
 int validate_net(const evs_net* net) {
   if (!net) return fail(EVS_EINVAL, "net is NULL");
   const int L = net->n_layers;
-  if (L < 1 || L > 3) return fail(EVS_EINVAL, "n_layers must be 1..3");
+  if (L < 1 || L > kMaxLayers) return fail(EVS_EINVAL, "n_layers must be 1..8");
   if (net->ch[0] != 1 && net->ch[0] != 3) return fail(EVS_EUNSUPPORTED, "input channels must be 1 or 3");
   for (int l = 1; l < L; ++l)
     if (net->ch[l] < 1 || net->ch[l] > 32) return fail(EVS_EUNSUPPORTED, "hidden width must be 1..32");
-  if (L == 3 && net->ch[1] != net->ch[2]) return fail(EVS_EUNSUPPORTED, "hidden layers must have equal widths");
   if (net->ch[L] < 1 || net->ch[L] > 2) return fail(EVS_EUNSUPPORTED, "output channels must be 1 or 2");
   if (!(net->theta > 0.f) || !(net->theta < 3.0e38f)) return fail(EVS_EINVAL, "theta must be positive and finite");
   if (!(net->leak >= 0.f && net->leak <= 1.f)) return fail(EVS_EINVAL, "leak must be in [0, 1]");
@@ -124,7 +123,7 @@ FwdNetArgs make_net_args(const evs_net& net, const void* packed, bool with_frag)
                 : nullptr;
   na.n_layers = net.n_layers;
   int ofs = 0;
-  for (int l = 0; l < 4; ++l) na.ch[l] = l <= net.n_layers ? net.ch[l] : 0;
+  for (int l = 0; l <= kMaxLayers; ++l) na.ch[l] = l <= net.n_layers ? net.ch[l] : 0;
   for (int l = 0; l < net.n_layers; ++l) {
     na.wofs[l] = ofs;
     ofs += net.ch[l + 1] * net.ch[l] * 9;
@@ -203,6 +202,15 @@ size_t evs_workspace_bytes(const evs_net* net, const evs_clip* clips, int32_t n_
     case EVS_OP_FORWARD: {
       if (validate_net(net) != EVS_OK) return (size_t)-1;
       size_t b = 0;
+      if (!fused_shape(*net)) {
+        // layer by layer: the clips run one after the other in one workspace
+        for (int i = 0; i < n_clips; ++i) {
+          if (validate_clip(*net, clips[i], false) != EVS_OK) return (size_t)-1;
+          const size_t bi = layerwise_workspace_bytes(*net, clips[i].N, clips[i].H, clips[i].W);
+          b = bi > b ? bi : b;
+        }
+        return b;
+      }
       for (int i = 0; i < n_clips; ++i) {
         if (validate_clip(*net, clips[i], false) != EVS_OK) return (size_t)-1;
         if (clips[i].v_state)
@@ -252,6 +260,31 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
                           fp16_split ? 65520.f : 0.f, dev_status + EVS_STATUS_FLAGS, EVS_FLAG_X_RANGE)))
         return st;
     }
+  }
+  if (!fused_shape(*net)) {
+    // no fused kernel for this shape: layer by layer, clip after clip
+    if (net->input != EVS_INPUT_DIRECT)
+      return fail(EVS_EUNSUPPORTED, "RGB input needs a network shape with fused kernels (at most 3 layers)");
+    const int sumc = real_sum_channels(*net);
+    for (int i = 0; i < n_clips; ++i) {
+      const evs_clip& c = clips[i];
+      const long long HW = (long long)c.H * c.W;
+      LwClip lc{};
+      lc.N = c.N; lc.T = c.T; lc.H = c.H; lc.W = c.W;
+      lc.x = c.x;
+      lc.x_nstride = (long long)c.T * net->ch[0] * HW;
+      lc.v_in = c.v_state;
+      lc.vin_nstride = (long long)sumc * HW;
+      lc.v_out = c.v_state;
+      lc.s_out = c.s_out;
+      lc.s_fp32 = c.s_fp32;
+      lc.ckpt = ckpt;
+      lc.ckpt_every = ckpt ? ckpt_every : 0;
+      lc.h_trace = c.h_trace;
+      for (int k = 0; k < 4; ++k) lc.tb[k] = c.trace_box[k];
+      if ((st = layerwise_forward(*net, reinterpret_cast<const float*>(packed), lc, ws, s))) return st;
+    }
+    return EVS_OK;
   }
   const FwdNetArgs na = make_net_args(*net, packed);
   const int sumc = na.sum_c;

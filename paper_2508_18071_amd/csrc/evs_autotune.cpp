@@ -91,7 +91,11 @@ int evs_autotune(const evs_net* net, int32_t H, int32_t W, int32_t T, int32_t* c
   if (H < 1 || W < 1 || T < 1 || H > 4096 || W > 4096) return fail(EVS_EINVAL, "autotune: bad frame size");
   load_tile_cache_once();
   const int n = forward_tile_count(*net);
-  if (n < 1) return fail(EVS_EUNSUPPORTED, "autotune: no compiled kernel for this network");
+  if (n < 1) {
+    // a shape without fused kernels runs layer by layer: nothing to choose
+    if (chosen) *chosen = -1;
+    return EVS_OK;
+  }
   hipStream_t s = (hipStream_t)stream;
   const size_t HW = (size_t)H * W;
   const int cin = net->ch[0], cout = net->ch[net->n_layers];

@@ -1239,7 +1239,7 @@ int trace_planes(const evs_net& net) {
 }
 
 struct BwdLayout {
-  size_t hseg, gv, gh, gh2, partial, acc, wT, total;
+  size_t hseg, gv, gh, gh2, partial, acc, wT, lw, total;
   int k, nseg, cmax, tiles_x, tiles_y;
 };
 
@@ -1270,6 +1270,8 @@ BwdLayout layout(const evs_net& net, const evs_clip& c, int k) {
   L.partial = o; o += align256(nblk * accsum * 4);
   L.acc = o; o += align256((size_t)accsum * 4);
   L.wT = o; o += align256((size_t)accsum * 4);
+  // the layer-by-layer recompute's own buffers (shapes without fused kernels)
+  L.lw = o; o += fused_shape(net) ? 0 : align256(layerwise_workspace_bytes(net, c.N, c.H, c.W));
   L.total = o;
   return L;
 }
@@ -1305,17 +1307,17 @@ int run_backward(const evs_net& net, const void* packed, const evs_clip& clip, c
   const bool bf = net.precision == EVS_BF16;
   const FwdNetArgs na = make_net_args(net, packed);
   const float* wbase = reinterpret_cast<const float*>(packed);
-  int choff[4] = {0, 0, 0, 0};
+  int choff[kMaxLayers + 1] = {};
   for (int l = 1; l < L; ++l) choff[l] = choff[l - 1] + net.ch[l];   // choff[l-1] = offset of layer l
   // the layers' blocks in the pixel-major segment trace: ht[l - 1] is layer l
   const int tpf = trace_planes(net);
-  HTrace ht[4];
+  HTrace ht[kMaxLayers];
   for (int l = 1, o = 0; l <= L; ++l) {
     const int cw = l == L ? 4 : (net.ch[l] + 3) & ~3;
     ht[l - 1] = HTrace{tpf, o, cw};
     o += cw;
   }
-  int accofs[4] = {0, 0, 0, 0};
+  int accofs[kMaxLayers + 1] = {};
   for (int l = 1; l <= L; ++l) accofs[l] = accofs[l - 1] + pad_in(net.ch[l - 1]) * pad_out(net.ch[l]) * 9;
 
   if ((rc = zero_f32(gv, (size_t)N * sumc * HW, st))) return rc;
@@ -1330,31 +1332,48 @@ int run_backward(const evs_net& net, const void* packed, const evs_clip& clip, c
                        net.ch[l], net.ch[l - 1], CI, CO, bf ? 1 : 0, wT + accofs[l - 1]);
     EVS_HIP(hipGetLastError());
   }
-  const int tile = choose_tile(net, H, W, N);
+  const bool fused = fused_shape(net);
+  const int tile = fused ? choose_tile(net, H, W, N) : -1;
   int th = 0, tw = 0;
-  forward_tile_dims(net, tile, &th, &tw);
-  if (th == 0) return fail(EVS_EUNSUPPORTED, "backward: no forward kernel for this network");
+  if (fused) {
+    forward_tile_dims(net, tile, &th, &tw);
+    if (th == 0) return fail(EVS_EUNSUPPORTED, "backward: no forward kernel for this network");
+  }
 
   for (int s = Lo.nseg - 1; s >= 0; --s) {
     const int t0 = s * k;
     const int len = (t0 + k <= T ? k : T - t0);
-    // 1. recompute the segment's potentials from its checkpoint
-    FwdClipArgs ca{};
-    ca.x = clip.x + (size_t)t0 * cin0 * HW;
-    ca.x_nstride = (long long)T * cin0 * HW;
-    // checkpoint index: the forward stored one state every ckpt_every frames
+    // 1. recompute the segment's potentials from its checkpoint (the forward
+    // stored one state every ckpt_every frames)
     if (t0 % ckpt_every != 0) return fail(EVS_EINVAL, "backward: segment start is not a checkpoint");
-    ca.v_in = ckpt + (size_t)(t0 / ckpt_every) * sumc * HW;
-    ca.vin_nstride = (long long)nseg_ck * sumc * HW;
-    ca.h_trace = reinterpret_cast<float*>(hseg);
-    ca.trace_f16 = B16 ? 1 : 0;
-    ca.trace_pm = 1;
-    ca.trace_nstride = (long long)len * tpf * HW;
-    ca.tb_y0 = 0; ca.tb_x0 = 0; ca.tb_h = H; ca.tb_w = W;
-    ca.N = N; ca.T = len; ca.H = H; ca.W = W;
-    ca.tiles_x = (W + tw - 1) / tw;
-    ca.tiles_y = (H + th - 1) / th;
-    if ((rc = launch_forward(net, na, ca, tile, st))) return rc;
+    if (!fused) {
+      LwClip lc{};
+      lc.N = N; lc.T = len; lc.H = H; lc.W = W;
+      lc.x = clip.x + (size_t)t0 * cin0 * HW;
+      lc.x_nstride = (long long)T * cin0 * HW;
+      lc.v_in = ckpt + (size_t)(t0 / ckpt_every) * sumc * HW;
+      lc.vin_nstride = (long long)nseg_ck * sumc * HW;
+      lc.rtrace = hseg;
+      lc.rt_f16 = B16 ? 1 : 0;
+      lc.rt_nstride = (long long)len * tpf * HW;
+      if ((rc = layerwise_forward(net, wbase, lc, w8 + Lo.lw, st))) return rc;
+    } else {
+      FwdClipArgs ca{};
+      ca.x = clip.x + (size_t)t0 * cin0 * HW;
+      ca.x_nstride = (long long)T * cin0 * HW;
+      // checkpoint index: the forward stored one state every ckpt_every frames
+      ca.v_in = ckpt + (size_t)(t0 / ckpt_every) * sumc * HW;
+      ca.vin_nstride = (long long)nseg_ck * sumc * HW;
+      ca.h_trace = reinterpret_cast<float*>(hseg);
+      ca.trace_f16 = B16 ? 1 : 0;
+      ca.trace_pm = 1;
+      ca.trace_nstride = (long long)len * tpf * HW;
+      ca.tb_y0 = 0; ca.tb_x0 = 0; ca.tb_h = H; ca.tb_w = W;
+      ca.N = N; ca.T = len; ca.H = H; ca.W = W;
+      ca.tiles_x = (W + tw - 1) / tw;
+      ca.tiles_y = (H + th - 1) / th;
+      if ((rc = launch_forward(net, na, ca, tile, st))) return rc;
+    }
 
     // 2-4. layers L..1: the top layer's adjoint scan reads grad_s; each
     // lower layer's scan runs inside the conv-transpose of the layer above

@@ -1910,13 +1910,13 @@ int padded_hidden(const evs_net& net) {
 
 bool matches(const Variant& v, const evs_net& net) {
   return v.nl == net.n_layers && v.cin == net.ch[0] && v.bf16 == (net.precision == EVS_BF16) &&
-         (net.n_layers == 1 || v.ch == padded_hidden(net));
+         (net.n_layers == 1 || v.ch == padded_hidden(net)) && (net.n_layers < 3 || net.ch[1] == net.ch[2]);
 }
 
 const ShapePrepack* find_prepack(const evs_net& net) {
   for (const ShapePrepack& p : kPrepacks)
     if (p.nl == net.n_layers && p.cin == net.ch[0] && p.bf16 == (net.precision == EVS_BF16) &&
-        (net.n_layers == 1 || p.ch == padded_hidden(net)))
+        (net.n_layers == 1 || p.ch == padded_hidden(net)) && (net.n_layers < 3 || net.ch[1] == net.ch[2]))
       return &p;
   return nullptr;
 }
@@ -1952,6 +1952,8 @@ int forward_tile_count(const evs_net& net) {
   for (int i = 0; i < kNumVariants; ++i) k += matches(kVariants[i], net) ? 1 : 0;
   return k;
 }
+
+bool fused_shape(const evs_net& net) { return forward_tile_count(net) > 0; }
 
 const char* forward_tile_name(const evs_net& net, int tile_id) {
   const Variant* v = find_variant(net, tile_id);

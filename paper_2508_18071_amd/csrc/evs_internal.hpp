@@ -78,11 +78,12 @@ struct FwdClipArgs {
   int32_t trace_pm;
 };
 
+constexpr int kMaxLayers = EVS_MAX_LAYERS;
 struct FwdNetArgs {
   const float* w;        // packed fp32 weights, layer after layer [Cout][Cin][3][3]
   int32_t n_layers;
-  int32_t ch[4];         // real channel counts
-  int32_t wofs[3];       // float offsets of each layer in w
+  int32_t ch[kMaxLayers + 1];   // real channel counts
+  int32_t wofs[kMaxLayers];     // float offsets of each layer in w
   int32_t sum_c;
   float theta, leak, alpha;
   int32_t relaxed;       // 0 hard spikes, 1 relaxed (sigmoid step), 2 relaxed (arctangent step)

@@ -16,6 +16,40 @@ int fill_uniform(float* p, size_t n, uint32_t seed, float lo, float hi, hipStrea
 int count_nan(const float* p, size_t n, int32_t* word, hipStream_t s, float range = 0.f, int32_t* flags = nullptr,
               int flag = 0);
 
+// Layer-by-layer forward (evs_layerwise.hip) of the networks the fused
+// kernels do not cover (fused_shape false): one clip of N, direct input.
+//   x        [N][T][Cin][H][W] frames 0..T-1 of clip n at x + n x_nstride
+//   v_in     initial state [sum C][H][W] of clip n at v_in + n vin_nstride, or
+//            null (zero); v_out: final state [N][sum C][H][W], or null
+//   s_out    [N][T][Cout][H][W] int8 or (s_fp32) float32, or null
+//   ckpt     [N][ceil(T / ckpt_every)][sum C][H][W], or null
+//   h_trace  public trace [N][T][sum C][tb h][tb w] over tb (tb[2] == 0: the
+//            whole frame), or null
+//   rtrace   the backward's pixel-major trace, frames [T][planes][H][W]
+//            (fp16 if rt_f16), clip n at + n rt_nstride elements, or null
+struct LwClip {
+  int N, T, H, W;
+  const float* x;
+  long long x_nstride;
+  const float* v_in;
+  long long vin_nstride;
+  float* v_out;
+  void* s_out;
+  int s_fp32;
+  float* ckpt;
+  int ckpt_every;
+  float* h_trace;
+  int tb[4];
+  void* rtrace;
+  int rt_f16;
+  long long rt_nstride;
+};
+size_t layerwise_workspace_bytes(const evs_net& net, int N, int H, int W);
+int layerwise_forward(const evs_net& net, const float* w, const LwClip& c, void* ws, hipStream_t st);
+// true when compiled fused kernels cover the network's shape (at most three
+// layers, equal hidden widths)
+bool fused_shape(const evs_net& net);
+
 // EMD loss (evs_emd.hip)
 size_t emd_workspace_bytes(int N, int T, int C, int H, int W);
 int emd_loss(const float* s, const int8_t* e, int N, int T, int C, int H, int W, float lambda,

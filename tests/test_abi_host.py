@@ -55,7 +55,8 @@ def _net(evs, **kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(channels=(3, 16, 16, 2), theta=0.0), 1),
     (dict(channels=(3, 16, 16, 2), leak=1.5), 1),
-    (dict(channels=(3, 16, 8, 2)), 2),
+    (dict(channels=(3,) + (8,) * 8 + (2,)), 1),        # nine layers
+    (dict(channels=(3, 16, 33, 16, 2)), 2),             # a hidden layer wider than 32
     (dict(channels=(3, 64, 2)), 2),
     (dict(channels=(3, 16, 3)), 2),
     (dict(channels=(2, 16, 2)), 2),
@@ -94,8 +95,8 @@ def _header_struct_fields(name):
         if not decl:
             continue
         for part in decl.split(",") if "," in decl and "[" not in decl else [decl]:
-            tok = part.strip().split()[-1].lstrip("*")
-            fields.append(tok.split("[")[0])
+            # the declarator's name: the identifier before an optional [size]
+            fields.append(re.search(r"(\w+)\s*(?:\[[^\]]*\])?\s*$", part.strip()).group(1))
     return fields
 
 
