@@ -147,3 +147,50 @@ def test_layerwise_backward_matches_oracle(evs, channels, prec, k):
         r = rel(gws[l].cpu().numpy(), dW_ref[l])
         print(f"  layer {l + 1} dW rel err {r:.2e}", flush=True)
         assert r < tol
+
+
+@pytest.mark.parametrize("surr,alpha", [("sigmoid", 4.0), ("atan", 2.0)])
+def test_layerwise_relaxed_backward_matches_oracle_and_finite_differences(evs, surr, alpha):
+    """Smooth spikes through four layers (8x8 pixels, 4 frames): BPTT against
+    the oracle's relaxed BPTT and against central differences of the GPU's
+    own relaxed forward."""
+    channels = (3, 6, 10, 6, 2)
+    T, H, W = 4, 8, 8
+    x, ws = make_inputs(channels, T, H, W, seed=13)
+    net = evs.Net(channels, theta=THETA, leak=LEAK, relaxed=True, surrogate=surr, surr_alpha=alpha)
+    packed = evs.pack_weights(net, [torch.from_numpy(w).cuda() for w in ws])
+    assert evs.tile_count(net) == 0
+    xg = x.cuda()
+    G = np.random.default_rng(4).normal(size=(1, T, 2, H, W)).astype(np.float32)
+    Gt = torch.from_numpy(G).cuda()
+    out = evs.forward(net, packed, xg, s_fp32=True, ckpt_every=2)
+    gws, dx, _ = evs.backward(net, packed, xg, out["ckpt"], 2, Gt, want_dx=True)
+    torch.cuda.synchronize()
+    ref = evsnet.backward(x[0].numpy(), ws, THETA, LEAK, G[0], mode="relaxed", alpha=alpha, surr=surr)
+
+    def rel(a, b):
+        return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-12))
+
+    for l in range(len(ws)):
+        assert rel(gws[l].cpu().numpy(), ref["dW"][l]) < 1e-4
+    assert rel(dx[0].cpu().numpy(), ref["dx"]) < 1e-4
+
+    def loss(wlist):
+        p = evs.pack_weights(net, [torch.from_numpy(w).cuda() for w in wlist])
+        o = evs.forward(net, p, xg, s_fp32=True)
+        return float((o["s"].double() * Gt.double()).sum())
+
+    rng = np.random.default_rng(0)
+    eps = 2e-3
+    errs = []
+    for l in range(len(ws)):
+        for _ in range(4):
+            idx = tuple(int(rng.integers(0, n)) for n in ws[l].shape)
+            wp = [w.copy() for w in ws]
+            wm = [w.copy() for w in ws]
+            wp[l][idx] += eps
+            wm[l][idx] -= eps
+            errs.append(abs((loss(wp) - loss(wm)) / (2 * eps) - float(gws[l].cpu().numpy()[idx]))
+                        / max(1.0, abs((loss(wp) - loss(wm)) / (2 * eps))))
+    print(f"  relaxed FD max err {max(errs):.2e}", flush=True)
+    assert max(errs) < 1e-2
