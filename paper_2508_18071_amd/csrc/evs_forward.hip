@@ -558,21 +558,6 @@ __device__ __forceinline__ int tap_off(int tau, int cwt) {
   return (ty - 1) * cwt + (tau - 3 * ty - 1);
 }
 
-// Output spikes of one frame: buffer stores at 32-bit offsets into the
-// frame's [cout][H][W] block of s_out, int8 or (training builds with
-// s_fp32) float32.  A NULL s_out gives an empty resource, so every store is
-// dropped, and so is one at element kDeadOut (neurons that are not stored:
-// kDeadOut and four times it lie past any frame block).
-constexpr unsigned kDeadOut = 0x20000000u;
-struct SpikeOut {
-  __amdgpu_buffer_rsrc_t r;
-  bool f32;
-  __device__ __forceinline__ void put(unsigned el, float s) const {
-    if (f32) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, s), r, (int)(el * 4u), 0, 0);
-    else __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(int)s, r, (int)el, 0, 0);
-  }
-};
-
 // Window of the image whose potentials go to the trace.
 struct TraceBox {
   int y0, x0, h, w;
@@ -1113,14 +1098,6 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
   };
   const int nseg = ca.ckpt_every > 0 ? cdiv(T, ca.ckpt_every) : 0;
   const TraceBox tb{ca.tb_y0, ca.tb_x0, ca.tb_h, ca.tb_w};
-  auto spike_out = [&](int t) __attribute__((always_inline)) {
-    const bool f32 = C::CKS && ca.s_fp32;
-    const unsigned es = f32 ? 4u : 1u;
-    char* const base = reinterpret_cast<char*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW * es;
-    return SpikeOut{__builtin_amdgcn_make_buffer_rsrc(base, (short)0, ca.s_out ? (int)((unsigned)(cout * HW) * es) : 0,
-                                                      0x00020000),
-                    f32};
-  };
   auto write_state = [&](float* dst) __attribute__((always_inline)) {
     if constexpr (C::NH >= 1) write_hidden_state<C, C::NB1>(st1, vm1, a1, g, dst, c1, 0, gy0, gx0, W, HW, isc1);
     if constexpr (C::NH >= 2) write_hidden_state<C, C::NB2>(st2, vm2, a2, g, dst, c2, choff2, gy0, gx0, W, HW, isc2);
@@ -1441,7 +1418,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       // ================= output layer on MFMA: rows 4co + p, K = tap * CH + ci
       const char* const sob = C::NH == 2 ? sp2 : sp1;
       const u4* fr3 = reinterpret_cast<const u4*>(lds + Lo::FR3) + lane;
-      const SpikeOut sout = spike_out(t);
+      int8_t* const s8 = reinterpret_cast<int8_t*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
+      float* const s32 = reinterpret_cast<float*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
       // fire/reset of output block i; lanes of group g < 2 hold output
       // channel g of pixel j (rows 4g + p of the accumulator)
       auto out_epilogue = [&](int i, const f4& acc) __attribute__((always_inline)) {
@@ -1458,7 +1436,10 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
             rec_store1<C>(trace_t, rec_pix<C>(ao[i], oo[i] >= 0, gy0, gx0, H, W, 4) + g, h * isc3, sp);
           asm volatile("" : "+v"(v));
           vo[i] = v;
-          sout.put(oo[i] >= 0 ? (unsigned)oo[i] : kDeadOut, sp);
+          if (oo[i] >= 0 && ca.s_out) {
+            if (C::CKS && ca.s_fp32) s32[oo[i]] = sp;
+            else s8[oo[i]] = (int8_t)sp;
+          }
         }
       };
       if constexpr (C::BO) {
@@ -1518,7 +1499,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       // output pixel, both channels; potentials in the output conv's weight
       // scale (threshold theta3), traces and state unscaled
       const float* const ys = reinterpret_cast<const float*>(lds + Lo::YS);
-      const SpikeOut sout = spike_out(t);
+      int8_t* const s8 = reinterpret_cast<int8_t*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
+      float* const s32 = reinterpret_cast<float*>(ca.s_out) + ((size_t)tl.n * T + t) * cout * HW;
 #pragma unroll
       for (int k = 0; k < C::NOUT; ++k) {
         float u0 = 0.f, u1 = 0.f;
@@ -1544,7 +1526,10 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           so[k][co] = v;
           hs[co] = h * isc3;
           ss[co] = sp;
-          sout.put(ok && co < cout ? (unsigned)(co * (int)HW) + (unsigned)pix : kDeadOut, sp);
+          if (ok && co < cout && ca.s_out) {
+            if (C::CKS && ca.s_fp32) s32[(size_t)co * HW + pix] = sp;
+            else s8[(size_t)co * HW + pix] = (int8_t)sp;
+          }
         }
         // both channels of the pixel (a second channel of a one-channel net
         // has no weights and stays 0)
@@ -1552,7 +1537,6 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
       }
     } else {
       // ================= output layer (VALU), weights broadcast from LDS
-      const SpikeOut sout = spike_out(t);
       float u[C::NOUT][2];
 #pragma unroll
       for (int k = 0; k < C::NOUT; ++k) { u[k][0] = leak * so[k][0]; u[k][1] = leak * so[k][1]; }
@@ -1602,7 +1586,11 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           const float s = bilif(v, theta, alpha, C::RELAX ? relaxed : 0);
           if constexpr (C::REC) rec_store1<C>(trace_t, ok ? (unsigned)pix * 4u + co : 0x20000000u, u[k][co], s);
           so[k][co] = v;
-          sout.put(ok && co < cout ? (unsigned)(co * (int)HW) + (unsigned)pix : kDeadOut, s);
+          if (ok && co < cout && ca.s_out) {
+            const size_t o = (((size_t)tl.n * T + t) * cout + co) * HW + pix;
+            if (C::CKS && ca.s_fp32) reinterpret_cast<float*>(ca.s_out)[o] = s;
+            else reinterpret_cast<int8_t*>(ca.s_out)[o] = (int8_t)s;
+          }
         }
       }
     }
