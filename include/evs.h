@@ -80,7 +80,8 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
  *   precision  EVS_FP32: FP32 convolutions: sums accumulate in FP32 and
  *              every product is carried to within 2^-22 of its value
  *              (operands split into fp16 parts on the matrix cores, or f32
- *              MFMA), except in the input layer of nets with three input
+ *              MFMA, or FP32 multiply-adds on the layer-by-layer path),
+ *              except in the input layer of fused nets with three input
  *              channels and hidden layers (hard spikes), where x and W are
  *              split into two fp16 parts each: there every product is within
  *              2^-21 |w x| (plus absolute terms below 2^-35 |w|max at the
@@ -88,7 +89,9 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
  *              |x| < 65520 (larger or infinite values give NaN potentials;
  *              the status word flags them, EVS_FLAG_X_RANGE);
  *              EVS_BF16: x and W rounded to bfloat16 (round-to-nearest-even)
- *              and multiplied on BF16 MFMA with FP32 accumulation.
+ *              and multiplied on BF16 MFMA with FP32 accumulation (exact
+ *              products; the layer-by-layer path forms the same products
+ *              with FP32 multiply-adds).
  *              Membrane state, threshold compare and reset are FP32 in both.
  *   relaxed    0: hard spikes (Eq. 3).  1: smooth spikes
  *              sigma(h-theta) - sigma(-h-theta) in the output and the reset,

@@ -251,7 +251,7 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
   // channels, hidden layers, hard spikes) the same pass flags |x| >= 65520
   if (dev_status) {
     const bool fp16_split = net->precision == EVS_FP32 && net->input == EVS_INPUT_DIRECT && net->ch[0] == 3 &&
-                            net->n_layers >= 2 && !net->relaxed;
+                            net->n_layers >= 2 && !net->relaxed && fused_shape(*net);
     for (int i = 0; i < n_clips; ++i) {
       const evs_clip& c = clips[i];
       const size_t frames = net->input == EVS_INPUT_RGB_LOGDIFF ? (size_t)c.T + 1 : (size_t)c.T;

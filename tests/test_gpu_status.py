@@ -88,6 +88,7 @@ def test_forward_counts_nan_inputs_once(evs, channels, prec, kw):
     ((3, 32, 2), "bf16", 1e9, False),             # BF16 nets do not split x
     ((1, 16, 2), "fp32", 1e9, False),             # one-channel nets use the f32 matrix core
     ((3, 2), "fp32", 1e9, False),                 # no hidden layer: no split
+    ((3, 8, 16, 2), "fp32", 1e9, False),          # layer by layer: FP32 multiply-adds, no split
 ])
 def test_forward_flags_inputs_beyond_the_fp16_split(evs, channels, prec, value, flagged):
     print(f"case status range {channels} {prec} {value}", flush=True)
