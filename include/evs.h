@@ -68,8 +68,9 @@ typedef enum { EVS_FP32 = 0, EVS_BF16 = 1 } evs_precision;
  *              padded internally to 16 or 32 with zero weights; the tile
  *              calls below list them); other shapes run layer by layer
  *              (one launch per frame and layer, FP32 VALU arithmetic on the
- *              same operands, the same outputs and layouts; direct input
- *              only).  Entries past ch[L] are ignored.
+ *              same operands, the same outputs and layouts; RGB input is
+ *              formed by evs_logdiff's kernel first).  Entries past ch[L]
+ *              are ignored.
  *   ch[L]      output channels in 1..2.  With two outputs, channel 0 is the
  *              ON stream and channel 1 the OFF stream; each is a BiLIF unit
  *              that may itself fire with either sign.

@@ -206,7 +206,10 @@ size_t evs_workspace_bytes(const evs_net* net, const evs_clip* clips, int32_t n_
         // layer by layer: the clips run one after the other in one workspace
         for (int i = 0; i < n_clips; ++i) {
           if (validate_clip(*net, clips[i], false) != EVS_OK) return (size_t)-1;
-          const size_t bi = layerwise_workspace_bytes(*net, clips[i].N, clips[i].H, clips[i].W);
+          const evs_clip& c = clips[i];
+          size_t bi = layerwise_workspace_bytes(*net, c.N, c.H, c.W);
+          // RGB input: the Eq. (1) frames are formed first
+          if (net->input == EVS_INPUT_RGB_LOGDIFF) bi += align256((size_t)c.N * c.T * c.H * c.W * 4);
           b = bi > b ? bi : b;
         }
         return b;
@@ -262,9 +265,9 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
     }
   }
   if (!fused_shape(*net)) {
-    // no fused kernel for this shape: layer by layer, clip after clip
-    if (net->input != EVS_INPUT_DIRECT)
-      return fail(EVS_EUNSUPPORTED, "RGB input needs a network shape with fused kernels (at most 3 layers)");
+    // no fused kernel for this shape: layer by layer, clip after clip; RGB
+    // input goes through the Eq. (1) kernel into the workspace first (the
+    // fused kernels form the same values while staging)
     const int sumc = real_sum_channels(*net);
     for (int i = 0; i < n_clips; ++i) {
       const evs_clip& c = clips[i];
@@ -273,6 +276,13 @@ int evs_forward(const evs_net* net, const void* packed, const evs_clip* clips, i
       lc.N = c.N; lc.T = c.T; lc.H = c.H; lc.W = c.W;
       lc.x = c.x;
       lc.x_nstride = (long long)c.T * net->ch[0] * HW;
+      if (net->input == EVS_INPUT_RGB_LOGDIFF) {
+        float* xd = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) +
+                                             align256(layerwise_workspace_bytes(*net, c.N, c.H, c.W)));
+        if ((st = logdiff(c.x, c.N, c.T, c.H, c.W, net->lum_scale, net->knee, xd, s))) return st;
+        lc.x = xd;
+        lc.x_nstride = (long long)c.T * HW;
+      }
       lc.v_in = c.v_state;
       lc.vin_nstride = (long long)sumc * HW;
       lc.v_out = c.v_state;

@@ -194,3 +194,25 @@ def test_layerwise_relaxed_backward_matches_oracle_and_finite_differences(evs, s
                         / max(1.0, abs((loss(wp) - loss(wm)) / (2 * eps))))
     print(f"  relaxed FD max err {max(errs):.2e}", flush=True)
     assert max(errs) < 1e-2
+
+
+def test_layerwise_rgb_input_equals_logdiff_then_direct(evs):
+    """RGB input on the layer-by-layer path: the Eq. (1) frames formed first,
+    spikes and potentials bit for bit those of evs_logdiff followed by the
+    direct-input forward."""
+    channels = (1, 6, 8, 6, 2)
+    N, T, H, W = 1, 5, 29, 35
+    rng = np.random.default_rng(21)
+    rgb = torch.from_numpy(rng.uniform(0.0, 1.0, size=(N, T + 1, 3, H, W)).astype(np.float32)).cuda()
+    _, ws = make_inputs(channels, T, H, W, seed=2)
+    net_rgb = evs.Net(channels, theta=THETA, leak=LEAK, input="rgb_logdiff")
+    net = evs.Net(channels, theta=THETA, leak=LEAK)
+    assert evs.tile_count(net_rgb) == 0
+    p_rgb = evs.pack_weights(net_rgb, [torch.from_numpy(w).cuda() for w in ws])
+    p = evs.pack_weights(net, [torch.from_numpy(w).cuda() for w in ws])
+    a = evs.forward(net_rgb, p_rgb, rgb, trace=True)
+    x = evs.logdiff(rgb, net_rgb.lum_scale, net_rgb.knee)
+    b = evs.forward(net, p, x, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a["s"], b["s"])
+    assert torch.equal(a["h"], b["h"])
