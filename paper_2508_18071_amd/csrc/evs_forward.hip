@@ -271,32 +271,49 @@ __device__ inline float wpart(float w, int p) {
 
 // Layer-1 operand order of the split FP32 nets.  The six parts V(P) of
 // canvas pixel P are stored twice, at bytes 24P - 12 and 24P of the x area,
-// so the five 8-byte records at 24P + {-24, -16, -8, 8, 16} hold
+// so the five 8-byte records at 24P + {-24, -16, -8, 8, 16} (index rho 0..4)
+// hold
 //   V(P-1)[0..3] | V(P-1)[4..5] V(P)[0..1] | V(P)[2..5] | V(P)[4..5] V(P+1)[0..1] | V(P+1)[2..5]
 // : the 18 parts of one kernel row (taps dx = -1, 0, +1), the repeated
-// V(P)[4..5] aside.  A k-step gives lane group g records 2g and 2g + 1 of
-// its eight; record R = 8q + 2g + r of k-step q is record R % 5 of kernel
-// row R / 5, R = 15 is padding (read at P, zero weights).  Slot v of record
-// R holds (tap, channel c, part lo) when xslot returns true.
-__device__ __forceinline__ bool xslot(int R, int v, int& tap, int& c, int& lo) {
-  if (R >= 15) return false;
-  const int r = R % 5;
+// V(P)[4..5] aside.  The 15 records of the three kernel rows (and one
+// repeated record, zero weights) are dealt so that each lane group reads
+// two records a fixed distance apart, one 16-byte pair load per k-step:
+// k-step 0 the horizontal neighbours rho 0 | 1 of rows -1, 0, +1 and rho
+// 3 | 4 of row -1 (8 bytes apart), k-step 1 the vertical neighbours rho 2
+// of rows -1 | 0 and 0 | +1, rho 3 and rho 4 of rows 0 | +1 (one canvas
+// row apart).  kXRec[q][g] is (row + 1) * 5 + rho of the first record of
+// lane group g in k-step q.
+constexpr int kXRec[2][4] = {{0, 5, 10, 3}, {2, 7, 8, 9}};
+__device__ __forceinline__ int xrec_first(int q, int g) { return kXRec[q][g]; }
+// Record (row, rho) of slot r (0, 1) of lane group g in k-step q, and
+// whether it repeats another slot's record (zero weights).
+__device__ __forceinline__ int xrec_of(int q, int g, int r, bool& dup) {
+  const int f = kXRec[q][g];
+  dup = q == 1 && g == 1 && r == 0;                  // row 0, rho 2 again
+  return q == 0 ? f + r : f + 5 * r;
+}
+// Slot v of record (row, rho) holds (tap, channel c, part lo) when xslot
+// returns true.
+__device__ __forceinline__ bool xslot(int rec, int v, int& tap, int& c, int& lo) {
+  const int r = rec % 5;
   int dx, i;
   if (r == 0) { dx = -1; i = v; }
   else if (r == 1) { dx = v < 2 ? -1 : 0; i = v < 2 ? 4 + v : v - 2; }
   else if (r == 2) { dx = 0; i = 2 + v; }
   else if (r == 3) { if (v < 2) return false; dx = 1; i = v - 2; }
   else { dx = 1; i = 2 + v; }
-  tap = 3 * (R / 5) + dx + 1;
+  tap = 3 * (rec / 5) + dx + 1;
   c = i % 3;
   lo = i / 3;
   return true;
 }
-// Byte offset of record R from the 24P of its block pixel (row stride cwt).
-__device__ __forceinline__ int xrec_off(int R, int cwt) {
+// Byte offset of record (row, rho) from the 24P of its block pixel (row
+// stride cwt), and the distance of the second record of a k-step's pair.
+__device__ __forceinline__ int xrec_off(int rec, int cwt) {
   constexpr int kOff[5] = {-24, -16, -8, 8, 16};
-  return R >= 15 ? 0 : 24 * cwt * (R / 5 - 1) + kOff[R % 5];
+  return 24 * cwt * (rec / 5 - 1) + kOff[rec % 5];
 }
+constexpr int xpair_dist(int q, int cwt) { return q == 0 ? 8 : 24 * cwt; }
 
 // Power-of-two exponent s that brings the largest weight magnitude of a
 // layer (bits of |w|max) into [2^14, 2^15): the scaled weights use the fp16
@@ -414,7 +431,9 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
         for (int h = 0; h < 2; ++h) {
           const int slot = 2 * e2 + h;
           int tap = 0, c = 0, lo = 0;
-          const bool real = xslot(8 * q + 2 * g + (slot >> 2), slot & 3, tap, c, lo) && co < c1;
+          bool dup = false;
+          const int rec = xrec_of(q, g, slot >> 2, dup);
+          const bool real = !dup && xslot(rec, slot & 3, tap, c, lo) && co < c1;
           const float wp = real ? wpart16(wget(na, 0, co, c, tap), sc, p) : 0.f;
           ww[h] = lo ? (float)(_Float16)(wp * 0x1p-11f) : wp;
         }
@@ -1069,12 +1088,12 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     }
   };
 
-  // split nets: byte offset (from 24 P of a block pixel P) of record r of
-  // k-step q for this lane's group, k = 2q + r
-  int ro[C::XSPLIT ? 4 : 1];
+  // split nets: byte offset (from 24 P of a block pixel P) of the first
+  // record of k-step q's pair for this lane's group
+  int ro[C::XSPLIT ? 2 : 1];
   if constexpr (C::XSPLIT) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) ro[k] = xrec_off(8 * (k >> 1) + 2 * g + (k & 1), C::CWT);
+    for (int q = 0; q < 2; ++q) ro[q] = xrec_off(xrec_first(q, g), C::CWT);
   }
   // per-lane x-plane offsets of the layer-1 k-steps (FP32: K = 4q + g)
   int o1[C::BF16 || C::XSPLIT ? 1 : C::KS1];
@@ -1195,8 +1214,9 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         auto ldb = [&](int i, int sl) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            const uint2 lo = *reinterpret_cast<const uint2*>(xr + e1[i] * 24 + ro[2 * q]);
-            const uint2 hi = *reinterpret_cast<const uint2*>(xr + e1[i] * 24 + ro[2 * q + 1]);
+            const char* const b = xr + e1[i] * 24 + ro[q];
+            const uint2 lo = *reinterpret_cast<const uint2*>(b);
+            const uint2 hi = *reinterpret_cast<const uint2*>(b + xpair_dist(q, C::CWT));
             bq[sl][q] = u4{lo.x, lo.y, hi.x, hi.y};
           }
         };
