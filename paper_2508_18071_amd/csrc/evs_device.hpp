@@ -75,17 +75,32 @@ __device__ inline float spike_of(float h, float theta, float alpha, int relaxed)
 
 // Surrogate derivative of the spike (Eq. 4):
 // psi(h) = step'(h - theta) + step'(-h - theta), kind 0 sigmoid, 1 arctangent.
-// Only gradients use it, so its reciprocals are the hardware's (within 1 ulp)
-// rather than correctly rounded: two per neuron and frame, in kernels where
+// Only gradients use it, so its exponential and reciprocals are the
+// hardware's (within 1 ulp) rather than correctly rounded, in kernels where
 // the vector ALU is shared with the matrix pipe.
+//
+// Sigmoid: the slope alpha sig(alpha z)(1 - sig(alpha z)) equals
+// alpha e / (1 + e)^2 with e = exp(-alpha z), and psi is even in h.  With
+// u = |h|, a = exp(alpha (theta - u)) and b = exp(-alpha (u + theta)) =
+// a exp(-2 alpha theta), psi = alpha (a / (1+a)^2 + b / (1+b)^2): one
+// exponential, and one reciprocal r of (1+a)(1+b), which gives
+// 1/(1+a) = (1+b) r and 1/(1+b) = (1+a) r.  Since u >= 0, a <= exp(alpha
+// theta) and b <= 1; the exponent is capped at 2^64 (it binds only where
+// alpha (theta - u) > 44, where psi < alpha 2^-63), so (1+a)(1+b) stays
+// finite for any theta and alpha.
 __device__ inline float surrogate(float h, float theta, float alpha, int kind) {
   if (kind == 1) {
     const float qa = 1.57079633f * alpha * (h - theta), qb = 1.57079633f * alpha * (-h - theta);
     return 0.5f * alpha * (__builtin_amdgcn_rcpf(fmaf(qa, qa, 1.0f)) + __builtin_amdgcn_rcpf(fmaf(qb, qb, 1.0f)));
   }
-  const float a = __builtin_amdgcn_rcpf(1.0f + __expf(-alpha * (h - theta)));
-  const float b = __builtin_amdgcn_rcpf(1.0f + __expf(-alpha * (-h - theta)));
-  return alpha * (a * (1.0f - a) + b * (1.0f - b));
+  const float l2e = 1.44269504f;                       // log2(e)
+  const float z = fminf(fmaf(__builtin_fabsf(h), -alpha * l2e, alpha * theta * l2e), 64.0f);
+  const float a = __builtin_amdgcn_exp2f(z);
+  const float b = a * __builtin_amdgcn_exp2f(-2.0f * alpha * theta * l2e);
+  const float p = 1.0f + a, q = 1.0f + b;
+  const float r = __builtin_amdgcn_rcpf(p * q);
+  const float ip = q * r, iq = p * r;
+  return alpha * fmaf(a * ip, ip, (b * iq) * iq);
 }
 
 }  // namespace evs
