@@ -5,10 +5,11 @@
 // With d_t = S_t - E_t, D_i = sum_{t<=i} d_t (prefix) and the suffix sums
 // R_m = D_{T-1} - D_{m-1}, the loss of a sequence is (1/2T) sum_i |D_i| + |R_i|
 // and its gradient is (1/2T) [ sum_{i>=j} sgn D_i + sum_{m<=j} sgn R_m ].
-// Three streaming passes over time (total, loss + suffix signs, gradient)
-// keep the per-thread state O(1) for any T; reads are coalesced across the
-// pixel dimension.  Per-thread losses are summed in a fixed order (block
-// tree, then one block over the partials), so the loss is reproducible.
+// Two streaming passes over time (totals and the sum of sgn D, then loss
+// and gradient together) keep the per-thread state O(1) for any T; reads
+// are coalesced across the pixel dimension.  Per-thread losses are summed
+// in a fixed order (block tree, then one block over the partials), so the
+// loss is reproducible.
 #include <mutex>
 
 #include "evs_ops.hpp"
@@ -39,52 +40,42 @@ __global__ __launch_bounds__(kThreads) void k_emd(const float* __restrict__ s, c
     const size_t sfr = (size_t)C * HW, efr = (size_t)2 * HW;
     const size_t sbase = (size_t)n * T * sfr + px, ebase = (size_t)n * T * efr + px;
     const float inv2t = 0.5f / (float)T;
-    // pass 1: totals per polarity and spike/target counts
+    // pass 1: totals per polarity, spike/target counts, and the sum of sgn D
+    // over all frames (tot runs through the prefix sums D on the way)
     float tot[2] = {0.f, 0.f};
+    float sumsgnD[2] = {0.f, 0.f};
     float cnt_s = 0.f, cnt_e = 0.f;
     for (int t = 0; t < T; ++t) {
       for (int k = 0; k < 2; ++k) {
         const float sv = s_pol(s, sbase + t * sfr, C, k, HW);
         const float ev = (float)e[ebase + t * efr + k * HW];
         tot[k] += sv - ev;
+        sumsgnD[k] += sgnf(tot[k]);
         cnt_s += fabsf(sv);
         cnt_e += ev;
       }
     }
     const float cdiff = cnt_s - cnt_e;
-    // pass 2: loss and the total of sgn D (the gradient's reverse sums start there)
-    float D[2] = {0.f, 0.f};
-    float sumsgnD[2] = {0.f, 0.f};
+    // pass 2: loss (suffix sums R = total - prefix before the frame) and the
+    // gradient, whose reverse sums of sgn D start at the total
+    const float lam_sg = lambda * sgnf(cdiff);
+    float Dp[2] = {0.f, 0.f};
+    float revD[2] = {sumsgnD[0], sumsgnD[1]};     // sum_{i>=t} sgn D_i
+    float fwdR[2] = {0.f, 0.f};                   // sum_{m<=t} sgn R_m
     double l = 0.0;
     for (int t = 0; t < T; ++t) {
+      float g[2];
       for (int k = 0; k < 2; ++k) {
         const float sv = s_pol(s, sbase + t * sfr, C, k, HW);
         const float ev = (float)e[ebase + t * efr + k * HW];
-        const float R = tot[k] - D[k];            // suffix sum from t
-        D[k] += sv - ev;
-        l += (double)fabsf(D[k]) + (double)fabsf(R);
-        sumsgnD[k] += sgnf(D[k]);
+        const float R = tot[k] - Dp[k];           // suffix sum from t
+        Dp[k] += sv - ev;
+        l += (double)fabsf(Dp[k]) + (double)fabsf(R);
+        fwdR[k] += sgnf(R);
+        g[k] = (revD[k] + fwdR[k]) * inv2t + lam_sg * sgnf(sv);
+        revD[k] -= sgnf(Dp[k]);
       }
-    }
-    loss = l * (double)inv2t + (double)lambda * (double)fabsf(cdiff);
-    // pass 3: gradient
-    if (grad) {
-      const float lam_sg = lambda * sgnf(cdiff);
-      float Dp[2] = {0.f, 0.f};
-      float revD[2] = {sumsgnD[0], sumsgnD[1]};   // sum_{i>=t} sgn D_i
-      float fwdR[2] = {0.f, 0.f};                 // sum_{m<=t} sgn R_m
-      for (int t = 0; t < T; ++t) {
-        float g[2];
-        float sv[2];
-        for (int k = 0; k < 2; ++k) {
-          sv[k] = s_pol(s, sbase + t * sfr, C, k, HW);
-          const float ev = (float)e[ebase + t * efr + k * HW];
-          const float R = tot[k] - Dp[k];
-          fwdR[k] += sgnf(R);
-          g[k] = (revD[k] + fwdR[k]) * inv2t + lam_sg * sgnf(sv[k]);
-          Dp[k] += sv[k] - ev;
-          revD[k] -= sgnf(Dp[k]);
-        }
+      if (grad) {
         if (C == 2) {
           grad[sbase + t * sfr] = g[0];
           grad[sbase + t * sfr + HW] = g[1];
@@ -95,6 +86,7 @@ __global__ __launch_bounds__(kThreads) void k_emd(const float* __restrict__ s, c
         }
       }
     }
+    loss = l * (double)inv2t + (double)lambda * (double)fabsf(cdiff);
   }
   // fixed-order block reduction
   __shared__ double red[kThreads];

@@ -1214,7 +1214,9 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
         auto ldb = [&](int i, int sl) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            const char* const b = xr + e1[i] * 24 + ro[q];
+            // 24-bit multiply (canvas pixel indices are small): one
+            // full-rate multiply-add instead of a quarter-rate 32-bit multiply
+            const char* const b = xr + (__umul24((unsigned)e1[i], 24u) + ro[q]);
             const uint2 lo = *reinterpret_cast<const uint2*>(b);
             const uint2 hi = *reinterpret_cast<const uint2*>(b + xpair_dist(q, C::CWT));
             bq[sl][q] = u4{lo.x, lo.y, hi.x, hi.y};
