@@ -297,7 +297,21 @@ __device__ inline float bf16_part(float v, int p) {
   return p == 1 ? m : r - m;
 }
 
-template <int COUTP, bool B16>
+//
+// DW1 (16-wide layer above, the layer below fed by the clip input x): the
+// kernel also forms the input layer's weight gradient dW1[co][ci][tap] =
+// sum_p g_h1[co][p] x[ci][p + tap] from the g_h1 it has just computed, so
+// g_h1 is not written out unless the input gradient needs it (out
+// non-null).  Per frame each wave puts its 64 pixels' g_h1 ([pixel][co],
+// the A layout of v_mfma_f32_16x16x4_f32: rows co, K = 4 pixels) and its
+// own 6 x 18 window of x (B: columns (ci, tap)) into LDS regions only it
+// reads, over the g_h tile (after a barrier: the tile is consumed), and
+// issues 16 k-steps x 2 column tiles of FP32 MFMAs (products of the g_h1
+// values as stored and of x, bf16-rounded for BF16 nets).  Per-wave sums
+// stay in registers for the segment and are added in wave order at the end.
+// The backward uses it for FP32 nets; BF16 nets keep their separate bf16
+// input-layer kernel (faster than FP32 MFMAs at three waves per SIMD).
+template <int COUTP, bool B16, bool DW1 = false>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(B16 && COUTP == 16 ? 4 : 3)))
 void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int Cin, int len, int H,
                                                     int W, int tiles_x, const float* __restrict__ wT,
@@ -305,7 +319,8 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
                                                     const typename Store<B16>::H* __restrict__ hseg, HTrace ht,
                                                     int sumc, int choff, float* __restrict__ gv, float theta,
                                                     float leak, float alpha, int surr, int detach, int relaxed,
-                                                    float* __restrict__ dw_partial) {
+                                                    float* __restrict__ dw_partial, const float* __restrict__ x1,
+                                                    long long x1_ns, int cin0, float* __restrict__ dw1_partial) {
   using HS = typename Store<B16>::H;
   using GS = typename Store<B16>::G;
   constexpr unsigned ESH = sizeof(HS), ESG = sizeof(GS);
@@ -320,7 +335,13 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   constexpr int KSB = 5;                               // k-steps (bf16 product)
   static_assert(COG % 4 == 0, "co slots come in lane groups of 4");
   static_assert(E * E > NTH && E * E <= 2 * NTH, "a tile plane is staged in two passes");
-  __shared__ __attribute__((aligned(16))) float ghs[kBF ? 2 * PSB / 4 : (kF3 ? 6 * PSB / 4 : COUTP * PS)];
+  static_assert(!DW1 || COUTP == 16, "the fused input-layer gradient sits below a 16-wide layer");
+  constexpr int kGhsF = kBF ? 2 * PSB / 4 : (kF3 ? 6 * PSB / 4 : COUTP * PS);
+  // DW1 regions over the tile: per wave g_h1 [64 pixels][16 co], then per
+  // wave x [3 ci][6 rows][18 columns]; the end-of-segment wave sums reuse it
+  constexpr int XWP = 6 * (TT + 2);                    // x window plane (floats)
+  constexpr int kG1F = 4 * 64 * 16, kDw1F = kG1F + 4 * 3 * XWP;
+  __shared__ __attribute__((aligned(16))) float ghs[DW1 && kDw1F > kGhsF ? kDw1F : kGhsF];
   __shared__ unsigned gp2[kBF2 ? E * E : 1];           // [pixel] (co 0, co 1) bf16 pairs
   const int tile = xcd_remap(blockIdx.x, gridDim.x), n = blockIdx.y;
   const int ty0 = (tile / tiles_x) * TT, tx0 = (tile % tiles_x) * TT;
@@ -461,6 +482,40 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) g_v[r][i] = y0 + r < H ? ld_el<float>(rv, voff[i], r * W * 4) : 0.f;
+  // DW1: entries e = lane, lane + 64 of the wave's x window (rows y0 - 1 ..
+  // y0 + 4, columns tx0 - 1 .. tx0 + 16); outside the image: the dead offset
+  // (reads 0, the conv's zero padding).  Column tile nt of the B operand:
+  // column idx = 16 nt + j is (ci, tap) = (idx / 9, idx % 9).
+  unsigned xoff1[2] = {kDeadOff, kDeadOff};
+  float xv1[3][2];
+  int xb1[2] = {0, 0};
+  bool xc1[2] = {false, false};
+  f4 dacc1[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+  if constexpr (DW1) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = lane + 64 * k;
+      const int yy = y0 - 1 + e / (TT + 2), xx = tx0 - 1 + e % (TT + 2);
+      xoff1[k] = el_off<float>(e < XWP && yy >= 0 && yy < H && xx >= 0 && xx < W, (unsigned)(yy * W + xx));
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int idx = 16 * nt + j, ci = idx / 9, tap = idx % 9;
+      xc1[nt] = ci < cin0;
+      // pixel (row R, column C) of the wave's block reads window row R + 1 + dy,
+      // column C + 1 + dx; this lane's pixel of k-step kk is (kk / 4, 4 (kk % 4) + g)
+      xb1[nt] = kG1F + wave * 3 * XWP + (xc1[nt] ? ci : 0) * XWP + (tap / 3) * (TT + 2) + (tap % 3) + g;
+    }
+  }
+  auto load_x1 = [&](int t) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(x1 + (size_t)n * x1_ns + (size_t)t * cin0 * HW), (short)0,
+        (int)((unsigned)cin0 * (unsigned)HW * 4u), 0x00020000);
+#pragma unroll
+    for (int ci = 0; ci < 3; ++ci)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) xv1[ci][k] = ci < cin0 ? ld_el<float>(rx, xoff1[k] + 4u * ci * HW, 0) : 0.f;
+  };
   // a frame's loads: its haloed g_h tile (every load issued before the first
   // LDS store; planes past Cout fall outside the resource and read 0) and the
   // h of this lane's neurons.  Narrow layers above (memory-bound: the scan
@@ -544,6 +599,7 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
   for (int t = len - 1; t >= 0; --t) {
     __syncthreads();                                   // the previous frame's tile is consumed
     if constexpr (!kAhead) load_tile(t);
+    if constexpr (DW1) load_x1(t);
     stage_entry(st0, threadIdx.x);
     if (threadIdx.x < E * E - NTH) stage_entry(st1, threadIdx.x + NTH);
     __syncthreads();
@@ -630,18 +686,55 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
         }
       }
     }
-    const __amdgpu_buffer_rsrc_t ro =
-        __builtin_amdgcn_make_buffer_rsrc(out + ((size_t)n * len + t) * Cin * HW, (short)0, (int)(nel * ESG), 0x00020000);
+    // (DW1 without the input gradient: no g_h1 output, a resource of size 0)
+    const bool wout = !DW1 || out != nullptr;
+    const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+        wout ? out + ((size_t)n * len + t) * Cin * HW : out, (short)0, wout ? (int)(nel * ESG) : 0, 0x00020000);
+    float g1[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) g1[r][i] = 0.f;
       if (y0 + r < H) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const float Gv = acc[r][i];
           const float psi = surrogate(hv[r][i], theta, alpha, surr);
           const float gn = detach ? fmaf(Gv, psi, g_v[r][i]) : fmaf(fmaf(-theta, g_v[r][i], Gv), psi, g_v[r][i]);
-          st_el<GS>(gn, ro, voffG[i], r * W * ESG);
+          if (wout) st_el<GS>(gn, ro, voffG[i], r * W * ESG);
           g_v[r][i] = leak * gn;
+          // the value stored (bf16 for BF16 nets); 0 off the image and past Cin
+          if constexpr (DW1) g1[r][i] = x < W && 4 * g + i < Cin ? to_f32(from_f32<GS>(gn)) : 0.f;
+        }
+      }
+    }
+    if constexpr (DW1) {
+      __syncthreads();                                 // every wave is done with the g_h tile
+      float* const g1w = ghs + wave * 64 * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        *reinterpret_cast<f4*>(g1w + (16 * r + j) * 16 + 4 * g) = f4{g1[r][0], g1[r][1], g1[r][2], g1[r][3]};
+      float* const xw = ghs + kG1F + wave * 3 * XWP;
+#pragma unroll
+      for (int ci = 0; ci < 3; ++ci)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int e = lane + 64 * k;
+          if (ci < cin0 && e < XWP) xw[ci * XWP + e] = B16 ? round_bf16(xv1[ci][k]) : xv1[ci][k];
+        }
+      // the regions are this wave's own: its LDS operations run in order
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const float av = g1w[(4 * kk + g) * 16 + j];
+        const int imm = (kk / 4) * (TT + 2) + 4 * (kk % 4);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          if (nt == 0 || cin0 > 1) {
+            const float bv = xc1[nt] ? ghs[xb1[nt] + imm] : 0.f;
+            dacc1[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, dacc1[nt], 0, 0, 0);
+          }
         }
       }
     }
@@ -691,6 +784,36 @@ void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int C
 #pragma unroll
             for (int w2 = 0; w2 < 3; ++w2) v += red[(w2 * 64 + lane) * 8 + 4 * nt + i];
             o[(co * 16 + 4 * g + i) * 9 + tap] += v;     // [co][ci][tap], as the VALU kernel
+          }
+        }
+      }
+    }
+  }
+  if constexpr (DW1) {
+    // lane (column j, group g) holds dW1 for co 4g..4g+3 of column 16 nt + j;
+    // the four waves' sums are added in wave order
+    __syncthreads();
+    float* red = ghs;                                  // [wave - 1][lane][8]
+    if (wave > 0) {
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[((wave - 1) * 64 + lane) * 8 + 4 * nt + i] = dacc1[nt][i];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // [co][ci (4 slots)][tap], the layout of the separate input-layer kernels
+      float* o = dw1_partial + ((size_t)blockIdx.y * gridDim.x + tile) * (16 * 4 * 9);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const int idx = 16 * nt + j, ci = idx / 9, tap = idx % 9;
+        if (xc1[nt]) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float v = dacc1[nt][i];
+#pragma unroll
+            for (int w2 = 0; w2 < 3; ++w2) v += red[(w2 * 64 + lane) * 8 + 4 * nt + i];
+            o[((4 * g + i) * 4 + ci) * 9 + tap] += v;
           }
         }
       }
@@ -1161,6 +1284,9 @@ struct ConvTArgs {
   void* out; long long ons, ots;
   const void* hseg; HTrace ht; int sumc, choff; float* gv; float theta, leak, alpha; int surr, detach;
   int relaxed; float* dw_partial;     // the fused weight gradient of narrow layers
+  // the fused input-layer weight gradient (16-wide layer above the input
+  // layer): x of the segment, its clip stride, Cin of x, the partial sums
+  const float* x1; long long x1_ns; int cin0; float* dw1;
 };
 template <int CINP, int COUTP, bool B16>
 void launch_convT(dim3 g, hipStream_t st, bool adj, const ConvTArgs& a) {
@@ -1172,9 +1298,18 @@ void launch_convT(dim3 g, hipStream_t st, bool adj, const ConvTArgs& a) {
   // hidden layers below a 16-wide layer or the output layer
   if constexpr (CINP == 16 && COUTP <= 16) {
     if (adj) {
+      if constexpr (COUTP == 16 && !B16) {
+        if (a.dw1) {
+          hipLaunchKernelGGL((k_convT_mfma<16, B16, true>), g, dim3(NTH), 0, st, gh, a.Cout, a.Cin, a.len, a.H, a.W,
+                             a.tiles_x, a.wT, static_cast<GS*>(a.out), hseg, a.ht, a.sumc, a.choff, a.gv, a.theta,
+                             a.leak, a.alpha, a.surr, a.detach, a.relaxed, a.dw_partial, a.x1, a.x1_ns, a.cin0, a.dw1);
+          return;
+        }
+      }
       hipLaunchKernelGGL((k_convT_mfma<COUTP, B16>), g, dim3(NTH), 0, st, gh, a.Cout, a.Cin, a.len, a.H, a.W,
                          a.tiles_x, a.wT, static_cast<GS*>(a.out), hseg, a.ht, a.sumc, a.choff, a.gv, a.theta, a.leak,
-                         a.alpha, a.surr, a.detach, a.relaxed, a.dw_partial);
+                         a.alpha, a.surr, a.detach, a.relaxed, a.dw_partial, static_cast<const float*>(nullptr), 0LL,
+                         0, static_cast<float*>(nullptr));
       return;
     }
   } else {
@@ -1387,6 +1522,7 @@ int run_backward(const evs_net& net, const void* packed, const evs_clip& clip, c
       EVS_HIP(hipGetLastError());
     }
     int cur = 0;
+    bool dw1_done = false;
     for (int l = L; l >= 1; --l) {
       const int C = net.ch[l], Cin = net.ch[l - 1];
       GS* gh = ghb[cur];
@@ -1395,7 +1531,12 @@ int run_backward(const evs_net& net, const void* packed, const evs_clip& clip, c
       // fixed-order reduction; then the g_h of the layer below (the
       // conv-transpose and that layer's adjoint scan), or grad_x
       const int CI = pad_in(Cin), CO = pad_out(C);
-      const bool fused_dw = l >= 2 && CI == 16 && CO <= 4;
+      const bool fused_dw = (l >= 2 && CI == 16 && CO <= 4) || (l == 1 && dw1_done);
+      // FP32 nets: a 16-wide layer 2 over the input layer forms the input
+      // layer's weight gradient inside its conv-transpose (BF16 nets keep
+      // their separate bf16 kernel, faster than FP32 MFMAs at the fused
+      // kernel's lower occupancy)
+      const bool fuse_dw1 = !B16 && l == 2 && CI == 16 && CO == 16 && pad_in(net.ch[0]) == 4;
       const dim3 gdw((unsigned)(Lo.tiles_x * Lo.tiles_y), (unsigned)N);
       if (!fused_dw) {
         const HS* hin = l >= 2 ? hseg : nullptr;
@@ -1420,6 +1561,14 @@ int run_backward(const evs_net& net, const void* packed, const evs_clip& clip, c
         if (l >= 2) {
           a.out = ghb[cur ^ 1];
           a.hseg = hseg; a.ht = ht[l - 2]; a.choff = choff[l - 2]; a.gv = gv;
+          if (fuse_dw1) {
+            a.x1 = clip.x + (size_t)t0 * cin0 * HW;
+            a.x1_ns = (long long)T * cin0 * HW;
+            a.cin0 = cin0;
+            a.dw1 = partial;                           // layer 1's slots: accofs[0] = 0
+            if (!grad_x) a.out = nullptr;              // g_h1 only feeds the input gradient
+            dw1_done = true;
+          }
         } else {
           a.out = grad_x + (size_t)t0 * cin0 * HW;
           a.ons = (long long)T * cin0 * HW;
