@@ -157,6 +157,27 @@ def test_checkpoint_interval_and_determinism(evs):
         assert _rel(res[k][1].cpu().numpy(), res[4][1].cpu().numpy()) < 1e-5
 
 
+@pytest.mark.parametrize("channels,prec", [((3, 16, 16, 2), "fp32"), ((1, 12, 16, 2), "fp32"),
+                                           ((3, 16, 16, 2), "bf16")])
+def test_weight_gradients_do_not_depend_on_the_input_gradient(evs, channels, prec):
+    """Without the input gradient the backward skips writing layer 1's
+    adjoints (FP32 nets form the input layer's dW inside the layer-2
+    conv-transpose): the weight gradients and the initial-state gradient
+    equal, bit for bit, those of a call that also forms grad_x."""
+    T, H, W, k = 10, 37, 29, 4
+    x, ws, net, packed = _setup(evs, channels, prec, T, H, W, N=2, seed=8)
+    xg = x.cuda()
+    G = torch.from_numpy(np.random.default_rng(6).normal(size=(2, T, 2, H, W)).astype(np.float32)).cuda()
+    out = evs.forward(net, packed, xg, ckpt_every=k)
+    a = evs.backward(net, packed, xg, out["ckpt"], k, G, want_dx=True, want_dv=True)
+    b = evs.backward(net, packed, xg, out["ckpt"], k, G, want_dv=True)
+    torch.cuda.synchronize()
+    assert b[1] is None
+    for ga, gb in zip(a[0], b[0]):
+        assert torch.equal(ga, gb)
+    assert torch.equal(a[2], b[2])
+
+
 @pytest.mark.parametrize("surr", ["sigmoid", "atan"])
 def test_relaxed_backward_matches_oracle_and_finite_differences(evs, surr):
     """8x8x4 crop (8x8 pixels, 4 frames): GPU BPTT of the smooth forward

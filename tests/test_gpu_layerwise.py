@@ -108,6 +108,7 @@ def test_layerwise_state_carry_checkpoints_and_trace_window(evs, channels, prec)
 
 
 @pytest.mark.parametrize("channels,prec", [((3, 8, 16, 2), "fp32"), ((3, 8, 8, 8, 8, 2), "fp32"),
+                                           ((1, 12, 16, 2), "fp32"),    # one input channel, fused input-layer dW
                                            ((3, 16, 32, 2), "bf16"), ((3, 5, 12, 7, 1), "bf16")])
 @pytest.mark.parametrize("k", [4, 100])
 def test_layerwise_backward_matches_oracle(evs, channels, prec, k):
