@@ -312,7 +312,7 @@ __device__ inline float bf16_part(float v, int p) {
 // The backward uses it for FP32 nets; BF16 nets keep their separate bf16
 // input-layer kernel (faster than FP32 MFMAs at three waves per SIMD).
 template <int COUTP, bool B16, bool DW1 = false>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(B16 && COUTP == 16 ? 4 : 3)))
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(B16 && !DW1 ? 4 : 3)))
 void k_convT_mfma(const typename Store<B16>::G* __restrict__ gh, int Cout, int Cin, int len, int H,
                                                     int W, int tiles_x, const float* __restrict__ wT,
                                                     typename Store<B16>::G* __restrict__ out,
