@@ -695,7 +695,8 @@ template <class C, bool TOY = false>
 __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int sp_off, int p, bool valid, int g,
                                                 float theta, float alpha, int relaxed, const TraceFrame& tr, float tscale,
                                                 int cl, int choff, int gy0, int gx0, const TraceBox& tb,
-                                                const u4 (*ay)[C::KY] = nullptr, int yq = 0, int li = 0) {
+                                                const u4 (*ay)[C::KY] = nullptr, int yq = 0, int li = 0,
+                                                unsigned rec_base = 0u) {
   f4 hsave[C::REC ? C::MB : 1];
   if constexpr (C::REC) {
 #pragma unroll
@@ -745,7 +746,8 @@ __device__ __forceinline__ void hidden_epilogue(f4 (&st)[C::MB], char* lds, int 
       if constexpr (C::REC) {
         // the lane's channels 16m + 4g .. +3 of the pixel (the layer's
         // padding channels hold 0 and are stored too)
-        const unsigned e = rec_pix<C>(p, valid && 16 * m + 4 * g < tr.cw[li], gy0, gx0, tb.h, tb.w, tr.cw[li]);
+        // rec_base: rec_pix of the block pixel, formed once per tile
+        const unsigned e = 16 * m + 4 * g < tr.cw[li] ? rec_base : 0x20000000u;
         rec_store4<C>(tr, li, e + 16 * m + 4 * g, hsave[m], sw[m]);
       }
       // channels 16m + 4g .. +3: plane 2m + g/2, half (g & 1) of the pixel's 16 bytes
@@ -910,6 +912,19 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     vmo |= (ok ? 1u : 0u) << i;
     const int row = (ao[i] - C::PADF) / C::CWT, col = (ao[i] - C::PADF) % C::CWT;
     oo[i] = (ok && g < cout) ? g * (int)HW + (gy0 + row) * W + (gx0 + col) : -1;
+  }
+  // recompute builds: trace element offsets of the block pixels (rec_pix),
+  // frame-invariant, formed once here (the frame loop hides the block
+  // pixels from the optimiser, so they would be formed again every frame)
+  unsigned re1[C::NB1] = {}, re2[C::NB2] = {}, reo[C::NBO] = {};
+  if constexpr (C::REC) {
+    const int cpw1 = (c1 + 3) & ~3, cpw2 = (c2 + 3) & ~3;
+#pragma unroll
+    for (int i = 0; i < C::NB1; ++i) re1[i] = rec_pix<C>(a1[i], (vm1 >> i) & 1u, gy0, gx0, ca.tb_h, ca.tb_w, cpw1);
+#pragma unroll
+    for (int i = 0; i < C::NB2; ++i) re2[i] = rec_pix<C>(a2[i], (vm2 >> i) & 1u, gy0, gx0, ca.tb_h, ca.tb_w, cpw2);
+#pragma unroll
+    for (int i = 0; i < C::NBO; ++i) reo[i] = rec_pix<C>(ao[i], oo[i] >= 0, gy0, gx0, H, W, 4) + g;
   }
   // ---- output pixels of this lane (VALU output layer)
   int op[C::NOUT];
@@ -1164,6 +1179,16 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
     for (int i = 0; i < C::NB2; ++i) asm volatile("" : "+v"(a2[i]));
 #pragma unroll
     for (int i = 0; i < C::NBO; ++i) asm volatile("" : "+v"(ao[i]));
+    if constexpr (C::REC) {
+      // (the trace offsets too: only they stay in registers, not values
+      // derived from them)
+#pragma unroll
+      for (int i = 0; i < C::NB1; ++i) asm volatile("" : "+v"(re1[i]));
+#pragma unroll
+      for (int i = 0; i < C::NB2; ++i) asm volatile("" : "+v"(re2[i]));
+#pragma unroll
+      for (int i = 0; i < C::NBO; ++i) asm volatile("" : "+v"(reo[i]));
+    }
     const int (&e1)[C::NB1] = a1;
     const int (&e2)[C::NB2] = a2;
     const int (&eo)[C::NBO] = ao;
@@ -1239,7 +1264,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           }
           if (i > 0)
             hidden_epilogue<C, Y1>(st1[i - 1], lds, 0, e1[i - 1], (vm1 >> (i - 1)) & 1u, g, theta1, alpha, relaxed,
-                                   trace_t, isc1, c1, 0, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)));
+                                   trace_t, isc1, c1, 0, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)), 0,
+                                   re1[i - 1]);
         }
       } else if constexpr (!C::BF16) {
         // f32 MFMA; the operands of k-step q+1 load while those of q multiply
@@ -1300,7 +1326,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
         for (int i = 0; i < C::NB1; ++i)
           hidden_epilogue<C, Y1>(st1[i], lds, 0, e1[i], (vm1 >> i) & 1u, g, theta1, alpha, relaxed, trace_t, isc1, c1,
-                                 0, gy0, gx0, tb, ay, yidx(wave + C::NW * i));
+                                 0, gy0, gx0, tb, ay, yidx(wave + C::NW * i), 0, re1[i]);
       }
       lds_barrier();                                   // B1: s1 visible, x buffer (t & 1) free
       if constexpr (C::XDMA) {
@@ -1357,7 +1383,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           if (i > 0)
             hidden_epilogue<C, Y2>(st2[i - 1], lds, C::S2OFF, e2[i - 1], (vm2 >> (i - 1)) & 1u, g, theta2, alpha,
                                    relaxed, trace_t, isc2, c2, choff2, gy0, gx0, tb, ay, yidx(wave + C::NW * (i - 1)),
-                                   1);
+                                   1, re2[i - 1]);
         }
         if constexpr (STAGE_IN_L2) {
 #pragma unroll
@@ -1422,7 +1448,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
         for (int i = 0; i < C::NB2; ++i)
           hidden_epilogue<C>(st2[i], lds, C::S2OFF, e2[i], (vm2 >> i) & 1u, g, theta2, alpha, relaxed, trace_t, isc2,
-                             c2, choff2, gy0, gx0, tb, nullptr, 0, 1);
+                             c2, choff2, gy0, gx0, tb, nullptr, 0, 1, re2[i]);
       }
       if constexpr (C::XDMA) {
         if (t + 2 < T) issue_x(t + 2, t & 1);
@@ -1455,7 +1481,7 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
           float v = h;
           const float sp = bilif(v, theta3, alpha, false);
           if constexpr (C::REC)
-            rec_store1<C>(trace_t, rec_pix<C>(ao[i], oo[i] >= 0, gy0, gx0, H, W, 4) + g, h * isc3, sp);
+            rec_store1<C>(trace_t, reo[i], h * isc3, sp);
           asm volatile("" : "+v"(v));
           vo[i] = v;
           if (oo[i] >= 0 && ca.s_out) {
