@@ -118,6 +118,10 @@ struct Cfg {
   static constexpr bool OTAP = S16 && (NH == 1 || (NH == 2 && CH == 16));
   static constexpr bool OMF = S16 && NH >= 1 && !OTAP;   // output layer on MFMA, rows (channel, part)
   static constexpr int KB = CH == 32 ? 9 : 5;        // spike-operand k-steps (32 of K = 9*CH each)
+  // FP32 16-wide layer 2: the last k-step holds tap 8 only (lane groups
+  // 0-1), so its two weight parts share one MFMA: groups 2-3, which read
+  // tap 8's spikes too, carry its low part (9 MFMAs per block, not 10)
+  static constexpr bool M2 = SF16 && CH == 16 && NH >= 2;
   static constexpr int NBO = OMF ? cdiv(nblk(NL), NW) : 1;
   // tail lanes of a layer's last block read around and write to this
   // canvas pixel, which lies past the canvas and is read by no real pixel
@@ -476,13 +480,17 @@ __device__ __forceinline__ void load_weights(const FwdNetArgs& na, char* lds) {
         const int co = 16 * m + (lane & 15), g = lane >> 4;
         int tau, cib;
         kslot<C::CH>(kb, g, tau, cib);
+        // merged last k-step (M2): part 0 of it holds tap 8's low part in
+        // the slots of tap 9; its part 1 is never multiplied
+        const bool merged = C::M2 && kb == C::KB - 1 && tau == 9;
+        const int tw = merged ? 8 : tau, pw = merged ? p + 1 : p;
         unsigned wd[4];
         for (int e2 = 0; e2 < 4; ++e2) {
           float ww[2];
           for (int h = 0; h < 2; ++h) {
             const int ci = cib + 2 * e2 + h;
-            const bool real = tau < 9 && co < c2 && ci < c1;
-            if constexpr (C::SF16) ww[h] = real ? wpart16(wget(na, 1, co, ci, tau), sc, p) : 0.f;
+            const bool real = tw < 9 && pw < C::NSP && co < c2 && ci < c1;
+            if constexpr (C::SF16) ww[h] = real ? wpart16(wget(na, 1, co, ci, tw), sc, pw) : 0.f;
             else ww[h] = real ? wbf(na, 1, co, ci, tau, C::BF16, p) : 0.f;
           }
           wd[e2] = C::SF16 ? pack_f16x2(ww[0], ww[1]) : pack_bf16x2(ww[0], ww[1]);
@@ -1377,7 +1385,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
             for (int kb = 0; kb < C::KB; ++kb)
 #pragma unroll
-              for (int p = 0; p < C::NSP; ++p) st2[i][0] = mfma_sp<C>(aw[kb][p], bq[i & 1][kb], st2[i][0]);
+              for (int p = 0; p < C::NSP; ++p)
+                if (!(C::M2 && kb == C::KB - 1 && p > 0)) st2[i][0] = mfma_sp<C>(aw[kb][p], bq[i & 1][kb], st2[i][0]);
           }
           if (STAGE_IN_L2 && i < C::XPP && t + 1 < T) store_group(i);
           if (i > 0)
@@ -1416,7 +1425,8 @@ __device__ __forceinline__ void run_tile(const FwdNetArgs& na, const FwdClipArgs
 #pragma unroll
             for (int m = 0; m < C::MB; ++m)
 #pragma unroll
-              for (int i = 0; i < C::NB2; ++i) st2[i][m] = mfma_sp<C>(aq[kb & 1][p][m], bq[kb & 1][i], st2[i][m]);
+              for (int i = 0; i < C::NB2; ++i)
+                if (!(C::M2 && kb == C::KB - 1 && p > 0)) st2[i][m] = mfma_sp<C>(aq[kb & 1][p][m], bq[kb & 1][i], st2[i][m]);
         }
       } else {
         const float* spf = reinterpret_cast<const float*>(sp1);
