@@ -53,6 +53,7 @@ def _setup(evs, channels, prec, T, H, W, N=1, seed=0, scale=1.0, relaxed=False, 
                                                        ((3, 16, 16, 2), "fp32", True, "sigmoid"),
                                                        ((3, 16, 16, 2), "fp32", False, "atan"),
                                                        ((3, 32, 2), "bf16", False, "sigmoid"),
+                                                       ((3, 32, 2), "fp32", False, "sigmoid"),
                                                        ((3, 16, 16, 2), "bf16", False, "sigmoid"),
                                                        # widths that are not multiples of 4; two
                                                        # 32-wide hidden layers
