@@ -297,7 +297,6 @@ __device__ inline float bf16_part(float v, int p) {
   return p == 1 ? m : r - m;
 }
 
-//
 // DW1 (16-wide layer above, the layer below fed by the clip input x): the
 // kernel also forms the input layer's weight gradient dW1[co][ci][tap] =
 // sum_p g_h1[co][p] x[ci][p + tap] from the g_h1 it has just computed, so
