@@ -541,7 +541,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the EvSNet forward shards over clips and spatial "
-              "bands without communication, and this build runs on a single MI355X; "
+              "bands without communication, and the benchmark runs on one MI355X; "
               "use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
