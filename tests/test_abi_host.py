@@ -242,7 +242,7 @@ def _gpu_present():
         return False
 
 
-@pytest.mark.skipif(_gpu_present(), reason="checks the behaviour without a GPU; on a GPU box the call would "
+@pytest.mark.skipif(_gpu_present(), reason="checks the behaviour without a GPU; on a machine with a GPU the call would "
                                            "really run with the placeholder pointers")
 def test_no_gpu_reports_hip_error_with_message(evs):
     """Without a GPU, a call with valid arguments gets past validation and
