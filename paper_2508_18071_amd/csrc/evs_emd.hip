@@ -45,6 +45,10 @@ __global__ __launch_bounds__(kThreads) void k_emd(const float* __restrict__ s, c
     float tot[2] = {0.f, 0.f};
     float sumsgnD[2] = {0.f, 0.f};
     float cnt_s = 0.f, cnt_e = 0.f;
+    // unrolled so that several frames' loads are in flight at once (one
+    // thread per pixel: few waves per SIMD, so each thread's loads must
+    // overlap; the sums keep their order)
+#pragma unroll 8
     for (int t = 0; t < T; ++t) {
       for (int k = 0; k < 2; ++k) {
         const float sv = s_pol(s, sbase + t * sfr, C, k, HW);
@@ -63,6 +67,7 @@ __global__ __launch_bounds__(kThreads) void k_emd(const float* __restrict__ s, c
     float revD[2] = {sumsgnD[0], sumsgnD[1]};     // sum_{i>=t} sgn D_i
     float fwdR[2] = {0.f, 0.f};                   // sum_{m<=t} sgn R_m
     double l = 0.0;
+#pragma unroll 8
     for (int t = 0; t < T; ++t) {
       float g[2];
       for (int k = 0; k < 2; ++k) {
